@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the semiring sparse product on one MI355X.
+
+Default workload: R-MAT scale 20 (2^20 vertices, 16 edge draws per vertex,
+quadrant probabilities (0.57, 0.19, 0.19, 0.05), duplicates removed), float32
+weights uniform in [1, 100), C = A.A over the (min,+) semiring.  One step is
+the whole two-pass product through the C ABI: row analysis, binning,
+symbolic pass (with its one host read-back of nnz(C)), and numeric pass into
+a pre-reserved output buffer.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: semiring products per second (value), the HBM GB/s of
+the algorithmic byte model, the roofline of the dominant kernel (timed live
+with HIP events on the library's stream) and the CPU oracle's throughput on a
+bounded sample of the same rows.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "semiring products/s + HBM GB/s, R-MAT s20 A·A; batched vs per-call"
+PEAK_HBM_GBPS = 8000.0
+
+WORKLOADS = {
+    # name: (generator, semiring, value kind, lo, hi, description)
+    "rmat20_minplus": ("rmat", 20, 5, "f32u", 1.0, 100.0,
+                       "R-MAT scale 20, edge factor 16, (a,b,c,d)=(0.57,0.19,0.19,0.05), dedup, fp32 weights "
+                       "U[1,100), (min,+) C=A.A"),
+    "rmat18_bool": ("rmat", 18, 4, "ones", 0, 0,
+                    "R-MAT scale 18, edge factor 16, (or,and) C=A.A, all-true values"),
+    "rmat18_i64": ("rmat", 18, 1, "i64u", 1, 9, "R-MAT scale 18, edge factor 16, (+,x) int64 C=A.A, values U{1..9}"),
+    "rmat20_f32": ("rmat", 20, 2, "f32n", 0, 1,
+                   "R-MAT scale 20, edge factor 16, (+,x) fp32 values N(0,1), compensated accumulation, C=A.A"),
+    "er4096_f64": ("er", 4096, 3, "f64u", 0, 1, "Erdos-Renyi n=4096, 8 per row, (+,x) fp64 U[0,1), C=A.B"),
+}
+VAL_BYTES = {1: 8, 2: 4, 3: 8, 4: 1, 5: 4}
+DTYPE = {1: "int64", 2: "f32", 3: "f64", 4: "u8", 5: "f32"}
+
+
+def make_inputs(name):
+    import synth
+    kind, size, sr, vk, lo, hi, desc = WORKLOADS[name]
+    vmap = {"f32u": synth.VAL_F32_UNIFORM, "ones": synth.VAL_ONES, "i64u": synth.VAL_I64_UNIFORM,
+            "f32n": synth.VAL_F32_NORMAL, "f64u": synth.VAL_F64_UNIFORM}
+    if kind == "rmat":
+        A = synth.rmat(size, 16, seed=1)
+        A = A.with_values(synth.values(vmap[vk], A.nnz, lo, hi, 2))
+        B = A
+    else:
+        A = synth.er(size, size, 8, 1).with_values(synth.values(vmap[vk], size * 8, lo, hi, 11))
+        B = synth.er(size, size, 8, 2).with_values(synth.values(vmap[vk], size * 8, lo, hi, 12))
+    return A, B, sr, desc
+
+
+def products_per_row(A, B):
+    lens = np.diff(B.rowptr)[A.col]
+    p = np.zeros(A.nrows, dtype=np.int64)
+    np.add.at(p, np.repeat(np.arange(A.nrows), np.diff(A.rowptr)), lens)
+    return p
+
+
+def cpu_baseline(A, B, sr, p, target_s):
+    """The oracle, as it is, on a growing uniform sample of rows until one
+    run takes about target_s seconds on all host threads."""
+    import oracle
+    import synth
+    orc = oracle.get()
+    rng_rows = synth.select(A.nrows, min(A.nrows, 1 << 20), 3)  # a fixed random order of rows
+    order = np.argsort(synth.values(synth.VAL_F64_UNIFORM, len(rng_rows), 0, 1, 4))
+    rows_all = rng_rows[order]
+    k = 256
+    while True:
+        rows = np.sort(rows_all[:k])
+        t0 = time.perf_counter()
+        orc.spgemm(sr, A, B, rows=rows)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or k >= len(rows_all):
+            break
+        k = min(len(rows_all), int(k * max(2.0, min(8.0, 0.9 * target_s / max(dt, 1e-3)))))
+    prods = int(p[rows].sum())
+    return {"value": prods / dt, "unit": "semiring products/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{k} rows drawn uniformly (seed 3) of the same product, {prods} products, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20_minplus", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hash-max", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the product is the per-GPU local multiply and this build has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2504_06408_amd as sg
+
+    t_gen = time.perf_counter()
+    A, B, sr_id, desc = make_inputs(args.workload)
+    p = products_per_row(A, B)
+    P = int(p.sum())
+    print(f"# inputs ready in {time.perf_counter() - t_gen:.1f}s: n={A.nrows} nnz(A)={A.nnz} products={P}",
+          file=sys.stderr, flush=True)
+
+    dev = "cuda:0"
+    dA = sg.DeviceCSR.from_host(A, dev)
+    dB = dA if B is A else sg.DeviceCSR.from_host(B, dev)
+    h = sg.Handle(0)
+    h.set_option("timing", 1)
+    if args.hash_max is not None:
+        h.set_option("hash_max_products", args.hash_max)
+    sr = sg.semiring(sr_id)
+    vb = VAL_BYTES[sr_id]
+
+    # pre-reserved output: sized by one symbolic pass before timing
+    rowptr, nnzC = h.symbolic(dA, dB)
+    col = torch.empty(nnzC, dtype=torch.int32, device=dev)
+    val = torch.empty(nnzC, dtype={1: torch.int64, 2: torch.float32, 3: torch.float64, 4: torch.uint8,
+                                   5: torch.float32}[sr_id], device=dev)
+
+    def step():
+        rp, nz = h.symbolic(dA, dB)
+        C = sg.DeviceCSR(A.nrows, B.ncols, rp, col[:nz], val[:nz])
+        h.numeric(sr, dA, dB, C)
+        return C, nz
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.check()
+
+    phase_runs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C, nz = step()
+        phase_runs.append(h.timings())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.check()
+    assert nz == nnzC
+    ms = (t1 - t0) * 1e3 / args.steps
+    print(f"# {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    n, nnzA, nnzB = A.nrows, A.nnz, B.nnz
+    b_sym = 8 * (n + 1) + 4 * nnzA + 8 * (B.nrows + 1) + 4 * nnzB + 8 * (n + 1)
+    b_num = 8 * (n + 1) + (4 + vb) * nnzA + 8 * (B.nrows + 1) + (4 + vb) * nnzB + 8 * (n + 1) + (4 + vb) * nnzC
+    b_alg = b_sym + b_num
+
+    phases = {k: float(np.mean([r[k] for r in phase_runs])) for k in phase_runs[0]}
+    dom = max(phases, key=phases.get)
+    # algorithmic bytes of the dominant kernel: the per-output-entry figure
+    # (4 + value bytes) times the entries it writes, plus one read of the A
+    # rows it handles and one read of B (col + value), plus row offsets
+    rp_host = C.rowptr.cpu().numpy()
+    m_row = np.diff(rp_host)
+    hm = 4096 if args.hash_max is None else args.hash_max
+    dense = p > hm
+    small = p <= 64
+    hashr = (~dense) & (~small) & (p > 0)
+    sel = {"num_dense": dense, "num_hash": hashr, "num_small": small & (p > 0),
+           "sym_dense": dense, "sym_hash": hashr, "sym_small": small & (p > 0)}.get(dom)
+    if sel is not None:
+        a_rows = np.diff(A.rowptr)[sel].sum()
+        if dom.startswith("num"):
+            kb = (4 + vb) * int(m_row[sel].sum()) + (4 + vb) * int(a_rows) + (4 + vb) * nnzB + 16 * int(sel.sum())
+        else:
+            kb = 4 * int(a_rows) + 4 * nnzB + 16 * int(sel.sum()) + 8 * int(sel.sum())
+    else:
+        kb = b_alg
+    achieved = kb / (phases[dom] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_launch": int(kb),
+            "ms_per_launch": round(phases[dom], 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": P / (ms * 1e-3),
+        "unit": "semiring products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": DTYPE[sr_id],
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "semiring": sg.SEMIRING_NAMES[sr_id], "n": int(A.nrows),
+                   "nnz_A": int(nnzA), "products": P, "nnz_C": int(nnzC), "path": "per-call symbolic+numeric"},
+        "hbm_gbps_model": round(b_alg / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac_model": round(b_alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+        "bytes_alg": int(b_alg),
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, B, sr_id, p, args.cpu_seconds)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * spgemm.h -- semiring sparse x sparse product C = A (x).(+) B and the
+ * semiring merge of partial products on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Section 2.2 "Semiring Abstraction"): for a semiring
+ * (S, (+), (x), 0, 1) with commutative, associative (+) and associative (x),
+ *     C_ij = (+)_{k : A_ik and B_kj stored} A_ik (x) B_kj .
+ * C's pattern is structural: (i, j) is stored iff at least one product
+ * reaches it, even when the folded value equals the semiring zero.  This is
+ * the local multiply that every stage of the paper's distributed Sparse SUMMA
+ * runs (Section 2.1; Section 4.3 "GALATIC SpGEMM"), and the merge is the
+ * combination of those stage outputs into one matrix (Section 2.1, last
+ * paragraph; Section 4.4 "Merging Operation"), done here on the GPU.
+ *
+ * Conventions shared by every call
+ *  - Matrices are CSR.  rowptr: int64[nrows+1], rowptr[0] = 0; col: int32[nnz];
+ *    val: nnz values of the semiring's value type (int64, float, double,
+ *    uint8 0/1, float).  All matrix arrays are DEVICE pointers.  Columns in a
+ *    row must be strictly ascending (unique, sorted); with the environment
+ *    variable SG_VALIDATE=1 every call checks this and returns
+ *    SG_ERR_UNSORTED otherwise.  nrows = 0 and nnz = 0 are legal.
+ *  - Ownership: the caller allocates and frees every matrix array.  The
+ *    library never frees caller memory.  A handle owns its scratch memory
+ *    (grown on demand, freed by sg_handle_destroy); a plan owns its pool.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is
+ *    queued on it; only the *_symbolic calls and sg_batch_plan wait for it.
+ *  - Errors: every call returns an sg_status and never aborts or throws.
+ *    sg_last_error() gives a message.  An asynchronous device fault surfaces
+ *    as SG_ERR_HIP on a later call.  On failure no output array holds a
+ *    partial result that the caller may rely on.
+ *  - A and B may alias (A.A).  C must not alias A or B.
+ *  - One handle serves one host thread at a time.
+ */
+#ifndef SG_SPGEMM_H
+#define SG_SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SG_OK = 0,
+  SG_ERR_INVALID = -1,  /* null pointer, negative size, bad option */
+  SG_ERR_SHAPE = -2,    /* A.ncols != B.nrows, or parts of unequal shape */
+  SG_ERR_SEMIRING = -3, /* unknown semiring id or accumulation flag */
+  SG_ERR_NOMEM = -4,    /* device allocation failed or pool too small */
+  SG_ERR_OVERFLOW = -5, /* a size exceeds the index types (ncols > 2^31-1) */
+  SG_ERR_UNSORTED = -6, /* validation found an unsorted or duplicate column */
+  SG_ERR_HIP = -7       /* a HIP runtime call or a kernel failed */
+} sg_status;
+
+/* The five semirings (paper, Section 2.2; Section 5.1 uses (+,x) on floats
+ * and (min,+)).
+ *  SG_PLUS_TIMES_I64 : int64, (+) and (x) wrap modulo 2^64, 0 = 0, 1 = 1
+ *  SG_PLUS_TIMES_F32 : float, IEEE binary32 (x) and (+); see acc_flags
+ *  SG_PLUS_TIMES_F64 : double, IEEE binary64
+ *  SG_OR_AND_BOOL    : uint8 (nonzero = true), (+) = or, (x) = and; C holds 0/1
+ *  SG_MIN_PLUS_F32   : float, (x) = binary32 addition, (+) = minimum,
+ *                      0 = +inf, 1 = +0.0.  Inputs must not be NaN and no
+ *                      product may be +inf + -inf.                         */
+typedef enum {
+  SG_PLUS_TIMES_I64 = 1,
+  SG_PLUS_TIMES_F32 = 2,
+  SG_PLUS_TIMES_F64 = 3,
+  SG_OR_AND_BOOL = 4,
+  SG_MIN_PLUS_F32 = 5
+} sg_semiring_id;
+
+/* Accumulation of SG_PLUS_TIMES_F32 sums (ignored by the other semirings).
+ *  SG_ACC_DEFAULT     : compensated (two-sum plus exact product error, kept
+ *                       as a float pair per accumulator slot) for rows with
+ *                       more than comp_min_terms stored entries in A's row
+ *                       and more than comp_min_products products; plain
+ *                       binary32 otherwise.
+ *  SG_ACC_COMPENSATED : compensated for every row that is not a small row
+ *                       (at most 64 products).
+ *  SG_ACC_PLAIN       : plain binary32 everywhere.                          */
+enum { SG_ACC_DEFAULT = 0, SG_ACC_COMPENSATED = 1, SG_ACC_PLAIN = 2 };
+
+typedef struct {
+  int32_t id;                /* sg_semiring_id */
+  int32_t value_bytes;       /* size of one value: 8, 4, 8, 1, 4 */
+  uint32_t acc_flags;        /* SG_ACC_* */
+  int32_t comp_min_terms;    /* default 64 */
+  int64_t comp_min_products; /* default 0 */
+} sg_semiring;
+
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  int64_t* rowptr; /* device, nrows+1 */
+  int32_t* col;    /* device, nnz */
+  void* val;       /* device, nnz values */
+} sg_csr;
+
+typedef struct sg_handle sg_handle;
+typedef struct sg_plan sg_plan;
+
+/* Fill *out (host memory) with the descriptor of semiring `id`.
+ * Returns SG_ERR_SEMIRING for an unknown id or flag, SG_ERR_INVALID for
+ * out == NULL. */
+sg_status sg_semiring_make(sg_semiring_id id, uint32_t acc_flags, sg_semiring* out);
+
+/* Create a handle bound to HIP device `device` (made current by every call
+ * that uses the handle).  tuning_json: path to a tuning table written by
+ * sg_tune, or NULL for the built-in defaults (the environment variable
+ * SG_TUNING names a table when tuning_json is NULL).  *out receives the
+ * handle. */
+sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out);
+sg_status sg_handle_destroy(sg_handle* h);
+
+/* Set a tuning option by name (host strings): "hash_max_products" (rows with
+ * more products take the column-tiled dense path; <= 4096), "force_path"
+ * ("auto", "small", "hash", "dense": route every row that the path can take
+ * through it), "validate" (0/1), "timing" (0/1: record per-phase HIP events,
+ * see sg_handle_timings).  Returns SG_ERR_INVALID for an unknown name or a
+ * bad value. */
+sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value);
+
+/* Pass 1 of C = A (x).(+) B (structure only; independent of the semiring).
+ * Writes C_rowptr[0..A.nrows] (device, int64, caller-allocated) and stores
+ * nnz(C) in *nnzC (host).  Waits for `stream`.  A.val and B.val are not
+ * read.  The row analysis is kept in the handle for the next
+ * sg_spgemm_numeric on the same A and B. */
+sg_status sg_spgemm_symbolic(sg_handle* h, const sg_csr* A, const sg_csr* B, int64_t* C_rowptr, int64_t* nnzC,
+                             void* stream);
+
+/* Pass 2: fills C->col and C->val (device, caller-allocated with nnz(C)
+ * entries) given C->rowptr from pass 1 on the same A and B.  Rows of C come
+ * out sorted by column.  Does not wait for `stream`.  C->nrows must equal
+ * A.nrows, C->ncols B.ncols, C->nnz the value pass 1 returned. */
+sg_status sg_spgemm_numeric(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, sg_csr* C,
+                            void* stream);
+
+/* Merge (paper, Section 4.4): C = parts[0] (+) ... (+) parts[nparts-1],
+ * entry by entry, pattern = union.  parts is a host array of nparts
+ * descriptors (device arrays) of one shape.  Same two-pass convention as the
+ * product: merge_symbolic writes C_rowptr and *nnzC (host) and waits for the
+ * stream; merge_numeric fills C->col, C->val.  1 <= nparts <= 4096. */
+sg_status sg_spgemm_merge_symbolic(sg_handle* h, int nparts, const sg_csr* parts, int64_t* C_rowptr,
+                                   int64_t* nnzC, void* stream);
+sg_status sg_spgemm_merge_numeric(sg_handle* h, const sg_semiring* sr, int nparts, const sg_csr* parts, sg_csr* C,
+                                  void* stream);
+
+/* Batched path (the many block products of a 2D Sparse SUMMA, Section 2.1,
+ * plus batches of small products): nprob products C_q = A[q] (x).(+) B[q]
+ * (host arrays of descriptors) and ngroups merges, group g combining the
+ * products group_offsets[g] .. group_offsets[g+1]-1 (host int32 array of
+ * ngroups+1 ascending entries; ngroups = 0 means no merges).  The plan sizes
+ * and owns a device pool (pool_bytes = 0: sized exactly from a symbolic
+ * pass at plan time; otherwise that many bytes) and records one graph of
+ * persistent kernels over a global work queue; sg_batch_plan waits for its
+ * own work.  sg_batch_execute replays the graph on `stream` with no host
+ * round trip; it recomputes every product and merge from the current values
+ * (the patterns of A[q], B[q] must not change after planning).
+ * sg_batch_results fills out_C (host array) with views into the pool: nprob
+ * product results followed by ngroups merge results; they stay valid until
+ * the plan is destroyed or executed again.  A pool overflow on execute sets
+ * SG_ERR_NOMEM on the next sg_batch_results. */
+sg_status sg_batch_plan(sg_handle* h, const sg_semiring* sr, int nprob, const sg_csr* A, const sg_csr* B,
+                        int ngroups, const int32_t* group_offsets, size_t pool_bytes, sg_plan** out);
+sg_status sg_batch_execute(sg_plan* plan, void* stream);
+sg_status sg_batch_results(sg_plan* plan, sg_csr* out_C);
+sg_status sg_plan_destroy(sg_plan* plan);
+
+/* Autotuner: times the candidate path thresholds on C = A (x).(+) B with
+ * semiring sr and writes the best as a tuning table (JSON) to out_json
+ * (host path).  The handle adopts the result.  Waits for its own work. */
+sg_status sg_tune(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, const char* out_json);
+
+/* Phases timed when the handle option "timing" is "1" (a pair of HIP events
+ * is recorded on the call's stream around each phase). */
+enum {
+  SG_PHASE_SYM_ANALYZE = 0, /* row analysis + binning of the symbolic pass */
+  SG_PHASE_SYM_BOUNDS = 1,  /* per-B-row column-tile offsets */
+  SG_PHASE_SYM_SMALL = 2,   /* wavefront rows */
+  SG_PHASE_SYM_HASH = 3,    /* LDS hash rows */
+  SG_PHASE_SYM_DENSE = 4,   /* bitmap rows (one kernel) */
+  SG_PHASE_SYM_SCAN = 5,    /* prefix sum into C.rowptr */
+  SG_PHASE_NUM_ANALYZE = 6, /* row analysis + binning of the numeric pass */
+  SG_PHASE_NUM_SMALL = 7,
+  SG_PHASE_NUM_HASH = 8,
+  SG_PHASE_NUM_DENSE = 9,   /* dense-tile rows (one kernel) */
+  SG_NPHASES = 10
+};
+
+/* Device milliseconds of each phase of the most recent symbolic and numeric
+ * calls (product or merge) on this handle: ms[0..n) receives
+ * min(n, SG_NPHASES) values; a phase that did not run reports 0.  Waits for
+ * the recorded events.  Requires the "timing" option. */
+sg_status sg_handle_timings(sg_handle* h, double* ms, int n);
+
+/* Wait for all work of the handle's device, then report any device-side
+ * consistency error (a numeric pass that filled a different number of
+ * entries than its symbolic pass counted) as SG_ERR_INVALID. */
+sg_status sg_handle_check(sg_handle* h);
+
+const char* sg_status_string(sg_status s);
+const char* sg_last_error(const sg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_SPGEMM_H */

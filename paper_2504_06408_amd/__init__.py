@@ -1,0 +1,338 @@
+"""Semiring sparse x sparse product C = A (x).(+) B and the semiring merge of
+partial products on an AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libsgspgemm.so`` (C ABI in ``include/spgemm.h``):
+it only marshals arguments.  Device memory comes from PyTorch (ROCm build);
+every step of the computation runs in the library's HIP kernels.  Importing
+this package does not need a GPU; creating a :class:`Handle` does, and any
+call raises :class:`SgError` when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgspgemm.so")
+
+# semiring ids (include/spgemm.h)
+PLUS_TIMES_I64, PLUS_TIMES_F32, PLUS_TIMES_F64, OR_AND_BOOL, MIN_PLUS_F32 = 1, 2, 3, 4, 5
+SEMIRING_NAMES = {1: "plus_times_i64", 2: "plus_times_f32", 3: "plus_times_f64", 4: "or_and_bool",
+                  5: "min_plus_f32"}
+ACC_DEFAULT, ACC_COMPENSATED, ACC_PLAIN = 0, 1, 2
+NP_DTYPE = {1: np.int64, 2: np.float32, 3: np.float64, 4: np.uint8, 5: np.float32}
+
+STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID", -2: "SG_ERR_SHAPE", -3: "SG_ERR_SEMIRING", -4: "SG_ERR_NOMEM",
+          -5: "SG_ERR_OVERFLOW", -6: "SG_ERR_UNSORTED", -7: "SG_ERR_HIP"}
+
+# every function include/spgemm.h declares
+EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_handle_set_option",
+           "sg_spgemm_symbolic", "sg_spgemm_numeric", "sg_spgemm_merge_symbolic", "sg_spgemm_merge_numeric",
+           "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune",
+           "sg_handle_check", "sg_handle_timings", "sg_status_string", "sg_last_error")
+
+PHASES = ("sym_analyze", "sym_bounds", "sym_small", "sym_hash", "sym_dense", "sym_scan", "num_analyze", "num_small",
+          "num_hash", "num_dense")
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sg_semiring(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int32), ("value_bytes", ctypes.c_int32), ("acc_flags", ctypes.c_uint32),
+                ("comp_min_terms", ctypes.c_int32), ("comp_min_products", ctypes.c_int64)]
+
+
+class sg_csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises SgError if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SgError(-7, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, ci = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+        SR, CSR = ctypes.POINTER(sg_semiring), ctypes.POINTER(sg_csr)
+        sig = {
+            "sg_semiring_make": ([ci, ctypes.c_uint32, SR], ci),
+            "sg_handle_create": ([ci, ctypes.c_char_p, ctypes.POINTER(P)], ci),
+            "sg_handle_destroy": ([P], ci),
+            "sg_handle_set_option": ([P, ctypes.c_char_p, ctypes.c_char_p], ci),
+            "sg_spgemm_symbolic": ([P, CSR, CSR, P, ctypes.POINTER(i64), P], ci),
+            "sg_spgemm_numeric": ([P, SR, CSR, CSR, CSR, P], ci),
+            "sg_spgemm_merge_symbolic": ([P, ci, CSR, P, ctypes.POINTER(i64), P], ci),
+            "sg_spgemm_merge_numeric": ([P, SR, ci, CSR, CSR, P], ci),
+            "sg_batch_plan": ([P, SR, ci, CSR, CSR, ci, ctypes.POINTER(i32), ctypes.c_size_t, ctypes.POINTER(P)], ci),
+            "sg_batch_execute": ([P, P], ci),
+            "sg_batch_results": ([P, CSR], ci),
+            "sg_plan_destroy": ([P], ci),
+            "sg_tune": ([P, SR, CSR, CSR, ctypes.c_char_p], ci),
+            "sg_handle_check": ([P], ci),
+            "sg_handle_timings": ([P, ctypes.POINTER(ctypes.c_double), ci], ci),
+            "sg_status_string": ([ci], ctypes.c_char_p),
+            "sg_last_error": ([P], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def semiring(sid: int, acc: int = ACC_DEFAULT, comp_min_terms: int = 64, comp_min_products: int = 0) -> sg_semiring:
+    s = sg_semiring()
+    rc = lib().sg_semiring_make(sid, acc, ctypes.byref(s))
+    if rc != 0:
+        raise SgError(rc, f"bad semiring {sid} / accumulation {acc}")
+    s.comp_min_terms = comp_min_terms
+    s.comp_min_products = comp_min_products
+    return s
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class DeviceCSR:
+    """CSR matrix in device memory (torch tensors): rowptr int64[nrows+1],
+    col int32[nnz], val[nnz] of the semiring's value type."""
+
+    def __init__(self, nrows: int, ncols: int, rowptr, col, val=None):
+        self.nrows, self.ncols = int(nrows), int(ncols)
+        self.rowptr, self.col, self.val = rowptr, col, val
+        self.nnz = int(col.numel())
+
+    @classmethod
+    def from_numpy(cls, nrows, ncols, rowptr, col, val=None, device="cuda"):
+        torch = _torch()
+        rp = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int64)).to(device)
+        cl = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
+        vl = None if val is None else torch.from_numpy(np.ascontiguousarray(val)).to(device)
+        return cls(nrows, ncols, rp, cl, vl)
+
+    @classmethod
+    def from_host(cls, M, device="cuda"):
+        """From any object with nrows, ncols, rowptr, col, val (numpy)."""
+        return cls.from_numpy(M.nrows, M.ncols, M.rowptr, M.col, M.val, device)
+
+    def desc(self) -> sg_csr:
+        d = sg_csr()
+        d.nrows, d.ncols, d.nnz = self.nrows, self.ncols, self.nnz
+        d.rowptr = self.rowptr.data_ptr()
+        d.col = self.col.data_ptr() if self.nnz else 0
+        d.val = self.val.data_ptr() if (self.val is not None and self.nnz) else 0
+        return d
+
+    def to_numpy(self):
+        rp = self.rowptr.cpu().numpy()
+        cl = self.col.cpu().numpy()
+        vl = None if self.val is None else self.val.cpu().numpy()
+        return rp, cl, vl
+
+
+def _torch_dtype(sid: int):
+    torch = _torch()
+    return {1: torch.int64, 2: torch.float32, 3: torch.float64, 4: torch.uint8, 5: torch.float32}[sid]
+
+
+class Plan:
+    """A recorded batched execution (sg_batch_plan)."""
+
+    def __init__(self, handle: "Handle", ptr, nprob: int, ngroups: int, keep):
+        self.handle, self.ptr, self.nprob, self.ngroups, self._keep = handle, ptr, nprob, ngroups, keep
+
+    def execute(self, stream=None):
+        self.handle._rc(lib().sg_batch_execute(self.ptr, _stream_ptr(stream)))
+
+    def results(self) -> List[sg_csr]:
+        n = self.nprob + self.ngroups
+        arr = (sg_csr * n)()
+        self.handle._rc(lib().sg_batch_results(self.ptr, arr))
+        return list(arr)
+
+    def destroy(self):
+        if self.ptr:
+            lib().sg_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Handle:
+    def __init__(self, device: int = 0, tuning: Optional[str] = None):
+        p = ctypes.c_void_p()
+        rc = lib().sg_handle_create(device, tuning.encode() if tuning else None, ctypes.byref(p))
+        if rc != 0:
+            raise SgError(rc, "sg_handle_create failed")
+        self.ptr = p
+        self.device = device
+
+    def close(self):
+        if self.ptr:
+            lib().sg_handle_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc: int):
+        if rc != 0:
+            msg = lib().sg_last_error(self.ptr)
+            raise SgError(rc, msg.decode() if msg else "")
+
+    def set_option(self, name: str, value) -> None:
+        self._rc(lib().sg_handle_set_option(self.ptr, name.encode(), str(value).encode()))
+
+    def check(self) -> None:
+        self._rc(lib().sg_handle_check(self.ptr))
+
+    def timings(self) -> dict:
+        """Per-phase device milliseconds of the last symbolic and numeric
+        calls (needs set_option("timing", 1))."""
+        arr = (ctypes.c_double * len(PHASES))()
+        self._rc(lib().sg_handle_timings(self.ptr, arr, len(PHASES)))
+        return dict(zip(PHASES, list(arr)))
+
+    # ---- product -------------------------------------------------------------
+    def symbolic(self, A: DeviceCSR, B: DeviceCSR, stream=None):
+        torch = _torch()
+        rowptr = torch.empty(A.nrows + 1, dtype=torch.int64, device=A.rowptr.device)
+        nnz = ctypes.c_int64()
+        a, b = A.desc(), B.desc()
+        self._rc(lib().sg_spgemm_symbolic(self.ptr, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.c_void_p(rowptr.data_ptr()), ctypes.byref(nnz), _stream_ptr(stream)))
+        return rowptr, int(nnz.value)
+
+    def numeric(self, sr: sg_semiring, A: DeviceCSR, B: DeviceCSR, C: DeviceCSR, stream=None) -> None:
+        a, b, c = A.desc(), B.desc(), C.desc()
+        self._rc(lib().sg_spgemm_numeric(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b),
+                                         ctypes.byref(c), _stream_ptr(stream)))
+
+    def spgemm(self, sr, A: DeviceCSR, B: DeviceCSR, stream=None) -> DeviceCSR:
+        """C = A (x).(+) B (both passes); sr: semiring id or descriptor."""
+        torch = _torch()
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        rowptr, nnz = self.symbolic(A, B, stream)
+        dev = A.rowptr.device
+        C = DeviceCSR(A.nrows, B.ncols, rowptr, torch.empty(nnz, dtype=torch.int32, device=dev),
+                      torch.empty(nnz, dtype=_torch_dtype(sr.id), device=dev))
+        self.numeric(sr, A, B, C, stream)
+        return C
+
+    # ---- merge ----------------------------------------------------------------
+    def merge_symbolic(self, parts: Sequence[DeviceCSR], stream=None):
+        torch = _torch()
+        arr = (sg_csr * len(parts))(*[p.desc() for p in parts])
+        rowptr = torch.empty(parts[0].nrows + 1, dtype=torch.int64, device=parts[0].rowptr.device)
+        nnz = ctypes.c_int64()
+        self._rc(lib().sg_spgemm_merge_symbolic(self.ptr, len(parts), arr, ctypes.c_void_p(rowptr.data_ptr()),
+                                                ctypes.byref(nnz), _stream_ptr(stream)))
+        return rowptr, int(nnz.value)
+
+    def merge_numeric(self, sr: sg_semiring, parts: Sequence[DeviceCSR], C: DeviceCSR, stream=None) -> None:
+        arr = (sg_csr * len(parts))(*[p.desc() for p in parts])
+        c = C.desc()
+        self._rc(lib().sg_spgemm_merge_numeric(self.ptr, ctypes.byref(sr), len(parts), arr, ctypes.byref(c),
+                                               _stream_ptr(stream)))
+
+    def merge(self, sr, parts: Sequence[DeviceCSR], stream=None) -> DeviceCSR:
+        torch = _torch()
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        rowptr, nnz = self.merge_symbolic(parts, stream)
+        dev = parts[0].rowptr.device
+        C = DeviceCSR(parts[0].nrows, parts[0].ncols, rowptr, torch.empty(nnz, dtype=torch.int32, device=dev),
+                      torch.empty(nnz, dtype=_torch_dtype(sr.id), device=dev))
+        self.merge_numeric(sr, parts, C, stream)
+        return C
+
+    # ---- batched ----------------------------------------------------------------
+    def batch_plan(self, sr, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], group_offsets=None,
+                   pool_bytes: int = 0) -> Plan:
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        n = len(As)
+        a = (sg_csr * n)(*[x.desc() for x in As])
+        b = (sg_csr * n)(*[x.desc() for x in Bs])
+        ng = 0 if group_offsets is None else len(group_offsets) - 1
+        go = None if group_offsets is None else (ctypes.c_int32 * len(group_offsets))(*group_offsets)
+        p = ctypes.c_void_p()
+        self._rc(lib().sg_batch_plan(self.ptr, ctypes.byref(sr), n, a, b, ng, go, pool_bytes, ctypes.byref(p)))
+        return Plan(self, p, n, ng, (As, Bs, sr))
+
+    def tune(self, sr, A: DeviceCSR, B: DeviceCSR, out_json: str) -> None:
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        a, b = A.desc(), B.desc()
+        self._rc(lib().sg_tune(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b), out_json.encode()))
+
+
+def view_results(res: sg_csr, sid: int, device="cuda") -> DeviceCSR:
+    """Wrap a result descriptor returned by Plan.results() as torch tensors
+    (views of the plan's pool; valid until the plan is executed again or
+    destroyed)."""
+    torch = _torch()
+
+    def wrap(ptr, n, dtype):
+        if n == 0 or not ptr:
+            return torch.empty(0, dtype=dtype, device=device)
+        return _from_ptr(ptr, n, dtype, device)
+
+    rp = wrap(res.rowptr, res.nrows + 1, torch.int64)
+    cl = wrap(res.col, res.nnz, torch.int32)
+    vl = wrap(res.val, res.nnz, _torch_dtype(sid))
+    return DeviceCSR(res.nrows, res.ncols, rp, cl, vl)
+
+
+def _from_ptr(ptr: int, n: int, dtype, device):
+    """Copy n elements at device address ptr into a new tensor."""
+    torch = _torch()
+    out = torch.empty(n, dtype=dtype, device=device)
+    nbytes = n * out.element_size()
+    hip = _hip()
+    rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes), 3)
+    if rc != 0:
+        raise SgError(-7, f"hipMemcpy failed ({rc})")
+    return out
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip_lib.hipMemcpy.restype = ctypes.c_int
+    return _hip_lib

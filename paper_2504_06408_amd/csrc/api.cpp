@@ -1,0 +1,599 @@
+// C-ABI of the semiring sparse product and merge (declared in include/spgemm.h).
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sg_handle.hpp"
+
+using namespace sg;
+
+sg_status sg_fail(sg_handle* h, sg_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+sg_status sg_check_hip(sg_handle* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return SG_OK;
+  if (e == hipErrorOutOfMemory) return sg_fail(h, SG_ERR_NOMEM, std::string(what) + ": out of device memory");
+  return sg_fail(h, SG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SG_HIP(h, call)                                        \
+  do {                                                         \
+    const sg_status _s = sg_check_hip((h), (call), #call);     \
+    if (_s != SG_OK) return _s;                                \
+  } while (0)
+
+#define SG_TRY(expr)                \
+  do {                              \
+    const sg_status _s = (expr);    \
+    if (_s != SG_OK) return _s;     \
+  } while (0)
+
+namespace sg {
+
+int32_t tiles_of(int64_t ncols) {
+  const int64_t t = (ncols + kTile - 1) / kTile;
+  return t < 1 ? 1 : (int32_t)t;
+}
+
+Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr) {
+  Policy p{};
+  p.numeric = numeric;
+  p.force = h->force;
+  p.hash_max = h->hash_max;
+  p.comp_mode = kCompNone;
+  p.comp_min_terms = 64;
+  p.comp_min_products = 0;
+  if (sr && sr->id == SG_PLUS_TIMES_F32) {
+    p.comp_mode = sr->acc_flags == SG_ACC_PLAIN ? kCompNone
+                  : sr->acc_flags == SG_ACC_COMPENSATED ? kCompAll
+                                                        : kCompRule;
+    p.comp_min_terms = sr->comp_min_terms;
+    p.comp_min_products = sr->comp_min_products;
+  }
+  return p;
+}
+
+static void handle_mark(void* ctx, int phase, int begin) {
+  sg_handle* h = (sg_handle*)ctx;
+  (void)hipEventRecord(h->ev[phase][begin ? 0 : 1], h->mark_stream);
+  if (!begin) h->ev_rec[phase] = true;
+}
+
+Marks handle_marks(sg_handle* h, hipStream_t st) {
+  Marks m;
+  if (h->timing) {
+    m.fn = handle_mark;
+    m.ctx = h;
+    h->mark_stream = st;
+  }
+  return m;
+}
+
+void clear_phases(sg_handle* h, int p0, int p1) {
+  for (int p = p0; p < p1; ++p) h->ev_rec[p] = false;
+}
+
+size_t plan_rows_bytes(int64_t nrows) {
+  SgArena a;
+  const int64_t nblk = analyze_blocks(nrows);
+  a.take<int64_t>(nrows);
+  a.take<uint8_t>(nrows);
+  a.take<int32_t>(nblk * kNB);
+  a.take<int32_t>(nblk * kNB);
+  a.take<int32_t>(kNB);
+  a.take<int32_t>(kNB);
+  a.take<int32_t>(nrows);
+  return a.off;
+}
+
+sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* cnt_out,
+                    SgArena& ar, BinPlan& plan, hipStream_t st) {
+  const int64_t n = r.nrows;
+  const int64_t nblk = analyze_blocks(n);
+  int64_t* p = ar.take<int64_t>(n);
+  uint8_t* bin = ar.take<uint8_t>(n);
+  int32_t* hist = ar.take<int32_t>(nblk * kNB);
+  int32_t* blk_off = ar.take<int32_t>(nblk * kNB);
+  int32_t* bin_start = ar.take<int32_t>(kNB);
+  int32_t* bin_count = ar.take<int32_t>(kNB);
+  int32_t* list = ar.take<int32_t>(n);
+  launch_analyze(r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count, list, cnt_out, st);
+  int32_t* hp = (int32_t*)h->h_pin;
+  SG_HIP(h, hipMemcpyAsync(hp, bin_count, kNB * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SG_HIP(h, hipMemcpyAsync(hp + kNB, bin_start, kNB * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SG_HIP(h, hipStreamSynchronize(st));
+  std::memcpy(plan.count, hp, sizeof(plan.count));
+  std::memcpy(plan.start, hp + kNB, sizeof(plan.start));
+  plan.bins.list = list;
+  plan.bins.start = bin_start;
+  plan.bins.count = bin_count;
+  return SG_OK;
+}
+
+}  // namespace sg
+
+namespace {
+
+sg_status check_csr(sg_handle* h, const sg_csr* M, const char* name) {
+  if (!M) return sg_fail(h, SG_ERR_INVALID, std::string(name) + " is NULL");
+  if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0) return sg_fail(h, SG_ERR_INVALID, std::string(name) + ": negative size");
+  if (M->ncols > INT32_MAX || M->nrows > INT32_MAX)
+    return sg_fail(h, SG_ERR_OVERFLOW, std::string(name) + ": more than 2^31-1 rows or columns");
+  if (!M->rowptr) return sg_fail(h, SG_ERR_INVALID, std::string(name) + ".rowptr is NULL");
+  if (M->nnz > 0 && !M->col) return sg_fail(h, SG_ERR_INVALID, std::string(name) + ".col is NULL");
+  return SG_OK;
+}
+
+sg_status check_semiring(sg_handle* h, const sg_semiring* sr) {
+  if (!sr) return sg_fail(h, SG_ERR_INVALID, "semiring descriptor is NULL");
+  static const int bytes[6] = {0, 8, 4, 8, 1, 4};
+  if (sr->id < 1 || sr->id > 5) return sg_fail(h, SG_ERR_SEMIRING, "unknown semiring id");
+  if (sr->value_bytes != bytes[sr->id]) return sg_fail(h, SG_ERR_SEMIRING, "value_bytes does not match the semiring");
+  if (sr->acc_flags > SG_ACC_PLAIN) return sg_fail(h, SG_ERR_SEMIRING, "unknown accumulation flag");
+  return SG_OK;
+}
+
+sg_status validate_input(sg_handle* h, const sg_csr* M, const char* name, hipStream_t st) {
+  if (!h->validate || M->nrows == 0) return SG_OK;
+  int32_t* flag = h->d_flags + 2;
+  launch_fill_i32(flag, 1, 0, st);
+  launch_validate(M->rowptr, M->col, M->nrows, M->ncols, M->nnz, flag, st);
+  int32_t v = 0;
+  SG_HIP(h, hipMemcpyAsync(h->h_pin, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SG_HIP(h, hipStreamSynchronize(st));
+  std::memcpy(&v, h->h_pin, sizeof(v));
+  if (v) return sg_fail(h, SG_ERR_UNSORTED, std::string(name) + ": unsorted or duplicate column, or bad row offsets");
+  return SG_OK;
+}
+
+SgCacheKey product_key(const sg_handle* h, const sg_csr* A, const sg_csr* B) {
+  SgCacheKey k{};
+  k.w[0] = 1;
+  k.w[1] = (uint64_t)(uintptr_t)A->rowptr;
+  k.w[2] = (uint64_t)(uintptr_t)A->col;
+  k.w[3] = (uint64_t)A->nrows;
+  k.w[4] = (uint64_t)A->ncols;
+  k.w[5] = (uint64_t)A->nnz;
+  k.w[6] = (uint64_t)(uintptr_t)B->rowptr;
+  k.w[7] = (uint64_t)(uintptr_t)B->col;
+  k.w[8] = (uint64_t)B->nrows;
+  k.w[9] = (uint64_t)B->ncols;
+  k.w[10] = (uint64_t)B->nnz;
+  k.w[11] = (uint64_t)h->force;
+  k.w[12] = (uint64_t)h->hash_max;
+  return k;
+}
+
+SgCacheKey merge_key(const sg_handle* h, int nparts, const sg_csr* parts) {
+  SgCacheKey k{};
+  k.w[0] = 2;
+  uint64_t a = 1469598103934665603ull;
+  for (int s = 0; s < nparts; ++s) {
+    const uint64_t v[5] = {(uint64_t)(uintptr_t)parts[s].rowptr, (uint64_t)(uintptr_t)parts[s].col,
+                           (uint64_t)parts[s].nrows, (uint64_t)parts[s].ncols, (uint64_t)parts[s].nnz};
+    for (uint64_t x : v) a = (a ^ x) * 1099511628211ull;
+  }
+  k.w[1] = a;
+  k.w[2] = (uint64_t)nparts;
+  k.w[11] = (uint64_t)h->force;
+  k.w[12] = (uint64_t)h->hash_max;
+  return k;
+}
+
+sg_status upload_parts(sg_handle* h, int nparts, const sg_csr* parts, hipStream_t st) {
+  h->parts_host.resize((size_t)nparts);
+  for (int s = 0; s < nparts; ++s)
+    h->parts_host[(size_t)s] = PartDesc{parts[s].rowptr, parts[s].col, parts[s].val, parts[s].nnz};
+  SG_HIP(h, h->parts_buf.ensure(sizeof(PartDesc) * (size_t)nparts));
+  SG_HIP(h, hipMemcpyAsync(h->parts_buf.p, h->parts_host.data(), sizeof(PartDesc) * (size_t)nparts,
+                           hipMemcpyHostToDevice, st));
+  return SG_OK;
+}
+
+// Shared body of the two symbolic entry points: counts into C_rowptr[1..n],
+// dense-row tile offsets into the handle's cache, scan, readback of nnz.
+sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_rowptr, int64_t* nnzC,
+                       const SgCacheKey& key, hipStream_t st) {
+  const int64_t n = r.nrows;
+  SgArena measure;
+  measure.off = plan_rows_bytes(n);
+  measure.take<int64_t>(scan_partials_len(n));
+  SG_HIP(h, h->ws.ensure(measure.off));
+  SgArena ar;
+  ar.base = (char*)h->ws.p;
+  BinPlan plan;
+  const Policy pol = make_policy(h, 0, nullptr);
+  clear_phases(h, kPhSymAnalyze, kPhNumAnalyze);
+  const Marks mk = handle_marks(h, st);
+  mk.mark(kPhSymAnalyze, 1);
+  SG_TRY(plan_rows(h, r, pol, nullptr, C_rowptr + 1, ar, plan, st));
+  mk.mark(kPhSymAnalyze, 0);
+  const int32_t nd = plan.ndense();
+  int32_t* off2 = nullptr;
+  if (nd > 0) {
+    if (!r.merge && r.T > 1) {
+      SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
+      r.rp2 = (const int32_t*)h->rp2_buf.p;
+      mk.mark(kPhSymBounds, 1);
+      launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
+      mk.mark(kPhSymBounds, 0);
+    }
+    SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
+    off2 = (int32_t*)h->off2_buf.p;
+  }
+  launch_symbolic(r, plan, C_rowptr + 1, off2, h->cus, mk, st);
+  mk.mark(kPhSymScan, 1);
+  launch_fill_i64(C_rowptr, 1, 0, st);
+  int64_t* partial = ar.take<int64_t>(scan_partials_len(n));
+  launch_scan_inclusive(C_rowptr + 1, n, partial, st);
+  mk.mark(kPhSymScan, 0);
+  SG_HIP(h, hipGetLastError());
+  SG_HIP(h, hipMemcpyAsync(h->h_pin, C_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SG_HIP(h, hipStreamSynchronize(st));
+  *nnzC = h->h_pin[0];
+  h->cache_valid = true;
+  h->cache_key = key;
+  h->cache_T = r.T;
+  h->cache_nd = nd;
+  return SG_OK;
+}
+
+sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const sg_csr* B, sg_csr* C,
+                      const SgCacheKey& key, hipStream_t st) {
+  const int64_t n = r.nrows;
+  SgArena measure;
+  measure.off = plan_rows_bytes(n);
+  measure.take<int64_t>(n);
+  SG_HIP(h, h->ws.ensure(measure.off));
+  SgArena ar;
+  ar.base = (char*)h->ws.p;
+  BinPlan plan;
+  const Policy pol = make_policy(h, 1, sr);
+  clear_phases(h, kPhNumAnalyze, kNPhases);
+  const Marks mk = handle_marks(h, st);
+  mk.mark(kPhNumAnalyze, 1);
+  SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st));
+  mk.mark(kPhNumAnalyze, 0);
+  const int32_t nd = plan.ndense();
+  const bool cached = h->cache_valid && h->cache_key == key && h->cache_T == r.T && h->cache_nd == nd;
+  if (nd > 0) {
+    if (!r.merge && r.T > 1) {
+      if (!cached) {
+        SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
+        launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
+      }
+      r.rp2 = (const int32_t*)h->rp2_buf.p;
+    }
+    if (!cached) {
+      SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
+      int64_t* scratch = ar.take<int64_t>(n);
+      launch_symbolic_dense(r, plan, scratch, (int32_t*)h->off2_buf.p, h->cus, st);
+      h->cache_valid = false;  // off2 now belongs to this call's inputs only
+    }
+  }
+  NumCtx c{};
+  c.marks = mk;
+  c.src = r;
+  c.plan = plan;
+  c.C = OutC{C->rowptr, C->col, C->val};
+  c.off2 = (const int32_t*)h->off2_buf.p;
+  c.err = h->d_flags;
+  c.task_ctr = h->d_flags + 1;
+  c.cus = h->cus;
+  c.comp_dense = pol.comp_mode != kCompNone;
+  switch (sr->id) {
+    case SG_PLUS_TIMES_I64: launch_numeric_i64(c, st); break;
+    case SG_PLUS_TIMES_F32: launch_numeric_f32(c, st); break;
+    case SG_PLUS_TIMES_F64: launch_numeric_f64(c, st); break;
+    case SG_OR_AND_BOOL: launch_numeric_bool(c, st); break;
+    case SG_MIN_PLUS_F32: launch_numeric_minplus(c, st); break;
+    default: return sg_fail(h, SG_ERR_SEMIRING, "unknown semiring id");
+  }
+  SG_HIP(h, hipGetLastError());
+  return SG_OK;
+}
+
+const char* env(const char* name) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? v : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_semiring_make(sg_semiring_id id, uint32_t acc_flags, sg_semiring* out) {
+  if (!out) return SG_ERR_INVALID;
+  static const int bytes[6] = {0, 8, 4, 8, 1, 4};
+  if ((int)id < 1 || (int)id > 5) return SG_ERR_SEMIRING;
+  if (acc_flags > SG_ACC_PLAIN) return SG_ERR_SEMIRING;
+  out->id = (int32_t)id;
+  out->value_bytes = bytes[id];
+  out->acc_flags = acc_flags;
+  out->comp_min_terms = 64;
+  out->comp_min_products = 0;
+  return SG_OK;
+}
+
+sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value) {
+  if (!h || !name || !value) return SG_ERR_INVALID;
+  const std::string n(name), v(value);
+  if (n == "hash_max_products") {
+    char* end = nullptr;
+    const long long x = std::strtoll(value, &end, 10);
+    if (!end || *end || x < 0 || x > kHashCap) return sg_fail(h, SG_ERR_INVALID, "hash_max_products must be in [0, 4096]");
+    h->hash_max = x;
+  } else if (n == "force_path") {
+    if (v == "auto") h->force = kForceAuto;
+    else if (v == "small") h->force = kForceSmall;
+    else if (v == "hash") h->force = kForceHash;
+    else if (v == "dense") h->force = kForceDense;
+    else return sg_fail(h, SG_ERR_INVALID, "force_path must be auto, small, hash or dense");
+  } else if (n == "validate") {
+    if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "validate must be 0 or 1");
+    h->validate = v == "1";
+  } else if (n == "timing") {
+    if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "timing must be 0 or 1");
+    if (v == "1" && !h->ev[0][0]) {
+      for (int p = 0; p < kNPhases; ++p)
+        for (int b = 0; b < 2; ++b)
+          if (hipEventCreate(&h->ev[p][b]) != hipSuccess) return sg_fail(h, SG_ERR_HIP, "hipEventCreate failed");
+    }
+    h->timing = v == "1";
+    clear_phases(h, 0, kNPhases);
+    return SG_OK;
+  } else {
+    return sg_fail(h, SG_ERR_INVALID, "unknown option " + n);
+  }
+  h->cache_valid = false;
+  return SG_OK;
+}
+
+sg_status sg_tune_load(sg_handle* h, const char* path);  // tune.cpp
+
+sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out) {
+  if (!out) return SG_ERR_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return SG_ERR_HIP;
+  if (device < 0 || device >= ndev) return SG_ERR_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return SG_ERR_HIP;
+  sg_handle* h = new sg_handle;
+  h->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete h;
+    return SG_ERR_HIP;
+  }
+  h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (hipMalloc(&h->d_flags, 64 * sizeof(int32_t)) != hipSuccess) {
+    delete h;
+    return SG_ERR_NOMEM;
+  }
+  (void)hipMemset(h->d_flags, 0, 64 * sizeof(int32_t));
+  if (hipHostMalloc(&h->h_pin, 4096, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(h->d_flags);
+    delete h;
+    return SG_ERR_NOMEM;
+  }
+  if (const char* v = env("SG_VALIDATE")) h->validate = std::atoi(v) != 0;
+  if (const char* v = env("SG_FORCE_PATH")) {
+    if (sg_handle_set_option(h, "force_path", v) != SG_OK) {
+      sg_handle_destroy(h);
+      return SG_ERR_INVALID;
+    }
+  }
+  if (const char* v = env("SG_HASH_MAX")) {
+    if (sg_handle_set_option(h, "hash_max_products", v) != SG_OK) {
+      sg_handle_destroy(h);
+      return SG_ERR_INVALID;
+    }
+  }
+  const char* tj = tuning_json ? tuning_json : env("SG_TUNING");
+  if (tj) {
+    const sg_status s = sg_tune_load(h, tj);
+    if (s != SG_OK) {
+      sg_handle_destroy(h);
+      return s;
+    }
+  }
+  (void)hipDeviceSynchronize();
+  *out = h;
+  return SG_OK;
+}
+
+sg_status sg_handle_destroy(sg_handle* h) {
+  if (!h) return SG_ERR_INVALID;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  h->ws.release();
+  h->rp2_buf.release();
+  h->off2_buf.release();
+  h->parts_buf.release();
+  if (h->d_flags) (void)hipFree(h->d_flags);
+  if (h->h_pin) (void)hipHostFree(h->h_pin);
+  for (int p = 0; p < kNPhases; ++p)
+    for (int b = 0; b < 2; ++b)
+      if (h->ev[p][b]) (void)hipEventDestroy(h->ev[p][b]);
+  delete h;
+  return SG_OK;
+}
+
+sg_status sg_spgemm_symbolic(sg_handle* h, const sg_csr* A, const sg_csr* B, int64_t* C_rowptr, int64_t* nnzC,
+                             void* stream) {
+  if (!h) return SG_ERR_INVALID;
+  SG_TRY(check_csr(h, A, "A"));
+  SG_TRY(check_csr(h, B, "B"));
+  if (!C_rowptr || !nnzC) return sg_fail(h, SG_ERR_INVALID, "C_rowptr or nnzC is NULL");
+  if (A->ncols != B->nrows) return sg_fail(h, SG_ERR_SHAPE, "A.ncols != B.nrows");
+  SG_HIP(h, hipSetDevice(h->device));
+  hipStream_t st = (hipStream_t)stream;
+  SG_TRY(validate_input(h, A, "A", st));
+  SG_TRY(validate_input(h, B, "B", st));
+  RowSource r{};
+  r.a_rowptr = A->rowptr;
+  r.a_col = A->col;
+  r.b_rowptr = B->rowptr;
+  r.b_col = B->col;
+  r.b_nrows = B->nrows;
+  r.nrows = A->nrows;
+  r.ncols = B->ncols;
+  r.T = tiles_of(B->ncols);
+  if (A->nrows == 0 || A->nnz == 0 || B->nnz == 0) {
+    // an empty operand: every row of C is empty (paper, Section 4.3 multiplies
+    // only when both inputs hold a nonzero)
+    launch_fill_i64(C_rowptr, A->nrows + 1, 0, st);
+    SG_HIP(h, hipGetLastError());
+    SG_HIP(h, hipStreamSynchronize(st));
+    *nnzC = 0;
+    h->cache_valid = false;
+    return SG_OK;
+  }
+  return run_symbolic(h, r, B, C_rowptr, nnzC, product_key(h, A, B), st);
+}
+
+sg_status sg_spgemm_numeric(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, sg_csr* C,
+                            void* stream) {
+  if (!h) return SG_ERR_INVALID;
+  SG_TRY(check_semiring(h, sr));
+  SG_TRY(check_csr(h, A, "A"));
+  SG_TRY(check_csr(h, B, "B"));
+  SG_TRY(check_csr(h, C, "C"));
+  if (A->ncols != B->nrows || C->nrows != A->nrows || C->ncols != B->ncols)
+    return sg_fail(h, SG_ERR_SHAPE, "shapes of A, B and C do not match");
+  if ((A->nnz > 0 && !A->val) || (B->nnz > 0 && !B->val) || (C->nnz > 0 && !C->val))
+    return sg_fail(h, SG_ERR_INVALID, "a value array is NULL");
+  SG_HIP(h, hipSetDevice(h->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (A->nrows == 0 || C->nnz == 0) return SG_OK;
+  SG_TRY(validate_input(h, A, "A", st));
+  SG_TRY(validate_input(h, B, "B", st));
+  RowSource r{};
+  r.a_rowptr = A->rowptr;
+  r.a_col = A->col;
+  r.a_val = A->val;
+  r.b_rowptr = B->rowptr;
+  r.b_col = B->col;
+  r.b_val = B->val;
+  r.b_nrows = B->nrows;
+  r.nrows = A->nrows;
+  r.ncols = B->ncols;
+  r.T = tiles_of(B->ncols);
+  return run_numeric(h, sr, r, B, C, product_key(h, A, B), st);
+}
+
+static sg_status check_parts(sg_handle* h, int nparts, const sg_csr* parts) {
+  if (nparts < 1 || nparts > 4096 || !parts) return sg_fail(h, SG_ERR_INVALID, "nparts must be in [1, 4096]");
+  for (int s = 0; s < nparts; ++s) {
+    SG_TRY(check_csr(h, &parts[s], "part"));
+    if (parts[s].nrows != parts[0].nrows || parts[s].ncols != parts[0].ncols)
+      return sg_fail(h, SG_ERR_SHAPE, "merge parts differ in shape");
+  }
+  return SG_OK;
+}
+
+sg_status sg_spgemm_merge_symbolic(sg_handle* h, int nparts, const sg_csr* parts, int64_t* C_rowptr, int64_t* nnzC,
+                                   void* stream) {
+  if (!h) return SG_ERR_INVALID;
+  SG_TRY(check_parts(h, nparts, parts));
+  if (!C_rowptr || !nnzC) return sg_fail(h, SG_ERR_INVALID, "C_rowptr or nnzC is NULL");
+  SG_HIP(h, hipSetDevice(h->device));
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < nparts; ++s) SG_TRY(validate_input(h, &parts[s], "part", st));
+  const int64_t n = parts[0].nrows;
+  int64_t total = 0;
+  for (int s = 0; s < nparts; ++s) total += parts[s].nnz;
+  if (n == 0 || total == 0) {
+    launch_fill_i64(C_rowptr, n + 1, 0, st);
+    SG_HIP(h, hipGetLastError());
+    SG_HIP(h, hipStreamSynchronize(st));
+    *nnzC = 0;
+    h->cache_valid = false;
+    return SG_OK;
+  }
+  SG_TRY(upload_parts(h, nparts, parts, st));
+  RowSource r{};
+  r.merge = 1;
+  r.parts = (const PartDesc*)h->parts_buf.p;
+  r.nparts = nparts;
+  r.nrows = n;
+  r.ncols = parts[0].ncols;
+  r.T = tiles_of(parts[0].ncols);
+  return run_symbolic(h, r, nullptr, C_rowptr, nnzC, merge_key(h, nparts, parts), st);
+}
+
+sg_status sg_spgemm_merge_numeric(sg_handle* h, const sg_semiring* sr, int nparts, const sg_csr* parts, sg_csr* C,
+                                  void* stream) {
+  if (!h) return SG_ERR_INVALID;
+  SG_TRY(check_semiring(h, sr));
+  SG_TRY(check_parts(h, nparts, parts));
+  SG_TRY(check_csr(h, C, "C"));
+  if (C->nrows != parts[0].nrows || C->ncols != parts[0].ncols)
+    return sg_fail(h, SG_ERR_SHAPE, "C does not have the parts' shape");
+  for (int s = 0; s < nparts; ++s)
+    if (parts[s].nnz > 0 && !parts[s].val) return sg_fail(h, SG_ERR_INVALID, "a part's value array is NULL");
+  if (C->nnz > 0 && !C->val) return sg_fail(h, SG_ERR_INVALID, "C.val is NULL");
+  SG_HIP(h, hipSetDevice(h->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (C->nrows == 0 || C->nnz == 0) return SG_OK;
+  for (int s = 0; s < nparts; ++s) SG_TRY(validate_input(h, &parts[s], "part", st));
+  SG_TRY(upload_parts(h, nparts, parts, st));
+  RowSource r{};
+  r.merge = 1;
+  r.parts = (const PartDesc*)h->parts_buf.p;
+  r.nparts = nparts;
+  r.nrows = C->nrows;
+  r.ncols = C->ncols;
+  r.T = tiles_of(C->ncols);
+  return run_numeric(h, sr, r, nullptr, C, merge_key(h, nparts, parts), st);
+}
+
+sg_status sg_handle_check(sg_handle* h) {
+  if (!h) return SG_ERR_INVALID;
+  SG_HIP(h, hipSetDevice(h->device));
+  SG_HIP(h, hipDeviceSynchronize());
+  int32_t v = 0;
+  SG_HIP(h, hipMemcpy(&v, h->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (v) {
+    SG_HIP(h, hipMemset(h->d_flags, 0, sizeof(int32_t)));
+    return sg_fail(h, SG_ERR_INVALID, "a numeric pass filled a different number of entries than its symbolic pass");
+  }
+  return SG_OK;
+}
+
+sg_status sg_handle_timings(sg_handle* h, double* ms, int n) {
+  if (!h || !ms || n < 0) return SG_ERR_INVALID;
+  if (!h->timing) return sg_fail(h, SG_ERR_INVALID, "the timing option is off");
+  SG_HIP(h, hipSetDevice(h->device));
+  for (int p = 0; p < n && p < kNPhases; ++p) {
+    ms[p] = 0.0;
+    if (!h->ev_rec[p]) continue;
+    SG_HIP(h, hipEventSynchronize(h->ev[p][1]));
+    float t = 0.f;
+    SG_HIP(h, hipEventElapsedTime(&t, h->ev[p][0], h->ev[p][1]));
+    ms[p] = t;
+  }
+  return SG_OK;
+}
+
+const char* sg_status_string(sg_status s) {
+  switch (s) {
+    case SG_OK: return "SG_OK";
+    case SG_ERR_INVALID: return "SG_ERR_INVALID";
+    case SG_ERR_SHAPE: return "SG_ERR_SHAPE";
+    case SG_ERR_SEMIRING: return "SG_ERR_SEMIRING";
+    case SG_ERR_NOMEM: return "SG_ERR_NOMEM";
+    case SG_ERR_OVERFLOW: return "SG_ERR_OVERFLOW";
+    case SG_ERR_UNSORTED: return "SG_ERR_UNSORTED";
+    case SG_ERR_HIP: return "SG_ERR_HIP";
+  }
+  return "unknown status";
+}
+
+const char* sg_last_error(const sg_handle* h) { return h ? h->err.c_str() : "no handle"; }
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+// Structural kernels and their launchers: row analysis and binning, tile
+// bounds, the symbolic pass (semiring independent), prefix sums, fills and
+// input validation.
+#include "sg_launch.hpp"
+
+namespace sg {
+
+namespace {
+constexpr int kAnaBS = 256;
+
+// Per-bin totals, bin starts and per-(block, bin) scatter offsets.  One block
+// of 1024 threads: 16 lanes per bin split the blocks into 16 runs.
+__global__ __launch_bounds__(1024) void k_bin_offsets(const int32_t* hist, int32_t nblk, int32_t* blk_off,
+                                                      int32_t* bin_start, int32_t* bin_count) {
+  __shared__ int32_t s_cnt[kNB], s_start[kNB];
+  const int b = threadIdx.x >> 4, g = threadIdx.x & 15;
+  const int per = (nblk + 15) / 16;
+  const int lo = g * per;
+  const int hi = (lo + per) < nblk ? (lo + per) : nblk;
+  int32_t sum = 0;
+  for (int k = lo; k < hi; ++k) sum += hist[(int64_t)k * kNB + b];
+  int32_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+    const int32_t u = __shfl_up(incl, (unsigned)d, 16);
+    if (g >= d) incl += u;
+  }
+  const int32_t excl = incl - sum;
+  if (g == 15) s_cnt[b] = incl;
+  __syncthreads();
+  if (threadIdx.x < kNB) {
+    const int32_t v = s_cnt[threadIdx.x];
+    const int32_t inc = wave_incl_scan(v);
+    s_start[threadIdx.x] = inc - v;
+    bin_start[threadIdx.x] = inc - v;
+    bin_count[threadIdx.x] = v;
+  }
+  __syncthreads();
+  int32_t run = s_start[b] + excl;
+  for (int k = lo; k < hi; ++k) {
+    blk_off[(int64_t)k * kNB + b] = run;
+    run += hist[(int64_t)k * kNB + b];
+  }
+}
+
+// Per B row, rp2[k*(T+1) + t] = number of entries of row k with column below
+// t*16384 (t = 0..T).  One wavefront per row, lanes over t, binary search.
+__global__ __launch_bounds__(256) void k_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows,
+                                                     int32_t T, int32_t* rp2) {
+  const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t k = w0; k < nrows; k += nw) {
+    const int64_t s = rowptr[k], e = rowptr[k + 1];
+    int32_t* r = rp2 + k * (T + 1);
+    for (int t = lane_id(); t <= T; t += kWave) {
+      const int64_t pos = (t == 0) ? s : (t == T ? e : lower_bound_col(col, s, e, (int64_t)t << kTileLog));
+      r[t] = (int32_t)(pos - s);
+    }
+  }
+}
+
+// ---- prefix sums over int64 (in place, inclusive) -----------------------------------
+__global__ __launch_bounds__(kScanBS) void k_scan_reduce(const int64_t* a, int64_t n, int64_t* partial) {
+  __shared__ int64_t s_wave[kScanBS / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  int64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    const int64_t x = base + (int64_t)q * kScanBS + threadIdx.x;
+    if (x < n) sum += a[x];
+  }
+  const int64_t tot = block_sum<kScanBS / kWave, int64_t>(sum, s_wave);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block partials by one block.
+__global__ __launch_bounds__(kScanBS) void k_scan_partials(int64_t* partial, int64_t nblk) {
+  __shared__ int64_t s_wave[kScanBS / kWave];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblk; b0 += kScanBS) {
+    const int64_t x = b0 + threadIdx.x;
+    const int64_t v = x < nblk ? partial[x] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<kScanBS / kWave, int64_t>(v, s_wave, &tot);
+    if (x < nblk) partial[x] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanBS) void k_scan_apply(int64_t* a, int64_t n, const int64_t* partial) {
+  __shared__ int64_t s_wave[kScanBS / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+  int64_t v[kScanPer];
+  int64_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    const int64_t x = base + q;
+    v[q] = x < n ? a[x] : 0;
+    sum += v[q];
+  }
+  int64_t tot;
+  int64_t run = partial[blockIdx.x] + block_excl_scan<kScanBS / kWave, int64_t>(sum, s_wave, &tot);
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    run += v[q];
+    const int64_t x = base + q;
+    if (x < n) a[x] = run;
+  }
+}
+
+
+template <class Src>
+void analyze_src(const Src& s, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p,
+                 uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                 int32_t* list, int64_t* cnt_out, hipStream_t st) {
+  const int64_t nblk = analyze_blocks(r.nrows);
+  hipLaunchKernelGGL((k_analyze<Src, kAnaBS>), dim3(nblk), dim3(kAnaBS), 0, st, s, r.nrows, pol, c_rowptr, p, bin,
+                     hist, cnt_out);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, hist, (int32_t)nblk, blk_off, bin_start, bin_count);
+  hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, list);
+}
+
+template <class Src, int LGS, int BS>
+void sym_hash_one(const Src& s, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
+  const int n = plan.count[bin];
+  if (n == 0) return;
+  auto k = k_sym_hash<Src, LGS, BS>;
+  static int occ = occupancy(k, BS);
+  hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, s, plan.bins, bin, cnt_out);
+}
+
+template <class Src>
+void sym_dense_src(const Src& s, const BinPlan& plan, int64_t ncols, int64_t* cnt_out, int32_t* off2, int cus,
+                   hipStream_t st) {
+  const int nd = plan.ndense();
+  if (nd == 0) return;
+  auto k = k_sym_dense<Src>;
+  static int occ = occupancy(k, 512);
+  hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(512), 0, st, s, plan.bins, ncols, cnt_out, off2);
+}
+
+template <class Src>
+void symbolic_src(const Src& s, const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
+                  const Marks& marks, hipStream_t st) {
+  marks.mark(kPhSymSmall, 1);
+  if (plan.count[kBinSmall]) {
+    auto k = k_sym_small<Src>;
+    static int occ = occupancy(k, 256);
+    hipLaunchKernelGGL(k, dim3(grid_for(plan.count[kBinSmall], 4, cus * occ * 4)), dim3(256), 0, st, s, plan.bins,
+                       kBinSmall, cnt_out);
+  }
+  marks.mark(kPhSymSmall, 0);
+  marks.mark(kPhSymHash, 1);
+  // hash bins hold tables of 2^8 .. 2^13 keys (symbolic tables start at 256)
+  sym_hash_one<Src, 8, 256>(s, plan, kBinHash0 + 1, cnt_out, cus, st);
+  sym_hash_one<Src, 9, 256>(s, plan, kBinHash0 + 2, cnt_out, cus, st);
+  sym_hash_one<Src, 10, 256>(s, plan, kBinHash0 + 3, cnt_out, cus, st);
+  sym_hash_one<Src, 11, 512>(s, plan, kBinHash0 + 4, cnt_out, cus, st);
+  sym_hash_one<Src, 12, 512>(s, plan, kBinHash0 + 5, cnt_out, cus, st);
+  sym_hash_one<Src, 13, 512>(s, plan, kBinHash0 + 6, cnt_out, cus, st);
+  marks.mark(kPhSymHash, 0);
+  marks.mark(kPhSymDense, 1);
+  sym_dense_src(s, plan, r.ncols, cnt_out, off2, cus, st);
+  marks.mark(kPhSymDense, 0);
+}
+
+__global__ __launch_bounds__(256) void k_validate(const int64_t* rowptr, const int32_t* col, int64_t nrows,
+                                                  int64_t ncols, int64_t nnz, int32_t* flag) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nrows; i += (int64_t)gridDim.x * 256) {
+    const int64_t s = rowptr[i], e = rowptr[i + 1];
+    bool bad = (i == 0 && s != 0) || e < s || (i == nrows - 1 && e != nnz) || s < 0 || e > nnz;
+    if (!bad) {
+      int64_t prev = -1;
+      for (int64_t x = s; x < e; ++x) {
+        const int64_t c = col[x];
+        if (c <= prev || c >= ncols) {
+          bad = true;
+          break;
+        }
+        prev = c;
+      }
+    }
+    if (bad) atomicOr(flag, 1);
+  }
+}
+}  // namespace
+
+int64_t analyze_blocks(int64_t nrows) { return (nrows + kAnaBS - 1) / kAnaBS; }
+
+void launch_analyze(const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p, uint8_t* bin,
+                    int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count, int32_t* list,
+                    int64_t* cnt_out, hipStream_t st) {
+  if (r.merge)
+    analyze_src(make_merge_src<uint8_t>(r), r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count, list,
+                cnt_out, st);
+  else
+    analyze_src(make_spgemm_src<uint8_t, false>(r), r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count,
+                list, cnt_out, st);
+}
+
+void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,
+                        hipStream_t st) {
+  if (nrows == 0) return;
+  hipLaunchKernelGGL(k_tile_bounds, dim3(grid_for(nrows, 4, cus * 16)), dim3(256), 0, st, rowptr, col, nrows, T, rp2);
+}
+
+void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
+                     const Marks& marks, hipStream_t st) {
+  if (r.merge) symbolic_src(make_merge_src<uint8_t>(r), r, plan, cnt_out, off2, cus, marks, st);
+  else symbolic_src(make_spgemm_src<uint8_t, false>(r), r, plan, cnt_out, off2, cus, marks, st);
+}
+
+void launch_symbolic_dense(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
+                           hipStream_t st) {
+  if (r.merge) sym_dense_src(make_merge_src<uint8_t>(r), plan, r.ncols, cnt_out, off2, cus, st);
+  else sym_dense_src(make_spgemm_src<uint8_t, false>(r), plan, r.ncols, cnt_out, off2, cus, st);
+}
+
+int64_t scan_partials_len(int64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }
+
+void launch_scan_inclusive(int64_t* a, int64_t n, int64_t* partial, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t nblk = (n + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kScanBS), 0, st, a, n, partial);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBS), 0, st, partial, nblk);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanBS), 0, st, a, n, partial);
+}
+
+void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<int64_t>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_validate(const int64_t* rowptr, const int32_t* col, int64_t nrows, int64_t ncols, int64_t nnz,
+                     int32_t* flag, hipStream_t st) {
+  if (nrows == 0) return;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(nrows, 256, 4096)), dim3(256), 0, st, rowptr, col, nrows, ncols, nnz,
+                     flag);
+}
+
+}  // namespace sg

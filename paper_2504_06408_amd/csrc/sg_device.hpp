@@ -1,0 +1,217 @@
+// Device building blocks shared by the gfx950 kernels: wavefront-64 scans and
+// reductions, a block-wide exclusive scan, the LDS open-addressing hash used
+// to find an output slot for a column id, an LDS bitonic sort, and the
+// flattened product iterator that spreads the uneven B-row segments of one
+// output row evenly over a workgroup's lanes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SG_DEV __device__ __forceinline__
+
+namespace sg {
+
+constexpr int kWave = 64;
+constexpr int32_t kEmptyKey = -1;
+
+SG_DEV int lane_id() { return (int)__lane_id(); }
+SG_DEV int wave_id() { return (int)(threadIdx.x >> 6); }
+
+SG_DEV unsigned long long lanes_below() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <class T>
+SG_DEV T shfl(T v, int src) {
+  return __shfl(v, src, kWave);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+template <class T>
+SG_DEV T wave_incl_scan(T v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T u = __shfl_up(v, (unsigned)d, kWave);
+    if (l >= d) v += u;
+  }
+  return v;
+}
+
+template <class T>
+SG_DEV T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+template <class T>
+SG_DEV T wave_max(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    T u = __shfl_xor(v, d, kWave);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan for NW wavefronts.  s_wave: NW slots of LDS.
+// Returns the exclusive prefix of v; *total receives the block sum.  Every
+// thread of the block must call it (it contains barriers).
+template <int NW, class T>
+SG_DEV T block_excl_scan(T v, T* s_wave, T* total) {
+  const T incl = wave_incl_scan(v);
+  if (lane_id() == kWave - 1) s_wave[wave_id()] = incl;
+  __syncthreads();
+  T pre = 0, tot = 0;
+  const int w = wave_id();
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const T s = s_wave[i];
+    pre += (i < w) ? s : (T)0;
+    tot += s;
+  }
+  *total = tot;
+  __syncthreads();
+  return pre + incl - v;
+}
+
+template <int NW, class T>
+SG_DEV T block_sum(T v, T* s_wave) {
+  T tot;
+  (void)block_excl_scan<NW, T>(v, s_wave, &tot);
+  return tot;
+}
+
+SG_DEV int ceil_log2_u64(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll((long long)(x - 1)); }
+
+// ---------------------------------------------------------------------------
+// LDS hash of int32 column ids, linear probing, power-of-two size 2^lgS.
+// Multiplicative hashing spreads the clustered low column ids of power-law
+// graphs.  The table must never fill up (callers size it >= 2x keys).
+SG_DEV uint32_t hash_home(int32_t key, int lgS) { return ((uint32_t)key * 0x9E3779B1u) >> (32 - lgS); }
+
+// Find or claim the slot of `key`; *fresh tells whether this call claimed it.
+// Returns kHashFull after probing every slot without success (a full table,
+// which only inconsistent inputs can cause), so a wave never spins forever.
+constexpr uint32_t kHashFull = 0xFFFFFFFFu;
+SG_DEV uint32_t hash_insert(int32_t* keys, int lgS, int32_t key, bool* fresh) {
+  const uint32_t mask = (1u << lgS) - 1u;
+  uint32_t s = hash_home(key, lgS);
+  *fresh = false;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    int32_t cur = __hip_atomic_load(keys + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == key) {
+      *fresh = false;
+      return s;
+    }
+    if (cur == kEmptyKey) {
+      const int32_t old = atomicCAS(keys + s, kEmptyKey, key);
+      if (old == kEmptyKey) {
+        *fresh = true;
+        return s;
+      }
+      if (old == key) {
+        *fresh = false;
+        return s;
+      }
+    }
+    s = (s + 1u) & mask;
+  }
+  return kHashFull;
+}
+
+// ---------------------------------------------------------------------------
+// Ascending bitonic sort of n (power of two) 64-bit keys in LDS by a whole
+// workgroup of BS threads.  Contains barriers.
+template <int BS>
+SG_DEV void block_bitonic_sort(uint64_t* buf, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int x = threadIdx.x; x < (n >> 1); x += BS) {
+        const int i = 2 * x - (x & (j - 1));
+        const int l = i + j;
+        const uint64_t a = buf[i], b = buf[l];
+        const bool up = (i & k) == 0;
+        if ((a > b) == up) {
+          buf[i] = b;
+          buf[l] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Ascending bitonic sort across the 64 lanes of a wavefront of (key, payload)
+// pairs, keys compared as signed int32.
+template <class P>
+SG_DEV void wave_bitonic_sort(int32_t& key, P& pay) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int32_t ok = __shfl_xor(key, j, kWave);
+      const P op = __shfl_xor(pay, j, kWave);
+      const bool lower = (l & j) == 0;
+      const bool up = (l & k) == 0;
+      // the lower lane of a pair keeps the smaller key when sorting up
+      const bool take_other = (lower == up) ? (ok < key) : (ok > key);
+      if (take_other) {
+        key = ok;
+        pay = op;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Flattened product iteration for one output row by a whole workgroup.
+//
+// An output row is fed by `nsrc` sources (A's stored entries of the row, or
+// the parts of a merge); source j contributes a segment of `len` consecutive
+// entries starting at `start` in its own arrays.  Lengths are very uneven
+// (power-law B rows), so instead of one lane per source the sources are taken
+// BS at a time, their lengths are prefix-summed, and product q of the chunk
+// goes to lane q mod BS: lane loads of one segment are contiguous and every
+// lane does the same amount of work.
+//
+// Src provides:
+//   using Item;                              per-source payload kept in LDS
+//   SG_DEV void load(int64_t j, Item& it, int64_t& start, int64_t& len) const;
+// and body(const Item&, int64_t idx) is called once per product with the
+// product's index in its source's arrays.
+template <int BS, class Src, class Body>
+SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s_item, int64_t* s_start,
+                             int64_t* s_off, int64_t* s_wave, Body& body) {
+  constexpr int NW = BS / kWave;
+  for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
+    const int64_t j = c0 + threadIdx.x;
+    int64_t start = 0, len = 0;
+    typename Src::Item it{};
+    if (j < nsrc) src.load(j, it, start, len);
+    int64_t total;
+    const int64_t off = block_excl_scan<NW, int64_t>(len, s_wave, &total);
+    s_item[threadIdx.x] = it;
+    s_start[threadIdx.x] = start;
+    s_off[threadIdx.x] = off;
+    const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < total; q += BS) {
+      // owner: the last source whose offset is <= q
+      int lo = 0, hi = nc - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= q) lo = mid;
+        else hi = mid - 1;
+      }
+      body(s_item[lo], s_start[lo] + (q - s_off[lo]));
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace sg

@@ -1,0 +1,98 @@
+// Handle, scratch memory and shared host-side helpers of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spgemm.h"
+#include "sg_launch.hpp"
+
+// Grow-only device buffer.
+struct SgBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    const size_t nb = bytes + bytes / 4 + 4096;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = nb;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// Bump allocator over a buffer; with base == nullptr it only measures.
+struct SgArena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* r = base ? (T*)(base + off) : nullptr;
+    off += n * sizeof(T) + 1;
+    return r;
+  }
+};
+
+struct SgCacheKey {
+  uint64_t w[16];
+  bool operator==(const SgCacheKey& o) const {
+    for (int i = 0; i < 16; ++i)
+      if (w[i] != o.w[i]) return false;
+    return true;
+  }
+};
+
+struct sg_handle {
+  int device = 0;
+  int cus = 256;
+  std::string err;
+  // options
+  int force = sg::kForceAuto;
+  int64_t hash_max = sg::kHashCap;
+  int validate = 0;
+  int timing = 0;
+  hipEvent_t ev[sg::kNPhases][2] = {};
+  bool ev_rec[sg::kNPhases] = {};
+  hipStream_t mark_stream = nullptr;
+  // scratch
+  SgBuf ws;                  // per call
+  SgBuf rp2_buf, off2_buf;   // dense-path data kept from symbolic for numeric
+  SgBuf parts_buf;           // device table of merge parts
+  std::vector<sg::PartDesc> parts_host;
+  bool cache_valid = false;
+  SgCacheKey cache_key{};
+  int32_t cache_T = 0, cache_nd = 0;
+  int32_t* d_flags = nullptr;  // [0] consistency error, [1] task counter, [2] validation, [3..] batch
+  int64_t* h_pin = nullptr;    // pinned readback area (>= 256 int64)
+};
+
+// Status with message.
+sg_status sg_fail(sg_handle* h, sg_status s, const std::string& msg);
+sg_status sg_check_hip(sg_handle* h, hipError_t e, const char* what);
+
+namespace sg {
+int32_t tiles_of(int64_t ncols);
+Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr);
+// Analysis + binning of the rows of r; waits for the stream to read the bin
+// counts.  Scratch comes from `ar`.
+sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* cnt_out,
+                    SgArena& ar, BinPlan& plan, hipStream_t st);
+size_t plan_rows_bytes(int64_t nrows);
+// Timing hooks of the handle for a call on stream st (inactive unless the
+// "timing" option is on); clear_phases forgets phases [p0, p1).
+Marks handle_marks(sg_handle* h, hipStream_t st);
+void clear_phases(sg_handle* h, int p0, int p1);
+}  // namespace sg

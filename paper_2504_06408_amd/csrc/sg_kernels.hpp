@@ -1,0 +1,657 @@
+// Kernel templates of the semiring product and merge on gfx950.
+//
+// Pipeline for one product C = A (x).(+) B (the local multiply of a Sparse
+// SUMMA stage, paper Sections 2.1 and 4.3):
+//   analyze   p_i = sum_{k in A_i} nnz(B_k) products per row, row -> bin
+//   bin       stable counting sort of rows into bins (lists per bin)
+//   bounds    per B row, the offsets where each 16384-column tile starts
+//   symbolic  nnz(C_i): wave sort (<= 64 products), LDS hash (<= 4096
+//             products) or LDS bitmap over column tiles (dense rows); dense
+//             rows also get per-tile output offsets
+//   scan      C.rowptr = prefix sum of the counts
+//   numeric   C_ij = (+)_k A_ik (x) B_kj: wave sort + segmented fold, LDS
+//             hash + bitonic sort, or a dense LDS accumulator per
+//             (row, column tile) task with bitmap compaction, which writes
+//             rows sorted with no sort at all.
+// The merge (Section 4.4) runs the same kernels with a different "source":
+// the parts' rows instead of B rows selected by A's entries, and (x) replaced
+// by taking the part's value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_device.hpp"
+#include "sg_semiring.hpp"
+
+namespace sg {
+
+// ---- bins and path parameters ----------------------------------------------
+constexpr int kNB = 64;
+constexpr int kBinEmpty = 0;
+constexpr int kBinSmall = 1;
+constexpr int kBinHash0 = 2;   // 2..8: hash table of 2^(7+b-2) slots
+constexpr int kBinHashC0 = 9;  // 9..15: same, compensated float sums
+constexpr int kBinDense0 = 16; // 16..63: dense rows, larger product counts first
+constexpr int kHashLgMin = 7, kHashLgMax = 13;
+constexpr int kSmallMax = 64;     // products of a wave-sorted row
+constexpr int kHashCap = 4096;    // products (symbolic) / entries (numeric) of a hash row
+constexpr int kTileLog = 14;      // dense column tile: 16384 columns
+constexpr int kTile = 1 << kTileLog;
+constexpr int kTileWords = kTile / 32;
+constexpr int kSymTiles = 64;     // tiles per bitmap pass of the dense symbolic kernel (128 KB)
+
+enum { kForceAuto = 0, kForceSmall = 1, kForceHash = 2, kForceDense = 3 };
+enum { kCompNone = 0, kCompRule = 1, kCompAll = 2 };
+
+struct Policy {
+  int32_t numeric;  // 0: symbolic (hash size from products), 1: numeric (from entries)
+  int32_t force;
+  int64_t hash_max;  // rows with more products take the dense path
+  int32_t comp_mode;
+  int32_t comp_min_terms;
+  int64_t comp_min_products;
+};
+
+SG_DEV int hash_bin(int64_t need, int lg_floor) {
+  // smallest table 2^lg >= 2*need, at least 2^lg_floor
+  int lg = ceil_log2_u64((uint64_t)(2 * need));
+  lg = lg < lg_floor ? lg_floor : lg;
+  return kBinHash0 + (lg - kHashLgMin);
+}
+
+SG_DEV bool is_dense(const Policy& pol, int64_t p) {
+  if (p == 0) return false;
+  if (pol.force == kForceDense) return true;
+  if (pol.force == kForceSmall && p <= kSmallMax) return false;
+  if (pol.force == kForceHash) return p > kHashCap;
+  return p > pol.hash_max;
+}
+
+SG_DEV int bin_of(const Policy& pol, int64_t p, int64_t m, int64_t nterms) {
+  if (p == 0) return kBinEmpty;
+  if (is_dense(pol, p)) {
+    int lg = ceil_log2_u64((uint64_t)p);
+    lg = lg > 47 ? 47 : lg;
+    return kNB - 1 - lg;  // 16..63
+  }
+  const bool small = (pol.force == kForceSmall || pol.force == kForceAuto) && p <= kSmallMax;
+  if (small) return kBinSmall;
+  if (!pol.numeric) return hash_bin(p, 8);
+  const bool comp = pol.comp_mode == kCompAll ||
+                    (pol.comp_mode == kCompRule && nterms > pol.comp_min_terms && p > pol.comp_min_products);
+  const int64_t mm = m < 1 ? 1 : (m > kHashCap ? kHashCap : m);
+  return hash_bin(mm, kHashLgMin) + (comp ? (kBinHashC0 - kBinHash0) : 0);
+}
+
+// ---- sources -----------------------------------------------------------------
+
+template <class T>
+SG_DEV T shfl_any(T v, int src) {
+  static_assert(sizeof(T) <= 8, "shfl_any");
+  uint64_t u = 0;
+  __builtin_memcpy(&u, &v, sizeof(T));
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)u, src, kWave);
+  uint32_t hi = 0;
+  if (sizeof(T) > 4) hi = (uint32_t)__shfl((int)(uint32_t)(u >> 32), src, kWave);
+  u = (uint64_t)lo | ((uint64_t)hi << 32);
+  T o;
+  __builtin_memcpy(&o, &u, sizeof(T));
+  return o;
+}
+
+template <class T>
+SG_DEV T shfl_down_any(T v, int d) {
+  const int l = lane_id();
+  return shfl_any(v, l + d < kWave ? l + d : l);
+}
+
+// Row i of A (x) B: one source per stored A_ik, segment = B's row k (or the
+// part of it inside column tiles [t0, t1)).
+template <class V, bool kVals>
+struct SpgemmSrc {
+  const int64_t* a_rowptr;
+  const int32_t* a_col;
+  const V* a_val;
+  const int64_t* b_rowptr;
+  const int32_t* b_col;
+  const V* b_val;
+  const int32_t* rp2;  // per B row: T+1 row-local offsets where tile t starts
+  int32_t T;           // column tiles of B
+  int64_t a0;
+  int32_t t0, t1;
+
+  struct Item {
+    V a;
+  };
+
+  SG_DEV int64_t bind(int64_t i, int32_t ta, int32_t tb) {
+    a0 = a_rowptr[i];
+    t0 = ta;
+    t1 = tb;
+    return a_rowptr[i + 1] - a0;
+  }
+  SG_DEV void load(int64_t j, Item& it, int64_t& start, int64_t& len) const {
+    const int64_t e = a0 + j;
+    const int32_t k = a_col[e];
+    if constexpr (kVals) it.a = a_val[e];
+    const int64_t b0 = b_rowptr[k];
+    if (t0 == 0 && t1 == T) {
+      start = b0;
+      len = b_rowptr[k + 1] - b0;
+    } else {
+      const int32_t* r = rp2 + (int64_t)k * (T + 1);
+      const int32_t s = r[t0];
+      start = b0 + s;
+      len = r[t1] - s;
+    }
+  }
+  SG_DEV int32_t col(const Item&, int64_t idx) const { return b_col[idx]; }
+  template <class Sr>
+  SG_DEV typename Sr::Acc value(const Item& it, int64_t idx) const {
+    return Sr::mul(it.a, b_val[idx]);
+  }
+  SG_DEV static Item shfl_item(const Item& it, int src) {
+    Item o;
+    o.a = shfl_any(it.a, src);
+    return o;
+  }
+};
+
+struct PartDesc {
+  const int64_t* rowptr;
+  const int32_t* col;
+  const void* val;
+  int64_t nnz;
+};
+
+SG_DEV int64_t lower_bound_col(const int32_t* col, int64_t lo, int64_t hi, int64_t x) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)col[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Row i of a merge: one source per part, segment = the part's row i.
+template <class V>
+struct MergeSrc {
+  const PartDesc* parts;
+  int32_t nparts;
+  int32_t T;
+  int64_t ncols;
+  int64_t row;
+  int32_t t0, t1;
+
+  struct Item {
+    const int32_t* col;
+    const V* val;
+  };
+
+  SG_DEV int64_t bind(int64_t i, int32_t ta, int32_t tb) {
+    row = i;
+    t0 = ta;
+    t1 = tb;
+    return nparts;
+  }
+  SG_DEV void load(int64_t j, Item& it, int64_t& start, int64_t& len) const {
+    const PartDesc P = parts[j];
+    int64_t s = P.rowptr[row], e = P.rowptr[row + 1];
+    if (!(t0 == 0 && t1 == T)) {
+      const int64_t lo = (int64_t)t0 << kTileLog;
+      int64_t hi = (int64_t)t1 << kTileLog;
+      hi = hi < ncols ? hi : ncols;
+      s = lower_bound_col(P.col, s, e, lo);
+      e = lower_bound_col(P.col, s, e, hi);
+    }
+    it.col = P.col;
+    it.val = (const V*)P.val;
+    start = s;
+    len = e - s;
+  }
+  SG_DEV int32_t col(const Item& it, int64_t idx) const { return it.col[idx]; }
+  template <class Sr>
+  SG_DEV typename Sr::Acc value(const Item& it, int64_t idx) const {
+    return Sr::lift(it.val[idx]);
+  }
+  SG_DEV static Item shfl_item(const Item& it, int src) {
+    Item o;
+    o.col = shfl_any(it.col, src);
+    o.val = shfl_any(it.val, src);
+    return o;
+  }
+};
+
+// ---- shared argument blocks ---------------------------------------------------
+
+struct Bins {
+  const int32_t* list;   // rows of all bins, bin after bin
+  const int32_t* start;  // [kNB]
+  const int32_t* count;  // [kNB]
+};
+
+struct OutC {
+  const int64_t* rowptr;
+  int32_t* col;
+  void* val;
+};
+
+// ---- analysis and binning ---------------------------------------------------------
+
+template <class Src, int BS>
+__global__ __launch_bounds__(BS) void k_analyze(Src src, int64_t nrows, Policy pol, const int64_t* c_rowptr,
+                                                  int64_t* p_out, uint8_t* bin_out, int32_t* hist,
+                                                  int64_t* cnt_out) {
+  __shared__ int32_t s_hist[kNB];
+  for (int b = threadIdx.x; b < kNB; b += BS) s_hist[b] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const bool valid = i < nrows;
+  Src s = src;
+  const int64_t nsrc = valid ? s.bind(i, 0, s.T) : 0;
+  int64_t p = 0;
+  const bool heavy = nsrc > 32;
+  if (!heavy) {
+    for (int64_t j = 0; j < nsrc; ++j) {
+      typename Src::Item it;
+      int64_t st, len;
+      s.load(j, it, st, len);
+      p += len;
+    }
+  }
+  unsigned long long hmask = __ballot(heavy);
+  while (hmask) {
+    const int leader = __ffsll((long long)hmask) - 1;
+    hmask &= hmask - 1;
+    const int64_t ri = shfl(i, leader);
+    Src t = src;
+    const int64_t n2 = t.bind(ri, 0, t.T);
+    int64_t part = 0;
+    for (int64_t j = lane_id(); j < n2; j += kWave) {
+      typename Src::Item it;
+      int64_t st, len;
+      t.load(j, it, st, len);
+      part += len;
+    }
+    part = wave_sum(part);
+    if (lane_id() == leader) p = part;
+  }
+  if (valid) {
+    p_out[i] = p;
+    const int64_t m = pol.numeric ? (c_rowptr[i + 1] - c_rowptr[i]) : 0;
+    const int b = bin_of(pol, p, m, nsrc);
+    bin_out[i] = (uint8_t)b;
+    atomicAdd(&s_hist[b], 1);
+    if (!pol.numeric && b == kBinEmpty) cnt_out[i] = 0;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
+}
+
+// Stable scatter of row ids into their bins (ascending row order per bin).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_bin_scatter(const uint8_t* bin_in, int64_t nrows, const int32_t* blk_off,
+                                                      int32_t* list) {
+  constexpr int NW = BS / kWave;
+  __shared__ int32_t s_cnt[NW][kNB];
+  for (int x = threadIdx.x; x < NW * kNB; x += BS) (&s_cnt[0][0])[x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const bool valid = i < nrows;
+  const int b = valid ? (int)bin_in[i] : 0;
+  unsigned long long match = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 6; ++bit) {
+    const bool on = (b >> bit) & 1;
+    const unsigned long long bb = __ballot(on);
+    match &= on ? bb : ~bb;
+  }
+  const unsigned long long below = match & lanes_below();
+  const int rank = __popcll(below);
+  if (valid && below == 0) s_cnt[wave_id()][b] = __popcll(match);
+  __syncthreads();
+  if (valid) {
+    int32_t pre = 0;
+    for (int w = 0; w < wave_id(); ++w) pre += s_cnt[w][b];
+    list[blk_off[(int64_t)blockIdx.x * kNB + b] + pre + rank] = (int32_t)i;
+  }
+}
+
+// ---- prefix sums over int64 (in place, inclusive) ----
+constexpr int kScanBS = 1024, kScanPer = 8, kScanChunk = kScanBS * kScanPer;
+
+template <class T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    p[x] = v;
+}
+
+// ---- small rows: one wavefront per row, products held one per lane ---------------
+
+// Gathers the (<= 64) products of the bound row into lanes: lane q gets
+// product q (col, value); lanes beyond the row's product count get
+// (INT32_MAX, identity).  Returns the product count.
+template <class Sr, class Src, bool kVals>
+SG_DEV int wave_gather_products(Src& s, int64_t nsrc, int32_t& key, typename Sr::Acc& acc) {
+  using Item = typename Src::Item;
+  const int l = lane_id();
+  key = 0x7FFFFFFF;
+  acc = Sr::ident();
+  int base = 0;
+  for (int64_t c0 = 0; c0 < nsrc; c0 += kWave) {
+    const int64_t j = c0 + l;
+    Item it{};
+    int64_t start = 0, len = 0;
+    if (j < nsrc) s.load(j, it, start, len);
+    const int64_t incl = wave_incl_scan(len);
+    const int64_t tot = shfl(incl, kWave - 1);
+    int64_t rr = (int64_t)l - base;
+    const bool mine = rr >= 0 && rr < tot;
+    if (!mine) rr = 0;
+    // owner: first lane whose inclusive offset exceeds rr
+    int lo = 0, hi = kWave - 1;
+#pragma unroll
+    for (int step = 0; step < 6; ++step) {
+      const int mid = (lo + hi) >> 1;
+      const int64_t v = shfl(incl, mid);
+      if (v > rr) hi = mid;
+      else lo = mid + 1;
+    }
+    const int64_t o_start = shfl(start, lo);
+    const int64_t o_excl = shfl(incl - len, lo);
+    const Item o_item = Src::shfl_item(it, lo);
+    if (mine) {
+      const int64_t idx = o_start + (rr - o_excl);
+      key = s.col(o_item, idx);
+      if constexpr (kVals) acc = s.template value<Sr>(o_item, idx);
+    }
+    base += (int)tot;
+  }
+  return base;
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_sym_small(Src src, Bins bins, int bin, int64_t* cnt_out) {
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  const int w0 = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+  const int nw = gridDim.x * 4;
+  for (int r = w0; r < n; r += nw) {
+    const int64_t i = L[r];
+    Src s = src;
+    const int64_t nsrc = s.bind(i, 0, s.T);
+    int32_t key;
+    uint8_t dummy;
+    wave_gather_products<SrBool, Src, false>(s, nsrc, key, dummy);
+    wave_bitonic_sort(key, dummy);
+    const int32_t prev = __shfl_up(key, 1u, kWave);
+    const bool head = key != 0x7FFFFFFF && (lane_id() == 0 || prev != key);
+    const unsigned long long hm = __ballot(head);
+    if (lane_id() == 0) cnt_out[i] = __popcll(hm);
+  }
+}
+
+template <class Sr, class Src>
+__global__ __launch_bounds__(256) void k_num_small(Src src, Bins bins, int bin, OutC C, int32_t* err) {
+  using Acc = typename Sr::Acc;
+  using V = typename Sr::V;
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  const int w0 = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+  const int nw = gridDim.x * 4;
+  for (int r = w0; r < n; r += nw) {
+    const int64_t i = L[r];
+    Src s = src;
+    const int64_t nsrc = s.bind(i, 0, s.T);
+    int32_t key;
+    Acc acc;
+    wave_gather_products<Sr, Src, true>(s, nsrc, key, acc);
+    wave_bitonic_sort(key, acc);
+    // segmented fold of equal keys: after the loop the first lane of each run
+    // holds the (+) of the whole run
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int32_t ok = shfl_down_any(key, d);
+      const Acc oa = shfl_down_any(acc, d);
+      if (lane_id() + d < kWave && ok == key) acc = Sr::add(acc, oa);
+    }
+    const int32_t prev = __shfl_up(key, 1u, kWave);
+    const bool head = key != 0x7FFFFFFF && (lane_id() == 0 || prev != key);
+    const unsigned long long hm = __ballot(head);
+    const int64_t o = C.rowptr[i];
+    const int64_t m = C.rowptr[i + 1] - o;
+    if (head) {
+      const int pos = __popcll(hm & lanes_below());
+      if (pos < m) {
+        C.col[o + pos] = key;
+        ((V*)C.val)[o + pos] = Sr::out(acc);
+      }
+    }
+    if (lane_id() == 0 && __popcll(hm) != m) atomicOr(err, 1);
+  }
+}
+
+// ---- hash rows: one workgroup per row, LDS open addressing --------------------------
+
+template <class Src, int LGS, int BS>
+__global__ __launch_bounds__(BS) void k_sym_hash(Src src, Bins bins, int bin, int64_t* cnt_out) {
+  constexpr int S = 1 << LGS, NW = BS / kWave;
+  using Item = typename Src::Item;
+  __shared__ int32_t s_keys[S];
+  __shared__ Item s_item[BS];
+  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = L[r];
+    for (int x = threadIdx.x; x < S; x += BS) s_keys[x] = kEmptyKey;
+    __syncthreads();
+    Src s = src;
+    const int64_t nsrc = s.bind(i, 0, s.T);
+    int64_t fresh_cnt = 0;
+    auto body = [&](const Item& it, int64_t idx) {
+      bool fresh;
+      hash_insert(s_keys, LGS, s.col(it, idx), &fresh);
+      fresh_cnt += fresh ? 1 : 0;
+    };
+    for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+    const int64_t tot = block_sum<NW, int64_t>(fresh_cnt, s_wave);
+    if (threadIdx.x == 0) cnt_out[i] = tot;
+  }
+}
+
+template <class Sr, class Src, int LGS, int BS>
+__global__ __launch_bounds__(BS) void k_num_hash(Src src, Bins bins, int bin, OutC C, int32_t* err) {
+  constexpr int S = 1 << LGS, NW = BS / kWave;
+  using Item = typename Src::Item;
+  using Acc = typename Sr::Acc;
+  using V = typename Sr::V;
+  __shared__ int32_t s_keys[S];
+  __shared__ Acc s_vals[S];
+  __shared__ uint64_t s_sort[S / 2];
+  __shared__ Item s_item[BS];
+  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  __shared__ int32_t s_n;
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = L[r];
+    const int64_t o = C.rowptr[i];
+    const int64_t m = C.rowptr[i + 1] - o;
+    for (int x = threadIdx.x; x < S; x += BS) {
+      s_keys[x] = kEmptyKey;
+      s_vals[x] = Sr::ident();
+    }
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    Src s = src;
+    const int64_t nsrc = s.bind(i, 0, s.T);
+    auto body = [&](const Item& it, int64_t idx) {
+      bool fresh;
+      const uint32_t slot = hash_insert(s_keys, LGS, s.col(it, idx), &fresh);
+      if (slot != kHashFull) Sr::lds_acc(&s_vals[slot], s.template value<Sr>(it, idx));
+      else atomicOr(err, 2);
+    };
+    for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+    for (int x = threadIdx.x; x < S; x += BS) {
+      const int32_t k = s_keys[x];
+      if (k != kEmptyKey) {
+        const int pos = atomicAdd(&s_n, 1);
+        if (pos < S / 2) s_sort[pos] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)x;
+      }
+    }
+    __syncthreads();
+    int cnt = s_n;
+    if (threadIdx.x == 0 && cnt != m) atomicOr(err, 1);
+    cnt = cnt < S / 2 ? cnt : S / 2;
+    int M = 1;
+    while (M < cnt) M <<= 1;
+    for (int x = cnt + threadIdx.x; x < M; x += BS) s_sort[x] = ~0ull;
+    __syncthreads();
+    block_bitonic_sort<BS>(s_sort, M);
+    const int64_t wr = cnt < m ? cnt : m;
+    for (int x = threadIdx.x; x < wr; x += BS) {
+      const uint64_t e = s_sort[x];
+      C.col[o + x] = (int32_t)(e >> 32);
+      ((V*)C.val)[o + x] = Sr::out(s_vals[(uint32_t)e]);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- dense rows: column tiles ----------------------------------------------------------
+
+// Symbolic: a bitmap over up to 64 tiles (1M columns, 128 KB of LDS) per pass;
+// per-tile popcounts give the row's count and its per-tile output offsets
+// off2[h*(T+1) + t].
+template <class Src>
+__global__ __launch_bounds__(512) void k_sym_dense(Src src, Bins bins, int64_t ncols, int64_t* cnt_out,
+                                                   int32_t* off2) {
+  constexpr int BS = 512, NW = BS / kWave;
+  using Item = typename Src::Item;
+  __shared__ uint32_t s_bm[kSymTiles * kTileWords];
+  __shared__ Item s_item[BS];
+  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  __shared__ int32_t s_tcnt[kSymTiles];
+  __shared__ int32_t s_run;
+  const int32_t first = bins.start[kBinDense0];
+  const int32_t nd = bins.start[kNB - 1] + bins.count[kNB - 1] - first;
+  const int32_t* L = bins.list + first;
+  const int32_t T = src.T;
+  for (int h = blockIdx.x; h < nd; h += gridDim.x) {
+    const int64_t i = L[h];
+    int32_t* o2 = off2 + (int64_t)h * (T + 1);
+    int32_t run = 0;
+    for (int st = 0; st < T; st += kSymTiles) {
+      const int t1 = (st + kSymTiles) < T ? (st + kSymTiles) : T;
+      const int64_t c0 = (int64_t)st << kTileLog;
+      int64_t c1 = (int64_t)t1 << kTileLog;
+      c1 = c1 < ncols ? c1 : ncols;
+      const int nwords = (int)((c1 - c0 + 31) >> 5);
+      for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
+      __syncthreads();
+      Src s = src;
+      const int64_t nsrc = s.bind(i, st, t1);
+      auto body = [&](const Item& it, int64_t idx) {
+        const int32_t c = (int32_t)(s.col(it, idx) - c0);
+        atomicOr(&s_bm[c >> 5], 1u << (c & 31));
+      };
+      for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+      // one wavefront per tile, lanes over its 512 words
+      for (int tl = wave_id(); tl < t1 - st; tl += NW) {
+        int32_t c = 0;
+        for (int x = lane_id(); x < kTileWords; x += kWave) {
+          const int wx = tl * kTileWords + x;
+          if (wx < nwords) c += __popc(s_bm[wx]);
+        }
+        c = wave_sum(c);
+        if (lane_id() == 0) s_tcnt[tl] = c;
+      }
+      __syncthreads();
+      if (wave_id() == 0) {
+        const int ntl = t1 - st;
+        const int32_t v = lane_id() < ntl ? s_tcnt[lane_id()] : 0;
+        const int32_t inc = wave_incl_scan(v);
+        if (lane_id() < ntl) o2[st + lane_id()] = run + inc - v;
+        if (lane_id() == kWave - 1) s_run = run + inc;
+      }
+      __syncthreads();
+      run = s_run;
+    }
+    if (threadIdx.x == 0) {
+      o2[T] = run;
+      cnt_out[i] = run;
+    }
+    __syncthreads();
+  }
+}
+
+// Numeric: persistent workgroups take (dense row, tile) tasks from a global
+// counter; a tile's products are folded into a dense LDS accumulator of 16384
+// slots plus an occupancy bitmap; the bitmap is then compacted in column
+// order straight into C, and the touched slots are reset to the identity.
+template <class Sr, class Src, int BS>
+__global__ __launch_bounds__(BS) void k_num_dense(Src src, Bins bins, OutC C, const int32_t* off2,
+                                                  int32_t* task_ctr, int32_t* err) {
+  constexpr int NW = BS / kWave;
+  static_assert(BS >= kTileWords, "one compaction word per thread");
+  using Item = typename Src::Item;
+  using Acc = typename Sr::Acc;
+  using V = typename Sr::V;
+  __shared__ Acc s_acc[kTile];
+  __shared__ uint32_t s_bm[kTileWords];
+  __shared__ Item s_item[BS];
+  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  __shared__ int32_t s_task;
+  for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
+  for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
+  const int32_t first = bins.start[kBinDense0];
+  const int32_t nd = bins.start[kNB - 1] + bins.count[kNB - 1] - first;
+  const int32_t* L = bins.list + first;
+  const int32_t T = src.T;
+  const int64_t ntask = (int64_t)nd * T;
+  while (true) {
+    if (threadIdx.x == 0) s_task = atomicAdd(task_ctr, 1);
+    __syncthreads();
+    const int64_t task = s_task;
+    __syncthreads();
+    if (task >= ntask) break;
+    const int h = (int)(task / T), t = (int)(task % T);
+    const int32_t* o2 = off2 + (int64_t)h * (T + 1);
+    const int32_t lo = o2[t], hi = o2[t + 1];
+    if (hi == lo) continue;
+    const int64_t i = L[h];
+    const int64_t base = C.rowptr[i] + lo;
+    const int64_t c0 = (int64_t)t << kTileLog;
+    Src s = src;
+    const int64_t nsrc = s.bind(i, t, t + 1);
+    auto body = [&](const Item& it, int64_t idx) {
+      const int32_t c = (int32_t)(s.col(it, idx) - c0);
+      Sr::lds_acc(&s_acc[c], s.template value<Sr>(it, idx));
+      atomicOr(&s_bm[c >> 5], 1u << (c & 31));
+    };
+    for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+    uint32_t bits = threadIdx.x < kTileWords ? s_bm[threadIdx.x] : 0u;
+    int32_t tot;
+    int32_t pos = block_excl_scan<NW, int32_t>(__popc(bits), (int32_t*)s_wave, &tot);
+    if (threadIdx.x == 0 && tot != hi - lo) atomicOr(err, 1);
+    if (threadIdx.x < kTileWords) {
+      while (bits) {
+        const int b = __ffs((int)bits) - 1;
+        bits &= bits - 1u;
+        const int c = threadIdx.x * 32 + b;
+        if (pos < hi - lo) {
+          C.col[base + pos] = (int32_t)(c0 + c);
+          ((V*)C.val)[base + pos] = Sr::out(s_acc[c]);
+        }
+        s_acc[c] = Sr::ident();
+        ++pos;
+      }
+      s_bm[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace sg
