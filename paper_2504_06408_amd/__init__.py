@@ -63,6 +63,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise SgError(-7, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime with the same soname as the
+        # system one; load it first so the library binds to that one copy
+        # and the process has a single HIP runtime.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, ci = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
         SR, CSR = ctypes.POINTER(sg_semiring), ctypes.POINTER(sg_csr)
@@ -171,6 +175,18 @@ class Plan:
         arr = (sg_csr * n)()
         self.handle._rc(lib().sg_batch_results(self.ptr, arr))
         return list(arr)
+
+    def results_numpy(self):
+        """Host copies (rowptr, col, val) of every result: the nprob products,
+        then the ngroups merges."""
+        sid = self._keep[2].id
+        out = []
+        for r in self.results():
+            rp = _to_numpy(r.rowptr, r.nrows + 1, np.int64)
+            cl = _to_numpy(r.col, r.nnz, np.int32)
+            vl = _to_numpy(r.val, r.nnz, NP_DTYPE[sid])
+            out.append((rp, cl, vl))
+        return out
 
     def destroy(self):
         if self.ptr:
@@ -297,42 +313,37 @@ class Handle:
         self._rc(lib().sg_tune(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b), out_json.encode()))
 
 
+class _DevArray:
+    """A raw device range exposed through __cuda_array_interface__ so that
+    torch can wrap it without a copy."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 3}
+
+
+_TYPESTR = {np.dtype(np.int64): "<i8", np.dtype(np.int32): "<i4", np.dtype(np.float32): "<f4",
+            np.dtype(np.float64): "<f8", np.dtype(np.uint8): "|u1"}
+
+
+def _wrap(ptr, n: int, dtype, device="cuda"):
+    torch = _torch()
+    if n == 0 or not ptr:
+        return torch.empty(0, dtype={np.dtype(np.int64): torch.int64, np.dtype(np.int32): torch.int32,
+                                     np.dtype(np.float32): torch.float32, np.dtype(np.float64): torch.float64,
+                                     np.dtype(np.uint8): torch.uint8}[np.dtype(dtype)], device=device)
+    return torch.as_tensor(_DevArray(int(ptr), int(n), _TYPESTR[np.dtype(dtype)]), device=device)
+
+
+def _to_numpy(ptr, n: int, dtype) -> np.ndarray:
+    """Host copy of n elements at device address ptr."""
+    if n == 0 or not ptr:
+        return np.empty(0, dtype=dtype)
+    return _wrap(ptr, n, dtype).cpu().numpy()
+
+
 def view_results(res: sg_csr, sid: int, device="cuda") -> DeviceCSR:
     """Wrap a result descriptor returned by Plan.results() as torch tensors
-    (views of the plan's pool; valid until the plan is executed again or
-    destroyed)."""
-    torch = _torch()
-
-    def wrap(ptr, n, dtype):
-        if n == 0 or not ptr:
-            return torch.empty(0, dtype=dtype, device=device)
-        return _from_ptr(ptr, n, dtype, device)
-
-    rp = wrap(res.rowptr, res.nrows + 1, torch.int64)
-    cl = wrap(res.col, res.nnz, torch.int32)
-    vl = wrap(res.val, res.nnz, _torch_dtype(sid))
-    return DeviceCSR(res.nrows, res.ncols, rp, cl, vl)
-
-
-def _from_ptr(ptr: int, n: int, dtype, device):
-    """Copy n elements at device address ptr into a new tensor."""
-    torch = _torch()
-    out = torch.empty(n, dtype=dtype, device=device)
-    nbytes = n * out.element_size()
-    hip = _hip()
-    rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes), 3)
-    if rc != 0:
-        raise SgError(-7, f"hipMemcpy failed ({rc})")
-    return out
-
-
-_hip_lib = None
-
-
-def _hip():
-    global _hip_lib
-    if _hip_lib is None:
-        _hip_lib = ctypes.CDLL("libamdhip64.so")
-        _hip_lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-        _hip_lib.hipMemcpy.restype = ctypes.c_int
-    return _hip_lib
+    (views of the plan's pool, no copy; valid until the plan is executed
+    again or destroyed)."""
+    return DeviceCSR(res.nrows, res.ncols, _wrap(res.rowptr, res.nrows + 1, np.int64, device),
+                     _wrap(res.col, res.nnz, np.int32, device), _wrap(res.val, res.nnz, NP_DTYPE[sid], device))

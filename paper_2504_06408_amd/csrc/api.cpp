@@ -111,6 +111,7 @@ sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const i
   plan.bins.list = list;
   plan.bins.start = bin_start;
   plan.bins.count = bin_count;
+  plan.bins.nd_cap = plan.ndense();
   return SG_OK;
 }
 
@@ -215,7 +216,7 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   const int32_t nd = plan.ndense();
   int32_t* off2 = nullptr;
   if (nd > 0) {
-    if (!r.merge && r.T > 1) {
+    if (r.mode == kModeProduct && r.T > 1) {
       SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
       r.rp2 = (const int32_t*)h->rp2_buf.p;
       mk.mark(kPhSymBounds, 1);
@@ -261,7 +262,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   const int32_t nd = plan.ndense();
   const bool cached = h->cache_valid && h->cache_key == key && h->cache_T == r.T && h->cache_nd == nd;
   if (nd > 0) {
-    if (!r.merge && r.T > 1) {
+    if (r.mode == kModeProduct && r.T > 1) {
       if (!cached) {
         SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
         launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
@@ -282,7 +283,11 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.C = OutC{C->rowptr, C->col, C->val};
   c.off2 = (const int32_t*)h->off2_buf.p;
   c.err = h->d_flags;
-  c.task_ctr = h->d_flags + 1;
+  c.task_ctr = h->d_flags + 8;
+  c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;
+  SG_HIP(h, h->task_buf.ensure(sizeof(Task) * 2 * (size_t)c.task_cap));
+  c.tasks = (Task*)h->task_buf.p;
+  c.tile_min = h->tile_min;
   c.cus = h->cus;
   c.comp_dense = pol.comp_mode != kCompNone;
   switch (sr->id) {
@@ -327,6 +332,13 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
     const long long x = std::strtoll(value, &end, 10);
     if (!end || *end || x < 0 || x > kHashCap) return sg_fail(h, SG_ERR_INVALID, "hash_max_products must be in [0, 4096]");
     h->hash_max = x;
+  } else if (n == "dense_tile_min") {
+    char* end = nullptr;
+    const long long x = std::strtoll(value, &end, 10);
+    if (!end || *end || x < 1 || x > kRangeCap)
+      return sg_fail(h, SG_ERR_INVALID, "dense_tile_min must be in [1, 2048]");
+    h->tile_min = (int32_t)x;
+    return SG_OK;
   } else if (n == "force_path") {
     if (v == "auto") h->force = kForceAuto;
     else if (v == "small") h->force = kForceSmall;
@@ -411,6 +423,7 @@ sg_status sg_handle_destroy(sg_handle* h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   h->ws.release();
+  h->task_buf.release();
   h->rp2_buf.release();
   h->off2_buf.release();
   h->parts_buf.release();
@@ -517,7 +530,7 @@ sg_status sg_spgemm_merge_symbolic(sg_handle* h, int nparts, const sg_csr* parts
   }
   SG_TRY(upload_parts(h, nparts, parts, st));
   RowSource r{};
-  r.merge = 1;
+  r.mode = kModeMerge;
   r.parts = (const PartDesc*)h->parts_buf.p;
   r.nparts = nparts;
   r.nrows = n;
@@ -543,7 +556,7 @@ sg_status sg_spgemm_merge_numeric(sg_handle* h, const sg_semiring* sr, int npart
   for (int s = 0; s < nparts; ++s) SG_TRY(validate_input(h, &parts[s], "part", st));
   SG_TRY(upload_parts(h, nparts, parts, st));
   RowSource r{};
-  r.merge = 1;
+  r.mode = kModeMerge;
   r.parts = (const PartDesc*)h->parts_buf.p;
   r.nparts = nparts;
   r.nrows = C->nrows;

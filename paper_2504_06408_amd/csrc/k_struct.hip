@@ -109,58 +109,58 @@ __global__ __launch_bounds__(kScanBS) void k_scan_apply(int64_t* a, int64_t n, c
 }
 
 
-template <class Src>
-void analyze_src(const Src& s, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p,
-                 uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
-                 int32_t* list, int64_t* cnt_out, hipStream_t st) {
+template <class Rows>
+void analyze_rows(const Rows& rows, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p,
+                  uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                  int32_t* list, int64_t* cnt_out, hipStream_t st) {
   const int64_t nblk = analyze_blocks(r.nrows);
-  hipLaunchKernelGGL((k_analyze<Src, kAnaBS>), dim3(nblk), dim3(kAnaBS), 0, st, s, r.nrows, pol, c_rowptr, p, bin,
-                     hist, cnt_out);
+  hipLaunchKernelGGL((k_analyze<Rows, kAnaBS>), dim3(nblk), dim3(kAnaBS), 0, st, rows, r.nrows, pol, c_rowptr, p,
+                     bin, hist, cnt_out);
   hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, hist, (int32_t)nblk, blk_off, bin_start, bin_count);
   hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, list);
 }
 
-template <class Src, int LGS, int BS>
-void sym_hash_one(const Src& s, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
+template <class Rows, int LGS, int BS>
+void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
   const int n = plan.count[bin];
   if (n == 0) return;
-  auto k = k_sym_hash<Src, LGS, BS>;
+  auto k = k_sym_hash<Rows, LGS, BS>;
   static int occ = occupancy(k, BS);
-  hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, s, plan.bins, bin, cnt_out);
+  hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, rows, plan.bins, bin, cnt_out);
 }
 
-template <class Src>
-void sym_dense_src(const Src& s, const BinPlan& plan, int64_t ncols, int64_t* cnt_out, int32_t* off2, int cus,
-                   hipStream_t st) {
+template <class Rows>
+void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
+                    hipStream_t st) {
   const int nd = plan.ndense();
   if (nd == 0) return;
-  auto k = k_sym_dense<Src>;
+  auto k = k_sym_dense<Rows>;
   static int occ = occupancy(k, 512);
-  hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(512), 0, st, s, plan.bins, ncols, cnt_out, off2);
+  hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(512), 0, st, rows, plan.bins, cnt_out, off2);
 }
 
-template <class Src>
-void symbolic_src(const Src& s, const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
-                  const Marks& marks, hipStream_t st) {
+template <class Rows>
+void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
+                   const Marks& marks, hipStream_t st) {
   marks.mark(kPhSymSmall, 1);
   if (plan.count[kBinSmall]) {
-    auto k = k_sym_small<Src>;
+    auto k = k_sym_small<Rows>;
     static int occ = occupancy(k, 256);
-    hipLaunchKernelGGL(k, dim3(grid_for(plan.count[kBinSmall], 4, cus * occ * 4)), dim3(256), 0, st, s, plan.bins,
-                       kBinSmall, cnt_out);
+    hipLaunchKernelGGL(k, dim3(grid_for(plan.count[kBinSmall], 4, cus * occ * 4)), dim3(256), 0, st, rows,
+                       plan.bins, kBinSmall, cnt_out);
   }
   marks.mark(kPhSymSmall, 0);
   marks.mark(kPhSymHash, 1);
   // hash bins hold tables of 2^8 .. 2^13 keys (symbolic tables start at 256)
-  sym_hash_one<Src, 8, 256>(s, plan, kBinHash0 + 1, cnt_out, cus, st);
-  sym_hash_one<Src, 9, 256>(s, plan, kBinHash0 + 2, cnt_out, cus, st);
-  sym_hash_one<Src, 10, 256>(s, plan, kBinHash0 + 3, cnt_out, cus, st);
-  sym_hash_one<Src, 11, 512>(s, plan, kBinHash0 + 4, cnt_out, cus, st);
-  sym_hash_one<Src, 12, 512>(s, plan, kBinHash0 + 5, cnt_out, cus, st);
-  sym_hash_one<Src, 13, 512>(s, plan, kBinHash0 + 6, cnt_out, cus, st);
+  sym_hash_one<Rows, 8, 256>(rows, plan, kBinHash0 + 1, cnt_out, cus, st);
+  sym_hash_one<Rows, 9, 256>(rows, plan, kBinHash0 + 2, cnt_out, cus, st);
+  sym_hash_one<Rows, 10, 256>(rows, plan, kBinHash0 + 3, cnt_out, cus, st);
+  sym_hash_one<Rows, 11, 512>(rows, plan, kBinHash0 + 4, cnt_out, cus, st);
+  sym_hash_one<Rows, 12, 512>(rows, plan, kBinHash0 + 5, cnt_out, cus, st);
+  sym_hash_one<Rows, 13, 512>(rows, plan, kBinHash0 + 6, cnt_out, cus, st);
   marks.mark(kPhSymHash, 0);
   marks.mark(kPhSymDense, 1);
-  sym_dense_src(s, plan, r.ncols, cnt_out, off2, cus, st);
+  sym_dense_rows(rows, plan, cnt_out, off2, cus, st);
   marks.mark(kPhSymDense, 0);
 }
 
@@ -190,12 +190,9 @@ int64_t analyze_blocks(int64_t nrows) { return (nrows + kAnaBS - 1) / kAnaBS; }
 void launch_analyze(const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p, uint8_t* bin,
                     int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count, int32_t* list,
                     int64_t* cnt_out, hipStream_t st) {
-  if (r.merge)
-    analyze_src(make_merge_src<uint8_t>(r), r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count, list,
-                cnt_out, st);
-  else
-    analyze_src(make_spgemm_src<uint8_t, false>(r), r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count,
-                list, cnt_out, st);
+  with_rows<uint8_t, false>(r, [&](const auto& rows) {
+    analyze_rows(rows, r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count, list, cnt_out, st);
+  });
 }
 
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,
@@ -206,14 +203,12 @@ void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows
 
 void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                      const Marks& marks, hipStream_t st) {
-  if (r.merge) symbolic_src(make_merge_src<uint8_t>(r), r, plan, cnt_out, off2, cus, marks, st);
-  else symbolic_src(make_spgemm_src<uint8_t, false>(r), r, plan, cnt_out, off2, cus, marks, st);
+  with_rows<uint8_t, false>(r, [&](const auto& rows) { symbolic_rows(rows, plan, cnt_out, off2, cus, marks, st); });
 }
 
 void launch_symbolic_dense(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                            hipStream_t st) {
-  if (r.merge) sym_dense_src(make_merge_src<uint8_t>(r), plan, r.ncols, cnt_out, off2, cus, st);
-  else sym_dense_src(make_spgemm_src<uint8_t, false>(r), plan, r.ncols, cnt_out, off2, cus, st);
+  with_rows<uint8_t, false>(r, [&](const auto& rows) { sym_dense_rows(rows, plan, cnt_out, off2, cus, st); });
 }
 
 int64_t scan_partials_len(int64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }

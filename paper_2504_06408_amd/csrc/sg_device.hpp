@@ -145,6 +145,81 @@ SG_DEV void block_bitonic_sort(uint64_t* buf, int n) {
   }
 }
 
+// Stable LSD radix sort of n (<= NMAX) 64-bit items in LDS by the key bits
+// [32, 32 + kbits) (8-bit digits) by a workgroup of BS >= 256 threads.  Each
+// wavefront owns a contiguous chunk of the items and ranks 64 of them per
+// round: lanes with the same digit are found with eight ballots, and a
+// per-(wave, digit) counter in LDS carries the running count, so equal digits
+// keep their order.  A 256-digit scan then gives every (wave, digit) its
+// output offset.  buf and tmp hold NMAX items each; s_hist has NW*256 ints,
+// s_wt 4 ints.  Returns the buffer that holds the sorted items.
+template <int BS, int NMAX>
+SG_DEV uint64_t* block_radix_sort_hi(uint64_t* buf, uint64_t* tmp, int n, int kbits, int32_t* s_hist,
+                                     int32_t* s_wt) {
+  static_assert(BS >= 256, "one thread per digit");
+  constexpr int NW = BS / kWave;
+  constexpr int RPL = (NMAX + BS - 1) / BS;
+  const int w = wave_id(), l = lane_id();
+  const int per_wave = (n + NW - 1) / NW;
+  const int c0 = w * per_wave;
+  const int c1 = (c0 + per_wave) < n ? (c0 + per_wave) : n;
+  for (int shift = 32; shift < 32 + kbits; shift += 8) {
+    for (int x = threadIdx.x; x < NW * 256; x += BS) s_hist[x] = 0;
+    __syncthreads();
+    uint64_t item[RPL];
+    int rank[RPL], dig[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int x = c0 + r * kWave + l;
+      const bool valid = x < c1;
+      const uint64_t v = valid ? buf[x] : 0ull;
+      const int d = valid ? (int)((v >> shift) & 255u) : 0;
+      unsigned long long m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool on = (d >> b) & 1;
+        const unsigned long long bb = __ballot(on);
+        m &= on ? bb : ~bb;
+      }
+      const unsigned long long below = m & lanes_below();
+      int32_t* slot = s_hist + w * 256 + d;
+      const int old = valid ? *slot : 0;
+      if (valid && below == 0) *slot = old + __popcll(m);
+      item[r] = v;
+      rank[r] = old + __popcll(below);
+      dig[r] = valid ? d : -1;
+    }
+    __syncthreads();
+    // waves 0..3 (threads 0..255) own one digit each
+    int tot = 0, inc = 0;
+    if (threadIdx.x < 256) {
+      for (int q = 0; q < NW; ++q) tot += s_hist[q * 256 + threadIdx.x];
+      inc = wave_incl_scan(tot);
+      if (l == kWave - 1) s_wt[w] = inc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      const int d = threadIdx.x;
+      int run = inc - tot;
+      for (int q = 0; q < w; ++q) run += s_wt[q];
+      for (int q = 0; q < NW; ++q) {
+        const int t = s_hist[q * 256 + d];
+        s_hist[q * 256 + d] = run;
+        run += t;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+      if (dig[r] >= 0) tmp[s_hist[w * 256 + dig[r]] + rank[r]] = item[r];
+    __syncthreads();
+    uint64_t* t = buf;
+    buf = tmp;
+    tmp = t;
+  }
+  return buf;
+}
+
 // Ascending bitonic sort across the 64 lanes of a wavefront of (key, payload)
 // pairs, keys compared as signed int32.
 template <class P>

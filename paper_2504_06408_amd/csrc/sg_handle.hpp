@@ -71,11 +71,13 @@ struct sg_handle {
   SgBuf ws;                  // per call
   SgBuf rp2_buf, off2_buf;   // dense-path data kept from symbolic for numeric
   SgBuf parts_buf;           // device table of merge parts
+  SgBuf task_buf;            // dense-row task lists of the numeric pass
+  int32_t tile_min = sg::kTileMinDefault;
   std::vector<sg::PartDesc> parts_host;
   bool cache_valid = false;
   SgCacheKey cache_key{};
   int32_t cache_T = 0, cache_nd = 0;
-  int32_t* d_flags = nullptr;  // [0] consistency error, [1] task counter, [2] validation, [3..] batch
+  int32_t* d_flags = nullptr;  // [0] consistency error, [2] validation, [8..11] task counters
   int64_t* h_pin = nullptr;    // pinned readback area (>= 256 int64)
 };
 

@@ -118,6 +118,7 @@ struct SpgemmSrc {
   const V* b_val;
   const int32_t* rp2;  // per B row: T+1 row-local offsets where tile t starts
   int32_t T;           // column tiles of B
+  int64_t ncols;       // columns of B
   int64_t a0;
   int32_t t0, t1;
 
@@ -223,13 +224,111 @@ struct MergeSrc {
   }
 };
 
+// ---- row sets ---------------------------------------------------------------------
+//
+// Kernels see a set of "global" rows r; Rows::get maps r to the source of the
+// problem that owns it and the row's local index.  A single product or merge
+// is OneRows (r is the local row); a batch concatenates the rows of all its
+// products (TableRows) or merges (MergeTableRows) and finds the owner by a
+// binary search over the problems' first rows.  Outputs are indexed by r.
+
+template <class S>
+struct OneRows {
+  using Src = S;
+  S src;
+  int32_t Tmax;
+  SG_DEV void get(int64_t r, S& s, int64_t& i) const {
+    s = src;
+    i = r;
+  }
+};
+
+// One product of a batch (device table entry).
+struct ProbDesc {
+  const int64_t* a_rowptr;
+  const int32_t* a_col;
+  const void* a_val;
+  const int64_t* b_rowptr;
+  const int32_t* b_col;
+  const void* b_val;
+  const int32_t* rp2;
+  int64_t ncols;
+  int32_t T;
+  int32_t pad;
+};
+
+// One merge of a batch: its parts' descriptors live in a parts table.
+struct GroupDesc {
+  const PartDesc* parts;
+  int64_t ncols;
+  int32_t nparts;
+  int32_t T;
+};
+
+SG_DEV int owner_of(const int64_t* rbase, int32_t n, int64_t r) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rbase[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class V, bool kVals>
+struct TableRows {
+  using Src = SpgemmSrc<V, kVals>;
+  const ProbDesc* probs;
+  const int64_t* rbase;  // first global row of each product, ascending
+  int32_t nprob;
+  int32_t Tmax;
+  SG_DEV void get(int64_t r, Src& s, int64_t& i) const {
+    const int q = owner_of(rbase, nprob, r);
+    const ProbDesc& d = probs[q];
+    s.a_rowptr = d.a_rowptr;
+    s.a_col = d.a_col;
+    s.a_val = (const V*)d.a_val;
+    s.b_rowptr = d.b_rowptr;
+    s.b_col = d.b_col;
+    s.b_val = (const V*)d.b_val;
+    s.rp2 = d.rp2;
+    s.T = d.T;
+    s.ncols = d.ncols;
+    i = r - rbase[q];
+  }
+};
+
+template <class V>
+struct MergeTableRows {
+  using Src = MergeSrc<V>;
+  const GroupDesc* groups;
+  const int64_t* rbase;
+  int32_t ngroups;
+  int32_t Tmax;
+  SG_DEV void get(int64_t r, Src& s, int64_t& i) const {
+    const int q = owner_of(rbase, ngroups, r);
+    const GroupDesc& g = groups[q];
+    s.parts = g.parts;
+    s.nparts = g.nparts;
+    s.T = g.T;
+    s.ncols = g.ncols;
+    i = r - rbase[q];
+  }
+};
+
 // ---- shared argument blocks ---------------------------------------------------
 
 struct Bins {
   const int32_t* list;   // rows of all bins, bin after bin
   const int32_t* start;  // [kNB]
   const int32_t* count;  // [kNB]
+  int32_t nd_cap;        // dense rows the per-tile offset array has room for
 };
+
+SG_DEV int32_t dense_rows(const Bins& bins) {
+  const int32_t nd = bins.start[kNB - 1] + bins.count[kNB - 1] - bins.start[kBinDense0];
+  return nd < bins.nd_cap ? nd : bins.nd_cap;
+}
 
 struct OutC {
   const int64_t* rowptr;
@@ -239,17 +338,20 @@ struct OutC {
 
 // ---- analysis and binning ---------------------------------------------------------
 
-template <class Src, int BS>
-__global__ __launch_bounds__(BS) void k_analyze(Src src, int64_t nrows, Policy pol, const int64_t* c_rowptr,
+template <class Rows, int BS>
+__global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy pol, const int64_t* c_rowptr,
                                                   int64_t* p_out, uint8_t* bin_out, int32_t* hist,
                                                   int64_t* cnt_out) {
+  using Src = typename Rows::Src;
   __shared__ int32_t s_hist[kNB];
   for (int b = threadIdx.x; b < kNB; b += BS) s_hist[b] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   const bool valid = i < nrows;
-  Src s = src;
-  const int64_t nsrc = valid ? s.bind(i, 0, s.T) : 0;
+  Src s{};
+  int64_t li = 0;
+  if (valid) rows.get(i, s, li);
+  const int64_t nsrc = valid ? s.bind(li, 0, s.T) : 0;
   int64_t p = 0;
   const bool heavy = nsrc > 32;
   if (!heavy) {
@@ -265,8 +367,10 @@ __global__ __launch_bounds__(BS) void k_analyze(Src src, int64_t nrows, Policy p
     const int leader = __ffsll((long long)hmask) - 1;
     hmask &= hmask - 1;
     const int64_t ri = shfl(i, leader);
-    Src t = src;
-    const int64_t n2 = t.bind(ri, 0, t.T);
+    Src t{};
+    int64_t tl;
+    rows.get(ri, t, tl);
+    const int64_t n2 = t.bind(tl, 0, t.T);
     int64_t part = 0;
     for (int64_t j = lane_id(); j < n2; j += kWave) {
       typename Src::Item it;
@@ -371,16 +475,19 @@ SG_DEV int wave_gather_products(Src& s, int64_t nsrc, int32_t& key, typename Sr:
   return base;
 }
 
-template <class Src>
-__global__ __launch_bounds__(256) void k_sym_small(Src src, Bins bins, int bin, int64_t* cnt_out) {
+template <class Rows>
+__global__ __launch_bounds__(256) void k_sym_small(Rows rows, Bins bins, int bin, int64_t* cnt_out) {
+  using Src = typename Rows::Src;
   const int n = bins.count[bin];
   const int32_t* L = bins.list + bins.start[bin];
   const int w0 = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
   const int nw = gridDim.x * 4;
   for (int r = w0; r < n; r += nw) {
     const int64_t i = L[r];
-    Src s = src;
-    const int64_t nsrc = s.bind(i, 0, s.T);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
     int32_t key;
     uint8_t dummy;
     wave_gather_products<SrBool, Src, false>(s, nsrc, key, dummy);
@@ -392,8 +499,9 @@ __global__ __launch_bounds__(256) void k_sym_small(Src src, Bins bins, int bin, 
   }
 }
 
-template <class Sr, class Src>
-__global__ __launch_bounds__(256) void k_num_small(Src src, Bins bins, int bin, OutC C, int32_t* err) {
+template <class Sr, class Rows>
+__global__ __launch_bounds__(256) void k_num_small(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
+  using Src = typename Rows::Src;
   using Acc = typename Sr::Acc;
   using V = typename Sr::V;
   const int n = bins.count[bin];
@@ -402,8 +510,10 @@ __global__ __launch_bounds__(256) void k_num_small(Src src, Bins bins, int bin, 
   const int nw = gridDim.x * 4;
   for (int r = w0; r < n; r += nw) {
     const int64_t i = L[r];
-    Src s = src;
-    const int64_t nsrc = s.bind(i, 0, s.T);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
     int32_t key;
     Acc acc;
     wave_gather_products<Sr, Src, true>(s, nsrc, key, acc);
@@ -434,8 +544,9 @@ __global__ __launch_bounds__(256) void k_num_small(Src src, Bins bins, int bin, 
 
 // ---- hash rows: one workgroup per row, LDS open addressing --------------------------
 
-template <class Src, int LGS, int BS>
-__global__ __launch_bounds__(BS) void k_sym_hash(Src src, Bins bins, int bin, int64_t* cnt_out) {
+template <class Rows, int LGS, int BS>
+__global__ __launch_bounds__(BS) void k_sym_hash(Rows rows, Bins bins, int bin, int64_t* cnt_out) {
+  using Src = typename Rows::Src;
   constexpr int S = 1 << LGS, NW = BS / kWave;
   using Item = typename Src::Item;
   __shared__ int32_t s_keys[S];
@@ -447,8 +558,10 @@ __global__ __launch_bounds__(BS) void k_sym_hash(Src src, Bins bins, int bin, in
     const int64_t i = L[r];
     for (int x = threadIdx.x; x < S; x += BS) s_keys[x] = kEmptyKey;
     __syncthreads();
-    Src s = src;
-    const int64_t nsrc = s.bind(i, 0, s.T);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
     int64_t fresh_cnt = 0;
     auto body = [&](const Item& it, int64_t idx) {
       bool fresh;
@@ -461,62 +574,97 @@ __global__ __launch_bounds__(BS) void k_sym_hash(Src src, Bins bins, int bin, in
   }
 }
 
+// LDS of one hash task: a table of 2^LGS keys and accumulators, the sort
+// buffer, the flattened iterator's per-source arrays and radix-sort counters.
 template <class Sr, class Src, int LGS, int BS>
-__global__ __launch_bounds__(BS) void k_num_hash(Src src, Bins bins, int bin, OutC C, int32_t* err) {
-  constexpr int S = 1 << LGS, NW = BS / kWave;
+struct HashSmem {
+  static constexpr int S = 1 << LGS, NW = BS / kWave;
+  int32_t keys[S];
+  typename Sr::Acc vals[S];
+  uint64_t sort[S / 2];
+  typename Src::Item item[BS];
+  int64_t start[BS], off[BS], wave[NW];
+  int32_t hist[(S >= 1024) ? NW * 256 : 1];
+  int32_t wt[4];
+  int32_t n;
+};
+
+// One hash task: the products of local row li restricted to column tiles
+// [t0, t1) go into an LDS hash table (find-or-claim the column's slot, then
+// an LDS atomic (+)); the occupied slots are compacted, sorted by column
+// (radix sort above 256 entries, bitonic below) and written to
+// C.col/C.val[o .. o+m).  Contains barriers; the whole workgroup calls it.
+template <class Sr, class Src, int LGS, int BS>
+SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_t t0, int32_t t1, int64_t o,
+                      int64_t m, OutC C, int32_t* err) {
+  constexpr int S = 1 << LGS;
   using Item = typename Src::Item;
-  using Acc = typename Sr::Acc;
   using V = typename Sr::V;
-  __shared__ int32_t s_keys[S];
-  __shared__ Acc s_vals[S];
-  __shared__ uint64_t s_sort[S / 2];
-  __shared__ Item s_item[BS];
-  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
-  __shared__ int32_t s_n;
+  for (int x = threadIdx.x; x < S; x += BS) {
+    sm.keys[x] = kEmptyKey;
+    sm.vals[x] = Sr::ident();
+  }
+  if (threadIdx.x == 0) sm.n = 0;
+  __syncthreads();
+  const int64_t nsrc = s.bind(li, t0, t1);
+  auto body = [&](const Item& it, int64_t idx) {
+    bool fresh;
+    const uint32_t slot = hash_insert(sm.keys, LGS, s.col(it, idx), &fresh);
+    if (slot != kHashFull) Sr::lds_acc(&sm.vals[slot], s.template value<Sr>(it, idx));
+    else atomicOr(err, 2);
+  };
+  for_each_product<BS>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, body);
+  const int64_t key_base = (int64_t)t0 << kTileLog;
+  for (int x = threadIdx.x; x < S; x += BS) {
+    const int32_t k = sm.keys[x];
+    if (k != kEmptyKey) {
+      const int pos = atomicAdd(&sm.n, 1);
+      if (pos < S / 2) sm.sort[pos] = ((uint64_t)(uint32_t)(k - key_base) << 32) | (uint32_t)x;
+    }
+  }
+  __syncthreads();
+  int cnt = sm.n;
+  if (threadIdx.x == 0 && cnt != m) atomicOr(err, 1);
+  cnt = cnt < S / 2 ? cnt : S / 2;
+  const uint64_t* sorted = sm.sort;
+  if (cnt > 256) {
+    // radix sort on the bits of (column - key_base); the key table is free
+    // now and serves as the second buffer
+    int64_t hi = (int64_t)t1 << kTileLog;
+    hi = hi < s.ncols ? hi : s.ncols;
+    const int64_t width = hi - key_base;
+    const int kbits = width > 1 ? 32 - __clz((int)(width - 1)) : 1;
+    sorted = block_radix_sort_hi<BS, S / 2>(sm.sort, (uint64_t*)sm.keys, cnt, kbits, sm.hist, sm.wt);
+  } else {
+    int M = 1;
+    while (M < cnt) M <<= 1;
+    for (int x = cnt + threadIdx.x; x < M; x += BS) sm.sort[x] = ~0ull;
+    __syncthreads();
+    block_bitonic_sort<BS>(sm.sort, M);
+  }
+  const int64_t wr = cnt < m ? cnt : m;
+  for (int x = threadIdx.x; x < wr; x += BS) {
+    const uint64_t e = sorted[x];
+    C.col[o + x] = (int32_t)((int64_t)(e >> 32) + key_base);
+    ((V*)C.val)[o + x] = Sr::out(sm.vals[(uint32_t)e]);
+  }
+  __syncthreads();
+}
+
+template <class Sr, class Rows, int LGS, int BS>
+__global__ __launch_bounds__(BS) void k_num_hash(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
+  using Src = typename Rows::Src;
+  __shared__ HashSmem<Sr, Src, LGS, BS> sm;
   const int n = bins.count[bin];
   const int32_t* L = bins.list + bins.start[bin];
   for (int r = blockIdx.x; r < n; r += gridDim.x) {
     const int64_t i = L[r];
     const int64_t o = C.rowptr[i];
     const int64_t m = C.rowptr[i + 1] - o;
-    for (int x = threadIdx.x; x < S; x += BS) {
-      s_keys[x] = kEmptyKey;
-      s_vals[x] = Sr::ident();
-    }
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    Src s = src;
-    const int64_t nsrc = s.bind(i, 0, s.T);
-    auto body = [&](const Item& it, int64_t idx) {
-      bool fresh;
-      const uint32_t slot = hash_insert(s_keys, LGS, s.col(it, idx), &fresh);
-      if (slot != kHashFull) Sr::lds_acc(&s_vals[slot], s.template value<Sr>(it, idx));
-      else atomicOr(err, 2);
-    };
-    for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
-    for (int x = threadIdx.x; x < S; x += BS) {
-      const int32_t k = s_keys[x];
-      if (k != kEmptyKey) {
-        const int pos = atomicAdd(&s_n, 1);
-        if (pos < S / 2) s_sort[pos] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)x;
-      }
-    }
-    __syncthreads();
-    int cnt = s_n;
-    if (threadIdx.x == 0 && cnt != m) atomicOr(err, 1);
-    cnt = cnt < S / 2 ? cnt : S / 2;
-    int M = 1;
-    while (M < cnt) M <<= 1;
-    for (int x = cnt + threadIdx.x; x < M; x += BS) s_sort[x] = ~0ull;
-    __syncthreads();
-    block_bitonic_sort<BS>(s_sort, M);
-    const int64_t wr = cnt < m ? cnt : m;
-    for (int x = threadIdx.x; x < wr; x += BS) {
-      const uint64_t e = s_sort[x];
-      C.col[o + x] = (int32_t)(e >> 32);
-      ((V*)C.val)[o + x] = Sr::out(s_vals[(uint32_t)e]);
-    }
-    __syncthreads();
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    hash_task<Sr, Src, LGS, BS>(sm, s, li, 0, s.T, o, m, C, err);
   }
 }
 
@@ -524,10 +672,11 @@ __global__ __launch_bounds__(BS) void k_num_hash(Src src, Bins bins, int bin, Ou
 
 // Symbolic: a bitmap over up to 64 tiles (1M columns, 128 KB of LDS) per pass;
 // per-tile popcounts give the row's count and its per-tile output offsets
-// off2[h*(T+1) + t].
-template <class Src>
-__global__ __launch_bounds__(512) void k_sym_dense(Src src, Bins bins, int64_t ncols, int64_t* cnt_out,
-                                                   int32_t* off2) {
+// off2[h*(Tmax+1) + t] (t = 0..Tmax; entries past the row's own T repeat the
+// total).
+template <class Rows>
+__global__ __launch_bounds__(512) void k_sym_dense(Rows rows, Bins bins, int64_t* cnt_out, int32_t* off2) {
+  using Src = typename Rows::Src;
   constexpr int BS = 512, NW = BS / kWave;
   using Item = typename Src::Item;
   __shared__ uint32_t s_bm[kSymTiles * kTileWords];
@@ -536,12 +685,17 @@ __global__ __launch_bounds__(512) void k_sym_dense(Src src, Bins bins, int64_t n
   __shared__ int32_t s_tcnt[kSymTiles];
   __shared__ int32_t s_run;
   const int32_t first = bins.start[kBinDense0];
-  const int32_t nd = bins.start[kNB - 1] + bins.count[kNB - 1] - first;
+  const int32_t nd = dense_rows(bins);
   const int32_t* L = bins.list + first;
-  const int32_t T = src.T;
+  const int32_t Tmax = rows.Tmax;
   for (int h = blockIdx.x; h < nd; h += gridDim.x) {
     const int64_t i = L[h];
-    int32_t* o2 = off2 + (int64_t)h * (T + 1);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int32_t T = s.T;
+    const int64_t ncols = s.ncols;
+    int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
     int32_t run = 0;
     for (int st = 0; st < T; st += kSymTiles) {
       const int t1 = (st + kSymTiles) < T ? (st + kSymTiles) : T;
@@ -551,8 +705,7 @@ __global__ __launch_bounds__(512) void k_sym_dense(Src src, Bins bins, int64_t n
       const int nwords = (int)((c1 - c0 + 31) >> 5);
       for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
       __syncthreads();
-      Src s = src;
-      const int64_t nsrc = s.bind(i, st, t1);
+      const int64_t nsrc = s.bind(li, st, t1);
       auto body = [&](const Item& it, int64_t idx) {
         const int32_t c = (int32_t)(s.col(it, idx) - c0);
         atomicOr(&s_bm[c >> 5], 1u << (c & 31));
@@ -579,21 +732,60 @@ __global__ __launch_bounds__(512) void k_sym_dense(Src src, Bins bins, int64_t n
       __syncthreads();
       run = s_run;
     }
-    if (threadIdx.x == 0) {
-      o2[T] = run;
-      cnt_out[i] = run;
-    }
+    for (int t = T + threadIdx.x; t <= Tmax; t += BS) o2[t] = run;
+    if (threadIdx.x == 0) cnt_out[i] = run;
     __syncthreads();
   }
 }
 
-// Numeric: persistent workgroups take (dense row, tile) tasks from a global
-// counter; a tile's products are folded into a dense LDS accumulator of 16384
-// slots plus an occupancy bitmap; the bitmap is then compacted in column
-// order straight into C, and the touched slots are reset to the identity.
-template <class Sr, class Src, int BS>
-__global__ __launch_bounds__(BS) void k_num_dense(Src src, Bins bins, OutC C, const int32_t* off2,
-                                                  int32_t* task_ctr, int32_t* err) {
+// Numeric dense-row work is cut into tasks from the symbolic pass's per-tile
+// counts: a tile holding at least tile_min entries becomes a dense-tile task
+// (dense LDS accumulator, written in column order without a sort); runs of
+// sparser tiles are grouped into range tasks of at most range_cap entries
+// (LDS hash + radix sort).  One thread per dense row appends its tasks to the
+// two lists; ctr[0], ctr[1] count them.
+struct Task {
+  int32_t h, t0, t1;
+};
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t tile_min,
+                                                    int32_t range_cap, Task* tiles, Task* ranges, int32_t* ctr) {
+  const int32_t nd = dense_rows(bins);
+  for (int h = blockIdx.x * BS + threadIdx.x; h < nd; h += gridDim.x * BS) {
+    const int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
+    int32_t r0 = -1, rlast = -1, racc = 0;
+    for (int t = 0; t < Tmax; ++t) {
+      const int32_t c = o2[t + 1] - o2[t];
+      if (c == 0) continue;
+      if (c >= tile_min) {
+        if (r0 >= 0) ranges[atomicAdd(&ctr[1], 1)] = Task{h, r0, rlast + 1};
+        r0 = -1;
+        racc = 0;
+        tiles[atomicAdd(&ctr[0], 1)] = Task{h, t, t + 1};
+        continue;
+      }
+      if (r0 >= 0 && racc + c > range_cap) {
+        ranges[atomicAdd(&ctr[1], 1)] = Task{h, r0, rlast + 1};
+        r0 = -1;
+        racc = 0;
+      }
+      if (r0 < 0) r0 = t;
+      rlast = t;
+      racc += c;
+    }
+    if (r0 >= 0) ranges[atomicAdd(&ctr[1], 1)] = Task{h, r0, rlast + 1};
+  }
+}
+
+// Dense-tile tasks: persistent workgroups take tasks from a global counter; a
+// tile's products are folded into a dense LDS accumulator of 16384 slots
+// plus an occupancy bitmap; the bitmap is then compacted in column order
+// straight into C, and the touched slots are reset to the identity.
+template <class Sr, class Rows, int BS>
+__global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, const int32_t* off2, const Task* tasks,
+                                                  int32_t* ctr, int32_t* err) {
+  using Src = typename Rows::Src;
   constexpr int NW = BS / kWave;
   static_assert(BS >= kTileWords, "one compaction word per thread");
   using Item = typename Src::Item;
@@ -606,26 +798,25 @@ __global__ __launch_bounds__(BS) void k_num_dense(Src src, Bins bins, OutC C, co
   __shared__ int32_t s_task;
   for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
   for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
-  const int32_t first = bins.start[kBinDense0];
-  const int32_t nd = bins.start[kNB - 1] + bins.count[kNB - 1] - first;
-  const int32_t* L = bins.list + first;
-  const int32_t T = src.T;
-  const int64_t ntask = (int64_t)nd * T;
+  const int32_t* L = bins.list + bins.start[kBinDense0];
+  const int32_t Tmax = rows.Tmax;
+  const int32_t ntask = ctr[0];
   while (true) {
-    if (threadIdx.x == 0) s_task = atomicAdd(task_ctr, 1);
+    if (threadIdx.x == 0) s_task = atomicAdd(&ctr[2], 1);
     __syncthreads();
-    const int64_t task = s_task;
+    const int32_t task = s_task;
     __syncthreads();
     if (task >= ntask) break;
-    const int h = (int)(task / T), t = (int)(task % T);
-    const int32_t* o2 = off2 + (int64_t)h * (T + 1);
-    const int32_t lo = o2[t], hi = o2[t + 1];
-    if (hi == lo) continue;
-    const int64_t i = L[h];
+    const Task tk = tasks[task];
+    const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
+    const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
+    const int64_t i = L[tk.h];
     const int64_t base = C.rowptr[i] + lo;
-    const int64_t c0 = (int64_t)t << kTileLog;
-    Src s = src;
-    const int64_t nsrc = s.bind(i, t, t + 1);
+    const int64_t c0 = (int64_t)tk.t0 << kTileLog;
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, tk.t0, tk.t1);
     auto body = [&](const Item& it, int64_t idx) {
       const int32_t c = (int32_t)(s.col(it, idx) - c0);
       Sr::lds_acc(&s_acc[c], s.template value<Sr>(it, idx));
@@ -651,6 +842,33 @@ __global__ __launch_bounds__(BS) void k_num_dense(Src src, Bins bins, OutC C, co
       s_bm[threadIdx.x] = 0u;
     }
     __syncthreads();
+  }
+}
+
+// Range tasks: persistent workgroups, one hash task per range of tiles.
+template <class Sr, class Rows, int LGS, int BS>
+__global__ __launch_bounds__(BS) void k_num_ranges(Rows rows, Bins bins, OutC C, const int32_t* off2,
+                                                   const Task* tasks, int32_t* ctr, int32_t* err) {
+  using Src = typename Rows::Src;
+  __shared__ HashSmem<Sr, Src, LGS, BS> sm;
+  __shared__ int32_t s_task;
+  const int32_t* L = bins.list + bins.start[kBinDense0];
+  const int32_t Tmax = rows.Tmax;
+  const int32_t ntask = ctr[1];
+  while (true) {
+    if (threadIdx.x == 0) s_task = atomicAdd(&ctr[3], 1);
+    __syncthreads();
+    const int32_t task = s_task;
+    __syncthreads();
+    if (task >= ntask) break;
+    const Task tk = tasks[task];
+    const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
+    const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
+    const int64_t i = L[tk.h];
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    hash_task<Sr, Src, LGS, BS>(sm, s, li, tk.t0, tk.t1, C.rowptr[i] + lo, hi - lo, C, err);
   }
 }
 

@@ -10,10 +10,12 @@
 
 namespace sg {
 
+enum RowMode { kModeProduct = 0, kModeMerge = 1, kModeBatchProducts = 2, kModeBatchMerges = 3 };
+
 // Everything a symbolic or numeric launch needs to describe its rows.
 struct RowSource {
-  int merge;  // 0: product rows of A (x) B, 1: merge of parts
-  // product
+  int mode;
+  // single product
   const int64_t* a_rowptr;
   const int32_t* a_col;
   const void* a_val;
@@ -22,23 +24,29 @@ struct RowSource {
   const void* b_val;
   int64_t b_nrows;
   const int32_t* rp2;
-  // merge
+  // single merge
   const PartDesc* parts;
   int32_t nparts;
-  // both
-  int64_t nrows;
-  int64_t ncols;  // columns of C
-  int32_t T;      // column tiles of C
+  // batches
+  const ProbDesc* probs;
+  const GroupDesc* groups;
+  const int64_t* rbase;
+  int32_t ntable;
+  // all
+  int64_t nrows;  // (global) rows
+  int64_t ncols;  // columns of C (single modes)
+  int32_t T;      // column tiles (single modes) or the largest over the batch
 };
 
 struct BinPlan {
   Bins bins;
-  int32_t count[kNB];  // host copy
+  int32_t count[kNB];  // host copy (graph mode: a large placeholder per bin)
   int32_t start[kNB];
+  bool graph = false;  // counts unknown on the host: launch every kernel
   int32_t ndense() const {
-    int32_t s = 0;
+    int64_t s = 0;
     for (int b = kBinDense0; b < kNB; ++b) s += count[b];
-    return s;
+    return s > INT32_MAX ? INT32_MAX : (int32_t)s;
   }
 };
 
@@ -62,7 +70,10 @@ struct NumCtx {
   OutC C;
   const int32_t* off2;
   int32_t* err;
-  int32_t* task_ctr;
+  int32_t* task_ctr;  // 4 counters: tile tasks, range tasks, and their cursors
+  Task* tasks;        // tile tasks [0, task_cap), range tasks [task_cap, 2*task_cap)
+  int64_t task_cap;   // >= dense rows x tiles
+  int32_t tile_min;
   int cus;
   int comp_dense;  // float sums: dense rows use compensated accumulation
 };
@@ -78,6 +89,7 @@ inline SpgemmSrc<V, kVals> make_spgemm_src(const RowSource& r) {
   s.b_val = (const V*)r.b_val;
   s.rp2 = r.rp2;
   s.T = r.T;
+  s.ncols = r.ncols;
   return s;
 }
 
@@ -89,6 +101,18 @@ inline MergeSrc<V> make_merge_src(const RowSource& r) {
   s.T = r.T;
   s.ncols = r.ncols;
   return s;
+}
+
+// Calls f(rows) with the row set of r's mode; V is the value type the
+// sources read (uint8_t and kVals = false for structure-only passes).
+template <class V, bool kVals, class F>
+inline void with_rows(const RowSource& r, F&& f) {
+  switch (r.mode) {
+    case kModeProduct: f(OneRows<SpgemmSrc<V, kVals>>{make_spgemm_src<V, kVals>(r), r.T}); break;
+    case kModeMerge: f(OneRows<MergeSrc<V>>{make_merge_src<V>(r), r.T}); break;
+    case kModeBatchProducts: f(TableRows<V, kVals>{r.probs, r.rbase, r.ntable, r.T}); break;
+    case kModeBatchMerges: f(MergeTableRows<V>{r.groups, r.rbase, r.ntable, r.T}); break;
+  }
 }
 
 template <class K>
@@ -104,64 +128,78 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   return g < 1 ? 1 : (int)g;
 }
 
-template <class Sr, class Src, int LGS, int BS>
-inline void launch_num_hash_one(const Src& s, const NumCtx& c, int bin, hipStream_t st) {
+template <class Sr, class Rows, int LGS, int BS>
+inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st) {
   const int n = c.plan.count[bin];
   if (n == 0) return;
-  auto k = k_num_hash<Sr, Src, LGS, BS>;
+  auto k = k_num_hash<Sr, Rows, LGS, BS>;
   static int occ = occupancy(k, BS);
-  hipLaunchKernelGGL(k, dim3(grid_for(n, 1, c.cus * occ * 4)), dim3(BS), 0, st, s, c.plan.bins, bin, c.C, c.err);
+  hipLaunchKernelGGL(k, dim3(grid_for(n, 1, c.cus * occ * 4)), dim3(BS), 0, st, rows, c.plan.bins, bin, c.C, c.err);
 }
 
-template <class Sr, class Src>
-inline void launch_num_hash_all(const Src& s, const NumCtx& c, int bin0, hipStream_t st) {
-  launch_num_hash_one<Sr, Src, 7, 256>(s, c, bin0 + 0, st);
-  launch_num_hash_one<Sr, Src, 8, 256>(s, c, bin0 + 1, st);
-  launch_num_hash_one<Sr, Src, 9, 256>(s, c, bin0 + 2, st);
-  launch_num_hash_one<Sr, Src, 10, 256>(s, c, bin0 + 3, st);
-  launch_num_hash_one<Sr, Src, 11, 512>(s, c, bin0 + 4, st);
-  launch_num_hash_one<Sr, Src, 12, 512>(s, c, bin0 + 5, st);
-  launch_num_hash_one<Sr, Src, 13, 512>(s, c, bin0 + 6, st);
+template <class Sr, class Rows>
+inline void launch_num_hash_all(const Rows& rows, const NumCtx& c, int bin0, hipStream_t st) {
+  launch_num_hash_one<Sr, Rows, 7, 256>(rows, c, bin0 + 0, st);
+  launch_num_hash_one<Sr, Rows, 8, 256>(rows, c, bin0 + 1, st);
+  launch_num_hash_one<Sr, Rows, 9, 256>(rows, c, bin0 + 2, st);
+  launch_num_hash_one<Sr, Rows, 10, 256>(rows, c, bin0 + 3, st);
+  launch_num_hash_one<Sr, Rows, 11, 512>(rows, c, bin0 + 4, st);
+  launch_num_hash_one<Sr, Rows, 12, 512>(rows, c, bin0 + 5, st);
+  launch_num_hash_one<Sr, Rows, 13, 512>(rows, c, bin0 + 6, st);
 }
 
-template <class Sr, class Src>
-inline void launch_num_dense(const Src& s, const NumCtx& c, hipStream_t st) {
+// Dense rows: build the tile and range task lists from the per-tile counts,
+// then run the two persistent task kernels.
+constexpr int kRangeLg = 12;          // range tasks: hash table of 4096 slots
+constexpr int kRangeCap = 2048;       // entries per range task
+constexpr int kTileMinDefault = 1024; // entries that make a tile a dense-tile task
+
+template <class Sr, class Rows>
+inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) {
   if (c.plan.ndense() == 0) return;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, c.task_ctr, (int64_t)4, (int32_t)0);
+  hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
+                     c.plan.bins, c.off2, rows.Tmax, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
+                     c.task_ctr);
   // 8-byte accumulators need the whole LDS for one 16384-slot tile: use a
   // 1024-thread workgroup (16 waves) when the per-source items are small.
-  constexpr int BS = (sizeof(typename Sr::Acc) >= 8 && sizeof(typename Src::Item) <= 8) ? 1024 : 512;
-  auto k = k_num_dense<Sr, Src, BS>;
+  constexpr int BS =
+      (sizeof(typename Sr::Acc) >= 8 && sizeof(typename Rows::Src::Item) <= 8) ? 1024 : 512;
+  auto k = k_num_tiles<Sr, Rows, BS>;
   static int occ = occupancy(k, BS);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, c.task_ctr, (int64_t)1, (int32_t)0);
-  hipLaunchKernelGGL(k, dim3(c.cus * occ), dim3(BS), 0, st, s, c.plan.bins, c.C, c.off2, c.task_ctr, c.err);
+  hipLaunchKernelGGL(k, dim3(c.cus * occ), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks, c.task_ctr,
+                     c.err);
+  constexpr int RBS = sizeof(typename Sr::Acc) >= 8 ? 256 : 512;
+  auto k2 = k_num_ranges<Sr, Rows, kRangeLg, RBS>;
+  static int occ2 = occupancy(k2, RBS);
+  hipLaunchKernelGGL(k2, dim3(c.cus * occ2), dim3(RBS), 0, st, rows, c.plan.bins, c.C, c.off2,
+                     c.tasks + c.task_cap, c.task_ctr, c.err);
 }
 
 // Numeric pass for semiring Sr (SrC: its compensated variant, or Sr).
-template <class Sr, class SrC, class Src>
-inline void launch_numeric_src(const Src& s, const NumCtx& c, hipStream_t st) {
+template <class Sr, class SrC, class Rows>
+inline void launch_numeric_rows(const Rows& rows, const NumCtx& c, hipStream_t st) {
   c.marks.mark(kPhNumSmall, 1);
   if (c.plan.count[kBinSmall]) {
-    auto k = k_num_small<Sr, Src>;
+    auto k = k_num_small<Sr, Rows>;
     static int occ = occupancy(k, 256);
-    hipLaunchKernelGGL(k, dim3(grid_for(c.plan.count[kBinSmall], 4, c.cus * occ * 4)), dim3(256), 0, st, s,
+    hipLaunchKernelGGL(k, dim3(grid_for(c.plan.count[kBinSmall], 4, c.cus * occ * 4)), dim3(256), 0, st, rows,
                        c.plan.bins, kBinSmall, c.C, c.err);
   }
   c.marks.mark(kPhNumSmall, 0);
   c.marks.mark(kPhNumHash, 1);
-  launch_num_hash_all<Sr, Src>(s, c, kBinHash0, st);
-  launch_num_hash_all<SrC, Src>(s, c, kBinHashC0, st);
+  launch_num_hash_all<Sr, Rows>(rows, c, kBinHash0, st);
+  launch_num_hash_all<SrC, Rows>(rows, c, kBinHashC0, st);
   c.marks.mark(kPhNumHash, 0);
   c.marks.mark(kPhNumDense, 1);
-  if (c.comp_dense) launch_num_dense<SrC, Src>(s, c, st);
-  else launch_num_dense<Sr, Src>(s, c, st);
+  if (c.comp_dense) launch_num_dense<SrC, Rows>(rows, c, st);
+  else launch_num_dense<Sr, Rows>(rows, c, st);
   c.marks.mark(kPhNumDense, 0);
 }
 
 template <class Sr, class SrC>
 inline void launch_numeric(const NumCtx& c, hipStream_t st) {
-  using V = typename Sr::V;
-  if (c.src.merge) launch_numeric_src<Sr, SrC>(make_merge_src<V>(c.src), c, st);
-  else launch_numeric_src<Sr, SrC>(make_spgemm_src<V, true>(c.src), c, st);
+  with_rows<typename Sr::V, true>(c.src, [&](const auto& rows) { launch_numeric_rows<Sr, SrC>(rows, c, st); });
 }
 
 // ---- entry points implemented in the .hip translation units -------------------------
