@@ -88,6 +88,126 @@ def cpu_baseline(A, B, sr, p, target_s):
             "sample": f"{k} rows drawn uniformly (seed 3) of the same product, {prods} products, {dt:.2f} s"}
 
 
+def parity_sample(A, B, sr, p, C, per_bin=12):
+    """Rows of the timed result against the oracle: a stratified sample over
+    product-count decades (exact semirings bit for bit; float sums: the gated
+    tolerance and plain max / median relative error)."""
+    import torch
+    import oracle
+    import synth
+    rows = []
+    edges = [1, 64, 4096, 65536, 1 << 20, 1 << 62]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        cand = np.nonzero((p >= lo) & (p < hi))[0]
+        if len(cand):
+            rows.extend(cand[synth.select(len(cand), min(per_bin, len(cand)), lo)].tolist())
+    rows = np.sort(np.array(rows, dtype=np.int64))
+    rp = C.rowptr.cpu().numpy()
+    idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+    ti = torch.from_numpy(idx).to(C.col.device)
+    g_col, g_val = C.col[ti].cpu().numpy(), C.val[ti].cpu().numpy()
+    g_rp = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum(rp[rows + 1] - rp[rows], out=g_rp[1:])
+    ref = oracle.get().spgemm(sr, A, B, rows=rows)
+    out = {"rows": int(len(rows)), "entries": int(len(idx)),
+           "pattern_equal": bool(np.array_equal(g_rp, ref.rowptr) and np.array_equal(g_col, ref.col))}
+    if not out["pattern_equal"]:
+        return out
+    if sr in (1, 4, 5):
+        a, b = g_val, ref.val
+        same = (a.view(np.uint8).reshape(len(a), -1) == b.view(np.uint8).reshape(len(b), -1)).all(axis=1)
+        if a.dtype.kind == "f":
+            same |= (a == 0) & (b == 0)
+        out["bit_exact"] = bool(same.all())
+    else:
+        tol = 1e-12 if sr == 3 else 1e-5
+        got, r = g_val.astype(np.float64), ref.val
+        scale = np.maximum(np.abs(r), ref.mag)
+        out["within_tol"] = bool((np.abs(got - r) <= tol * scale).all())
+        nz = r != 0
+        rel = np.abs(got[nz] - r[nz]) / np.abs(r[nz])
+        out["max_rel_err"] = float(rel.max()) if len(rel) else 0.0
+        out["median_rel_err"] = float(np.median(rel)) if len(rel) else 0.0
+    return out
+
+
+def batched_leg(sg, torch, h, sr, dA, dB, P, steps, ms_per_call):
+    """The same product through the batched path: one plan (sized once),
+    then whole-pipeline graph replays with no host round trip."""
+    t0 = time.perf_counter()
+    plan = h.batch_plan(sr, [dA], [dB])
+    t_plan = time.perf_counter() - t0
+    plan.execute()
+    torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.results()  # raises on pool overflow or a consistency error
+    plan.destroy()
+    return {"ms_per_step": round(ms, 4), "value": P / (ms * 1e-3), "unit": "semiring products/s",
+            "speedup_vs_per_call": round(ms_per_call / ms, 4), "plan_s": round(t_plan, 3)}
+
+
+def summa_leg(sg, torch, h, scale, steps):
+    """Sparse SUMMA emulation on one GPU: R-MAT A cut into an 8x8 block grid;
+    all 512 stage products A_IK.A_KJ (fp64 (+,x)) and the 64 merges of each
+    output block, batched (one graph) against per-call (one symbolic +
+    numeric call per product and per merge)."""
+    import synth
+    A = synth.rmat(scale, 16, seed=1)
+    A = A.with_values(synth.values(synth.VAL_F64_UNIFORM, A.nnz, 0, 1, 2))
+    g = 8
+    blk = synth.block_split(A, g)
+    dblk = [[sg.DeviceCSR.from_host(blk[I][J]) for J in range(g)] for I in range(g)]
+    As, Bs, go = [], [], [0]
+    for I in range(g):
+        for J in range(g):
+            for K in range(g):
+                As.append(dblk[I][K])
+                Bs.append(dblk[K][J])
+            go.append(len(As))
+    sr = sg.semiring(sg.PLUS_TIMES_F64)
+    nb = np.diff(A.rowptr)
+    prods = 0
+    for I in range(g):
+        for J in range(g):
+            for K in range(g):
+                a, b = blk[I][K], blk[K][J]
+                prods += int(np.diff(b.rowptr)[a.col].sum())
+
+    def per_call():
+        outs = []
+        for I in range(g):
+            for J in range(g):
+                parts = [h.spgemm(sr, dblk[I][K], dblk[K][J]) for K in range(g)]
+                outs.append(h.merge(sr, parts))
+        return outs
+
+    per_call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per_call()
+    torch.cuda.synchronize()
+    ms_pc = (time.perf_counter() - t0) * 1e3 / steps
+    plan = h.batch_plan(sr, As, Bs, go)
+    plan.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute()
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3 / steps
+    plan.results()
+    plan.destroy()
+    return {"workload": f"R-MAT s{scale} cut 8x8, 512 fp64 (+,x) stage products + 64 merges", "products": prods,
+            "ms_per_call_path": round(ms_pc, 3), "ms_batched": round(ms_b, 3),
+            "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +217,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hash-max", type=int, default=None)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched legs")
+    ap.add_argument("--summa-scale", type=int, default=18, help="R-MAT scale of the 8x8 SUMMA leg (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB copy kernel (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the product is the per-GPU local multiply and this build has no "
@@ -205,6 +329,22 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "roofline": roof,
     }
+    t_par = time.perf_counter()
+    out["parity_sample"] = parity_sample(A, B, sr_id, p, C)
+    print(f"# parity sample {out['parity_sample']} in {time.perf_counter() - t_par:.1f}s", file=sys.stderr, flush=True)
+    del C, col, val, rowptr
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_leg(sg, torch, h, sr, dA, dB, P, args.steps, ms)
+        if args.summa_scale > 0:
+            out["summa"] = summa_leg(sg, torch, h, args.summa_scale, args.steps)
+    if args.calibrate_copy:
+        n = 1 << 27
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n, "kernel": "torch mul int32 (elementwise)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, sr_id, p, args.cpu_seconds)
     h.close()

@@ -87,11 +87,12 @@ size_t plan_rows_bytes(int64_t nrows) {
   a.take<int32_t>(kNB);
   a.take<int32_t>(kNB);
   a.take<int32_t>(nrows);
+  a.take<int32_t>(nrows);
   return a.off;
 }
 
 sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* cnt_out,
-                    SgArena& ar, BinPlan& plan, hipStream_t st) {
+                    SgArena& ar, BinPlan& plan, hipStream_t st, int64_t* p_keep, int32_t* nt_keep, bool rebin) {
   const int64_t n = r.nrows;
   const int64_t nblk = analyze_blocks(n);
   int64_t* p = ar.take<int64_t>(n);
@@ -101,7 +102,11 @@ sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const i
   int32_t* bin_start = ar.take<int32_t>(kNB);
   int32_t* bin_count = ar.take<int32_t>(kNB);
   int32_t* list = ar.take<int32_t>(n);
-  launch_analyze(r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count, list, cnt_out, st);
+  int32_t* nt = ar.take<int32_t>(n);
+  if (p_keep) p = p_keep;
+  if (nt_keep) nt = nt_keep;
+  if (rebin) launch_rebin(p, nt, c_rowptr, n, pol, bin, hist, blk_off, bin_start, bin_count, list, st);
+  else launch_analyze(r, pol, c_rowptr, p, nt, bin, hist, blk_off, bin_start, bin_count, list, cnt_out, st);
   int32_t* hp = (int32_t*)h->h_pin;
   SG_HIP(h, hipMemcpyAsync(hp, bin_count, kNB * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   SG_HIP(h, hipMemcpyAsync(hp + kNB, bin_start, kNB * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -210,8 +215,10 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   const Policy pol = make_policy(h, 0, nullptr);
   clear_phases(h, kPhSymAnalyze, kPhNumAnalyze);
   const Marks mk = handle_marks(h, st);
+  SG_HIP(h, h->p_buf.ensure(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)));
+  SG_HIP(h, h->nt_buf.ensure(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
   mk.mark(kPhSymAnalyze, 1);
-  SG_TRY(plan_rows(h, r, pol, nullptr, C_rowptr + 1, ar, plan, st));
+  SG_TRY(plan_rows(h, r, pol, nullptr, C_rowptr + 1, ar, plan, st, (int64_t*)h->p_buf.p, (int32_t*)h->nt_buf.p));
   mk.mark(kPhSymAnalyze, 0);
   const int32_t nd = plan.ndense();
   int32_t* off2 = nullptr;
@@ -240,6 +247,7 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   h->cache_key = key;
   h->cache_T = r.T;
   h->cache_nd = nd;
+  h->cache_n = n;
   return SG_OK;
 }
 
@@ -256,11 +264,18 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   const Policy pol = make_policy(h, 1, sr);
   clear_phases(h, kPhNumAnalyze, kNPhases);
   const Marks mk = handle_marks(h, st);
+  // Same structure as the last symbolic call: its per-row counts give the bins
+  // without touching A or B again.  Dense classification depends only on the
+  // product count and the key's options, so the dense list is unchanged.
+  const bool same = h->cache_valid && h->cache_key == key && h->cache_T == r.T && h->cache_n == n;
   mk.mark(kPhNumAnalyze, 1);
-  SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st));
+  if (same)
+    SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st, (int64_t*)h->p_buf.p, (int32_t*)h->nt_buf.p, true));
+  else
+    SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st));
   mk.mark(kPhNumAnalyze, 0);
   const int32_t nd = plan.ndense();
-  const bool cached = h->cache_valid && h->cache_key == key && h->cache_T == r.T && h->cache_nd == nd;
+  const bool cached = same && h->cache_nd == nd;
   if (nd > 0) {
     if (r.mode == kModeProduct && r.T > 1) {
       if (!cached) {
@@ -285,7 +300,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.err = h->d_flags;
   c.task_ctr = h->d_flags + 8;
   c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;
-  SG_HIP(h, h->task_buf.ensure(sizeof(Task) * 2 * (size_t)c.task_cap));
+  SG_HIP(h, h->task_buf.ensure(task_buffer_bytes(c.task_cap, r.T)));
   c.tasks = (Task*)h->task_buf.p;
   c.tile_min = h->tile_min;
   c.cus = h->cus;
@@ -424,6 +439,8 @@ sg_status sg_handle_destroy(sg_handle* h) {
   (void)hipDeviceSynchronize();
   h->ws.release();
   h->task_buf.release();
+  h->p_buf.release();
+  h->nt_buf.release();
   h->rp2_buf.release();
   h->off2_buf.release();
   h->parts_buf.release();

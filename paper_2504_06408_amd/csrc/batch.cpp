@@ -44,6 +44,7 @@ struct Stage {
   SgBuf work, off_buf, off2_buf, col_buf, val_buf, task_buf;
   // views into work
   int64_t* p = nullptr;
+  int32_t* nt = nullptr;
   uint8_t* bin = nullptr;
   int32_t *hist = nullptr, *blk_off = nullptr, *bin_start = nullptr, *bin_count = nullptr, *list = nullptr;
   int64_t* partial = nullptr;
@@ -59,6 +60,7 @@ struct Stage {
     m.take<int32_t>(kNB);
     m.take<int32_t>(kNB);
     m.take<int32_t>(R);
+    m.take<int32_t>(R);
     m.take<int64_t>(scan_partials_len(R));
     SG_HIP(h, work.ensure(m.off));
     SgArena a;
@@ -70,6 +72,7 @@ struct Stage {
     bin_start = a.take<int32_t>(kNB);
     bin_count = a.take<int32_t>(kNB);
     list = a.take<int32_t>(R);
+    nt = a.take<int32_t>(R);
     partial = a.take<int64_t>(scan_partials_len(R));
     SG_HIP(h, off_buf.ensure(sizeof(int64_t) * (size_t)(R + 1)));
     off = (int64_t*)off_buf.p;
@@ -128,7 +131,7 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
   hipStream_t st = P->stream;
   // symbolic with host-known bin counts (this pass only sizes the plan)
   const Policy ps = make_policy(h, 0, nullptr);
-  launch_analyze(S.src, ps, nullptr, S.p, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, S.off + 1, st);
+  launch_analyze(S.src, ps, nullptr, S.p, S.nt, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, S.off + 1, st);
   BinPlan bp;
   int32_t* hp = (int32_t*)h->h_pin;
   SG_HIP(h, hipMemcpyAsync(hp, S.bin_count, kNB * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -137,7 +140,7 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
   S.nd = bp.ndense();
   bp.bins = Bins{S.list, S.bin_start, S.bin_count, S.nd};
   SG_HIP(h, S.off2_buf.ensure(sizeof(int32_t) * (size_t)(S.nd > 0 ? S.nd : 1) * (size_t)(S.src.T + 1)));
-  SG_HIP(h, S.task_buf.ensure(sizeof(Task) * 2 * (size_t)(S.nd > 0 ? S.nd : 1) * (size_t)S.src.T));
+  SG_HIP(h, S.task_buf.ensure(task_buffer_bytes((int64_t)(S.nd > 0 ? S.nd : 1) * S.src.T, S.src.T)));
   if (S.nd > 0 && has_dense_inputs)
     for (auto& b : P->bounds)
       launch_tile_bounds(std::get<0>(b), std::get<1>(b), std::get<2>(b), std::get<3>(b), std::get<4>(b), h->cus, st);
@@ -171,7 +174,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   hipStream_t st = P->stream;
   const Policy ps = make_policy(h, 0, nullptr);
   const Policy pn = make_policy(h, 1, &P->sr);
-  launch_analyze(S.src, ps, nullptr, S.p, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, S.off + 1, st);
+  launch_analyze(S.src, ps, nullptr, S.p, S.nt, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, S.off + 1, st);
   BinPlan bp = S.graph_plan();
   if (S.nd == 0) {
     for (int b = kBinDense0; b < kNB; ++b) bp.count[b] = 0;
@@ -182,7 +185,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   launch_symbolic(S.src, bp, S.off + 1, (int32_t*)S.off2_buf.p, h->cus, Marks{}, st);
   launch_fill_i64(S.off, 1, 0, st);
   launch_scan_inclusive(S.off + 1, S.R, S.partial, st);
-  launch_analyze(S.src, pn, S.off, S.p, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, nullptr, st);
+  launch_rebin(S.p, S.nt, S.off, S.R, pn, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, st);
   launch_pool_guard(S.off + S.R, pool_cap(S, (size_t)P->sr.value_bytes), S.bin_count, P->d_flag, st);
   NumCtx c{};
   c.src = S.src;

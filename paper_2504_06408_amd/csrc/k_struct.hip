@@ -111,11 +111,11 @@ __global__ __launch_bounds__(kScanBS) void k_scan_apply(int64_t* a, int64_t n, c
 
 template <class Rows>
 void analyze_rows(const Rows& rows, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p,
-                  uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                  int32_t* nt, uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
                   int32_t* list, int64_t* cnt_out, hipStream_t st) {
   const int64_t nblk = analyze_blocks(r.nrows);
   hipLaunchKernelGGL((k_analyze<Rows, kAnaBS>), dim3(nblk), dim3(kAnaBS), 0, st, rows, r.nrows, pol, c_rowptr, p,
-                     bin, hist, cnt_out);
+                     nt, bin, hist, cnt_out);
   hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, hist, (int32_t)nblk, blk_off, bin_start, bin_count);
   hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, list);
 }
@@ -134,9 +134,10 @@ void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int
                     hipStream_t st) {
   const int nd = plan.ndense();
   if (nd == 0) return;
+  constexpr int BS = sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512;
   auto k = k_sym_dense<Rows>;
-  static int occ = occupancy(k, 512);
-  hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(512), 0, st, rows, plan.bins, cnt_out, off2);
+  static int occ = occupancy(k, BS);
+  hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(BS), 0, st, rows, plan.bins, cnt_out, off2);
 }
 
 template <class Rows>
@@ -187,12 +188,21 @@ __global__ __launch_bounds__(256) void k_validate(const int64_t* rowptr, const i
 
 int64_t analyze_blocks(int64_t nrows) { return (nrows + kAnaBS - 1) / kAnaBS; }
 
-void launch_analyze(const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p, uint8_t* bin,
-                    int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count, int32_t* list,
-                    int64_t* cnt_out, hipStream_t st) {
+void launch_analyze(const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p, int32_t* nt,
+                    uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                    int32_t* list, int64_t* cnt_out, hipStream_t st) {
   with_rows<uint8_t, false>(r, [&](const auto& rows) {
-    analyze_rows(rows, r, pol, c_rowptr, p, bin, hist, blk_off, bin_start, bin_count, list, cnt_out, st);
+    analyze_rows(rows, r, pol, c_rowptr, p, nt, bin, hist, blk_off, bin_start, bin_count, list, cnt_out, st);
   });
+}
+
+void launch_rebin(const int64_t* p, const int32_t* nt, const int64_t* c_rowptr, int64_t nrows, const Policy& pol,
+                  uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                  int32_t* list, hipStream_t st) {
+  const int64_t nblk = analyze_blocks(nrows);
+  hipLaunchKernelGGL(k_rebin<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, p, nt, c_rowptr, nrows, pol, bin, hist);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, hist, (int32_t)nblk, blk_off, bin_start, bin_count);
+  hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, nrows, blk_off, list);
 }
 
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,

@@ -257,12 +257,16 @@ SG_DEV void wave_bitonic_sort(int32_t& key, P& pay) {
 // Src provides:
 //   using Item;                              per-source payload kept in LDS
 //   SG_DEV void load(int64_t j, Item& it, int64_t& start, int64_t& len) const;
-// and body(const Item&, int64_t idx) is called once per product with the
-// product's index in its source's arrays.
-template <int BS, class Src, class Body>
+// fetch(const Item&, int64_t idx) reads one product from global memory (idx
+// is its index in the source's arrays) and returns it by value; apply(p)
+// folds it into LDS.  Each lane first fetches U products (U independent loads
+// in flight, so the gathers are not serialised behind the LDS updates) and
+// then applies them.
+template <int BS, int U, class Src, class Fetch, class Apply>
 SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s_item, int64_t* s_start,
-                             int64_t* s_off, int64_t* s_wave, Body& body) {
+                             int64_t* s_off, int64_t* s_wave, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
+  using P = decltype(fetch(s_item[0], (int64_t)0));
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
     const int64_t j = c0 + threadIdx.x;
     int64_t start = 0, len = 0;
@@ -275,15 +279,46 @@ SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s
     s_off[threadIdx.x] = off;
     const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
     __syncthreads();
-    for (int64_t q = threadIdx.x; q < total; q += BS) {
-      // owner: the last source whose offset is <= q
-      int lo = 0, hi = nc - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= q) lo = mid;
-        else hi = mid - 1;
+    // Wave w takes blocks of 64*U consecutive products; its lanes take
+    // q = qb + u*64 + lane (u < U), so every load instruction is coalesced.
+    // The owners of the block's first and last product are found with
+    // searches at wave-uniform addresses (LDS broadcasts); each lane then
+    // searches only the sources in between, starting from its previous hit.
+    constexpr int64_t kBlock = (int64_t)kWave * U;
+    for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
+      const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
+      int a = 0, b = nc - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (s_off[mid] <= qb) a = mid;
+        else b = mid - 1;
       }
-      body(s_item[lo], s_start[lo] + (q - s_off[lo]));
+      int e = a, f = nc - 1;
+      while (e < f) {
+        const int mid = (e + f + 1) >> 1;
+        if (s_off[mid] <= qe) e = mid;
+        else f = mid - 1;
+      }
+      P p[U];
+      bool ok[U];
+      int lo = a;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t q = qb + u * kWave + lane_id();
+        ok[u] = q < total;
+        if (ok[u]) {
+          int hi = e;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= q) lo = mid;
+            else hi = mid - 1;
+          }
+          p[u] = fetch(s_item[lo], s_start[lo] + (q - s_off[lo]));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) apply(p[u]);
     }
     __syncthreads();
   }

@@ -72,11 +72,13 @@ struct sg_handle {
   SgBuf rp2_buf, off2_buf;   // dense-path data kept from symbolic for numeric
   SgBuf parts_buf;           // device table of merge parts
   SgBuf task_buf;            // dense-row task lists of the numeric pass
+  SgBuf p_buf, nt_buf;       // per-row products and terms from symbolic, reused to re-bin numeric
   int32_t tile_min = sg::kTileMinDefault;
   std::vector<sg::PartDesc> parts_host;
   bool cache_valid = false;
   SgCacheKey cache_key{};
   int32_t cache_T = 0, cache_nd = 0;
+  int64_t cache_n = -1;
   int32_t* d_flags = nullptr;  // [0] consistency error, [2] validation, [8..11] task counters
   int64_t* h_pin = nullptr;    // pinned readback area (>= 256 int64)
 };
@@ -89,9 +91,12 @@ namespace sg {
 int32_t tiles_of(int64_t ncols);
 Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr);
 // Analysis + binning of the rows of r; waits for the stream to read the bin
-// counts.  Scratch comes from `ar`.
+// counts.  Scratch comes from `ar`.  p_keep / nt_keep (optional) receive the
+// per-row product and term counts; with rebin set they are read instead and
+// no gathers are made.
 sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* cnt_out,
-                    SgArena& ar, BinPlan& plan, hipStream_t st);
+                    SgArena& ar, BinPlan& plan, hipStream_t st, int64_t* p_keep = nullptr,
+                    int32_t* nt_keep = nullptr, bool rebin = false);
 size_t plan_rows_bytes(int64_t nrows);
 // Timing hooks of the handle for a call on stream st (inactive unless the
 // "timing" option is on); clear_phases forgets phases [p0, p1).

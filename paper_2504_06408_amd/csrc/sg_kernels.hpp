@@ -224,6 +224,16 @@ struct MergeSrc {
   }
 };
 
+// Products each lane gathers before folding them into LDS (memory-level
+// parallelism of the B-row gathers).
+constexpr int kUnroll = 8;
+
+template <class Acc>
+struct ColVal {
+  int32_t c;
+  Acc v;
+};
+
 // ---- row sets ---------------------------------------------------------------------
 //
 // Kernels see a set of "global" rows r; Rows::get maps r to the source of the
@@ -340,7 +350,7 @@ struct OutC {
 
 template <class Rows, int BS>
 __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy pol, const int64_t* c_rowptr,
-                                                  int64_t* p_out, uint8_t* bin_out, int32_t* hist,
+                                                  int64_t* p_out, int32_t* nt_out, uint8_t* bin_out, int32_t* hist,
                                                   int64_t* cnt_out) {
   using Src = typename Rows::Src;
   __shared__ int32_t s_hist[kNB];
@@ -372,22 +382,55 @@ __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy
     rows.get(ri, t, tl);
     const int64_t n2 = t.bind(tl, 0, t.T);
     int64_t part = 0;
-    for (int64_t j = lane_id(); j < n2; j += kWave) {
-      typename Src::Item it;
-      int64_t st, len;
-      t.load(j, it, st, len);
-      part += len;
+    // eight independent source loads per lane in flight (hub rows of power-law
+    // graphs hold tens of thousands of entries)
+    for (int64_t j0 = 0; j0 < n2; j0 += 8 * kWave) {
+      int64_t lens[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + u * kWave + lane_id();
+        lens[u] = 0;
+        if (j < n2) {
+          typename Src::Item it;
+          int64_t st;
+          t.load(j, it, st, lens[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) part += lens[u];
     }
     part = wave_sum(part);
     if (lane_id() == leader) p = part;
   }
   if (valid) {
     p_out[i] = p;
+    nt_out[i] = (int32_t)nsrc;
     const int64_t m = pol.numeric ? (c_rowptr[i + 1] - c_rowptr[i]) : 0;
     const int b = bin_of(pol, p, m, nsrc);
     bin_out[i] = (uint8_t)b;
     atomicAdd(&s_hist[b], 1);
     if (!pol.numeric && b == kBinEmpty) cnt_out[i] = 0;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
+}
+
+// Numeric-pass binning from the product counts the symbolic pass already
+// computed (no gathers): only C's row lengths and, for the compensation rule,
+// the number of terms per row (also kept by the symbolic analysis) are read.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_rebin(const int64_t* p_in, const int32_t* nt_in, const int64_t* c_rowptr,
+                                              int64_t nrows, Policy pol, uint8_t* bin_out, int32_t* hist) {
+  __shared__ int32_t s_hist[kNB];
+  for (int b = threadIdx.x; b < kNB; b += BS) s_hist[b] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < nrows) {
+    const int64_t p = p_in[i];
+    const int64_t m = c_rowptr[i + 1] - c_rowptr[i];
+    const int b = bin_of(pol, p, m, nt_in[i]);
+    bin_out[i] = (uint8_t)b;
+    atomicAdd(&s_hist[b], 1);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
@@ -563,12 +606,13 @@ __global__ __launch_bounds__(BS) void k_sym_hash(Rows rows, Bins bins, int bin, 
     rows.get(i, s, li);
     const int64_t nsrc = s.bind(li, 0, s.T);
     int64_t fresh_cnt = 0;
-    auto body = [&](const Item& it, int64_t idx) {
+    auto fetch = [&](const Item& it, int64_t idx) { return s.col(it, idx); };
+    auto apply = [&](int32_t c) {
       bool fresh;
-      hash_insert(s_keys, LGS, s.col(it, idx), &fresh);
+      hash_insert(s_keys, LGS, c, &fresh);
       fresh_cnt += fresh ? 1 : 0;
     };
-    for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, fetch, apply);
     const int64_t tot = block_sum<NW, int64_t>(fresh_cnt, s_wave);
     if (threadIdx.x == 0) cnt_out[i] = tot;
   }
@@ -607,13 +651,16 @@ SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_
   if (threadIdx.x == 0) sm.n = 0;
   __syncthreads();
   const int64_t nsrc = s.bind(li, t0, t1);
-  auto body = [&](const Item& it, int64_t idx) {
+  auto fetch = [&](const Item& it, int64_t idx) {
+    return ColVal<typename Sr::Acc>{s.col(it, idx), s.template value<Sr>(it, idx)};
+  };
+  auto apply = [&](const ColVal<typename Sr::Acc>& p) {
     bool fresh;
-    const uint32_t slot = hash_insert(sm.keys, LGS, s.col(it, idx), &fresh);
-    if (slot != kHashFull) Sr::lds_acc(&sm.vals[slot], s.template value<Sr>(it, idx));
+    const uint32_t slot = hash_insert(sm.keys, LGS, p.c, &fresh);
+    if (slot != kHashFull) Sr::lds_acc(&sm.vals[slot], p.v);
     else atomicOr(err, 2);
   };
-  for_each_product<BS>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, body);
+  for_each_product<BS, kUnroll>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, fetch, apply);
   const int64_t key_base = (int64_t)t0 << kTileLog;
   for (int x = threadIdx.x; x < S; x += BS) {
     const int32_t k = sm.keys[x];
@@ -675,9 +722,10 @@ __global__ __launch_bounds__(BS) void k_num_hash(Rows rows, Bins bins, int bin, 
 // off2[h*(Tmax+1) + t] (t = 0..Tmax; entries past the row's own T repeat the
 // total).
 template <class Rows>
-__global__ __launch_bounds__(512) void k_sym_dense(Rows rows, Bins bins, int64_t* cnt_out, int32_t* off2) {
+__global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512) void k_sym_dense(
+    Rows rows, Bins bins, int64_t* cnt_out, int32_t* off2) {
   using Src = typename Rows::Src;
-  constexpr int BS = 512, NW = BS / kWave;
+  constexpr int BS = sizeof(typename Src::Item) <= 8 ? 1024 : 512, NW = BS / kWave;
   using Item = typename Src::Item;
   __shared__ uint32_t s_bm[kSymTiles * kTileWords];
   __shared__ Item s_item[BS];
@@ -706,11 +754,9 @@ __global__ __launch_bounds__(512) void k_sym_dense(Rows rows, Bins bins, int64_t
       for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
       __syncthreads();
       const int64_t nsrc = s.bind(li, st, t1);
-      auto body = [&](const Item& it, int64_t idx) {
-        const int32_t c = (int32_t)(s.col(it, idx) - c0);
-        atomicOr(&s_bm[c >> 5], 1u << (c & 31));
-      };
-      for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+      auto fetch = [&](const Item& it, int64_t idx) { return (int32_t)(s.col(it, idx) - c0); };
+      auto apply = [&](int32_t c) { atomicOr(&s_bm[c >> 5], 1u << (c & 31)); };
+      for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, fetch, apply);
       // one wavefront per tile, lanes over its 512 words
       for (int tl = wave_id(); tl < t1 - st; tl += NW) {
         int32_t c = 0;
@@ -742,16 +788,26 @@ __global__ __launch_bounds__(512) void k_sym_dense(Rows rows, Bins bins, int64_t
 // counts: a tile holding at least tile_min entries becomes a dense-tile task
 // (dense LDS accumulator, written in column order without a sort); runs of
 // sparser tiles are grouped into range tasks of at most range_cap entries
-// (LDS hash + radix sort).  One thread per dense row appends its tasks to the
-// two lists; ctr[0], ctr[1] count them.
+// (LDS hash + radix sort).  One thread per dense row puts its tasks into
+// per-tile buckets (bucket t of a list holds nd slots; a range goes to the
+// bucket of its first tile); the task kernels then walk the buckets in tile
+// order, so at any time all workgroups gather from the same narrow column
+// slice of B and it stays cache resident.
+//   book[0, Tmax)            tasks per tile bucket (tile list)
+//   book[Tmax, 2Tmax)        tasks per tile bucket (range list)
+//   book[2Tmax, 3Tmax+1)     bucket offsets (tile list)
+//   book[3Tmax+1, 4Tmax+2)   bucket offsets (range list)
+//   ctr[0], ctr[1]           task totals; ctr[2], ctr[3] the kernels' cursors
 struct Task {
   int32_t h, t0, t1;
 };
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t tile_min,
-                                                    int32_t range_cap, Task* tiles, Task* ranges, int32_t* ctr) {
+                                                    int32_t range_cap, Task* tiles, Task* ranges, int32_t* book) {
   const int32_t nd = dense_rows(bins);
+  int32_t* cnt_t = book;
+  int32_t* cnt_r = book + Tmax;
   for (int h = blockIdx.x * BS + threadIdx.x; h < nd; h += gridDim.x * BS) {
     const int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
     int32_t r0 = -1, rlast = -1, racc = 0;
@@ -759,14 +815,14 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
       const int32_t c = o2[t + 1] - o2[t];
       if (c == 0) continue;
       if (c >= tile_min) {
-        if (r0 >= 0) ranges[atomicAdd(&ctr[1], 1)] = Task{h, r0, rlast + 1};
+        if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
         r0 = -1;
         racc = 0;
-        tiles[atomicAdd(&ctr[0], 1)] = Task{h, t, t + 1};
+        tiles[(int64_t)t * nd + atomicAdd(&cnt_t[t], 1)] = Task{h, t, t + 1};
         continue;
       }
       if (r0 >= 0 && racc + c > range_cap) {
-        ranges[atomicAdd(&ctr[1], 1)] = Task{h, r0, rlast + 1};
+        ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
         r0 = -1;
         racc = 0;
       }
@@ -774,8 +830,42 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
       rlast = t;
       racc += c;
     }
-    if (r0 >= 0) ranges[atomicAdd(&ctr[1], 1)] = Task{h, r0, rlast + 1};
+    if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
   }
+}
+
+// Exclusive scans of the two bucket-count arrays (one block) and the totals.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_task_offsets(int32_t* book, int32_t Tmax, int32_t* ctr) {
+  __shared__ int32_t s_wave[BS / kWave];
+  for (int list = 0; list < 2; ++list) {
+    const int32_t* cnt = book + list * Tmax;
+    int32_t* off = book + 2 * Tmax + list * (Tmax + 1);
+    int32_t carry = 0;
+    for (int t0 = 0; t0 < Tmax; t0 += BS) {
+      const int t = t0 + threadIdx.x;
+      const int32_t v = t < Tmax ? cnt[t] : 0;
+      int32_t tot;
+      const int32_t ex = block_excl_scan<BS / kWave, int32_t>(v, s_wave, &tot);
+      if (t < Tmax) off[t] = carry + ex;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) {
+      off[Tmax] = carry;
+      ctr[list] = carry;
+    }
+  }
+}
+
+// Task g of a bucketed list: its bucket is the last t with off[t] <= g.
+SG_DEV Task bucket_task(const Task* tasks, const int32_t* off, int32_t Tmax, int32_t nd, int32_t g) {
+  int lo = 0, hi = Tmax - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return tasks[(int64_t)lo * nd + (g - off[lo])];
 }
 
 // Dense-tile tasks: persistent workgroups take tasks from a global counter; a
@@ -784,7 +874,7 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
 // straight into C, and the touched slots are reset to the identity.
 template <class Sr, class Rows, int BS>
 __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, const int32_t* off2, const Task* tasks,
-                                                  int32_t* ctr, int32_t* err) {
+                                                  const int32_t* book, int32_t* ctr, int32_t* err) {
   using Src = typename Rows::Src;
   constexpr int NW = BS / kWave;
   static_assert(BS >= kTileWords, "one compaction word per thread");
@@ -801,13 +891,14 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t ntask = ctr[0];
+  const int32_t nd = dense_rows(bins);
   while (true) {
     if (threadIdx.x == 0) s_task = atomicAdd(&ctr[2], 1);
     __syncthreads();
     const int32_t task = s_task;
     __syncthreads();
     if (task >= ntask) break;
-    const Task tk = tasks[task];
+    const Task tk = bucket_task(tasks, book + 2 * Tmax, Tmax, nd, task);
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];
@@ -817,12 +908,14 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
     int64_t li;
     rows.get(i, s, li);
     const int64_t nsrc = s.bind(li, tk.t0, tk.t1);
-    auto body = [&](const Item& it, int64_t idx) {
-      const int32_t c = (int32_t)(s.col(it, idx) - c0);
-      Sr::lds_acc(&s_acc[c], s.template value<Sr>(it, idx));
-      atomicOr(&s_bm[c >> 5], 1u << (c & 31));
+    auto fetch = [&](const Item& it, int64_t idx) {
+      return ColVal<Acc>{(int32_t)(s.col(it, idx) - c0), s.template value<Sr>(it, idx)};
     };
-    for_each_product<BS>(s, nsrc, s_item, s_start, s_off, s_wave, body);
+    auto apply = [&](const ColVal<Acc>& p) {
+      Sr::lds_acc(&s_acc[p.c], p.v);
+      atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
+    };
+    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, fetch, apply);
     uint32_t bits = threadIdx.x < kTileWords ? s_bm[threadIdx.x] : 0u;
     int32_t tot;
     int32_t pos = block_excl_scan<NW, int32_t>(__popc(bits), (int32_t*)s_wave, &tot);
@@ -848,20 +941,22 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
 // Range tasks: persistent workgroups, one hash task per range of tiles.
 template <class Sr, class Rows, int LGS, int BS>
 __global__ __launch_bounds__(BS) void k_num_ranges(Rows rows, Bins bins, OutC C, const int32_t* off2,
-                                                   const Task* tasks, int32_t* ctr, int32_t* err) {
+                                                   const Task* tasks, const int32_t* book, int32_t* ctr,
+                                                   int32_t* err) {
   using Src = typename Rows::Src;
   __shared__ HashSmem<Sr, Src, LGS, BS> sm;
   __shared__ int32_t s_task;
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t ntask = ctr[1];
+  const int32_t nd = dense_rows(bins);
   while (true) {
     if (threadIdx.x == 0) s_task = atomicAdd(&ctr[3], 1);
     __syncthreads();
     const int32_t task = s_task;
     __syncthreads();
     if (task >= ntask) break;
-    const Task tk = tasks[task];
+    const Task tk = bucket_task(tasks, book + 3 * Tmax + 1, Tmax, nd, task);
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];

@@ -78,6 +78,13 @@ struct NumCtx {
   int comp_dense;  // float sums: dense rows use compensated accumulation
 };
 
+// Bytes of the dense-row task buffer: two task lists of task_cap entries and
+// the bucket bookkeeping (4*T + 2 ints) after them.
+inline size_t task_buffer_bytes(int64_t task_cap, int32_t T) {
+  return sizeof(Task) * 2 * (size_t)task_cap + sizeof(int32_t) * (4 * (size_t)T + 2);
+}
+inline int32_t* task_book(const NumCtx& c) { return (int32_t*)(c.tasks + 2 * c.task_cap); }
+
 template <class V, bool kVals>
 inline SpgemmSrc<V, kVals> make_spgemm_src(const RowSource& r) {
   SpgemmSrc<V, kVals> s{};
@@ -157,23 +164,26 @@ constexpr int kTileMinDefault = 1024; // entries that make a tile a dense-tile t
 template <class Sr, class Rows>
 inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) {
   if (c.plan.ndense() == 0) return;
+  int32_t* book = task_book(c);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, c.task_ctr, (int64_t)4, (int32_t)0);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(2 * (int64_t)rows.Tmax, 256, 1024)), dim3(256), 0, st, book,
+                     2 * (int64_t)rows.Tmax, (int32_t)0);
   hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
-                     c.plan.bins, c.off2, rows.Tmax, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
-                     c.task_ctr);
+                     c.plan.bins, c.off2, rows.Tmax, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap, book);
+  hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, rows.Tmax, c.task_ctr);
   // 8-byte accumulators need the whole LDS for one 16384-slot tile: use a
   // 1024-thread workgroup (16 waves) when the per-source items are small.
   constexpr int BS =
       (sizeof(typename Sr::Acc) >= 8 && sizeof(typename Rows::Src::Item) <= 8) ? 1024 : 512;
   auto k = k_num_tiles<Sr, Rows, BS>;
   static int occ = occupancy(k, BS);
-  hipLaunchKernelGGL(k, dim3(c.cus * occ), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks, c.task_ctr,
-                     c.err);
+  hipLaunchKernelGGL(k, dim3(c.cus * occ), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks,
+                     (const int32_t*)book, c.task_ctr, c.err);
   constexpr int RBS = sizeof(typename Sr::Acc) >= 8 ? 256 : 512;
   auto k2 = k_num_ranges<Sr, Rows, kRangeLg, RBS>;
   static int occ2 = occupancy(k2, RBS);
   hipLaunchKernelGGL(k2, dim3(c.cus * occ2), dim3(RBS), 0, st, rows, c.plan.bins, c.C, c.off2,
-                     c.tasks + c.task_cap, c.task_ctr, c.err);
+                     c.tasks + c.task_cap, (const int32_t*)book, c.task_ctr, c.err);
 }
 
 // Numeric pass for semiring Sr (SrC: its compensated variant, or Sr).
@@ -205,9 +215,13 @@ inline void launch_numeric(const NumCtx& c, hipStream_t st) {
 // ---- entry points implemented in the .hip translation units -------------------------
 
 // k_struct.hip
-void launch_analyze(const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p, uint8_t* bin,
-                    int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count, int32_t* list,
-                    int64_t* cnt_out, hipStream_t st);
+void launch_analyze(const RowSource& r, const Policy& pol, const int64_t* c_rowptr, int64_t* p, int32_t* nt,
+                    uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                    int32_t* list, int64_t* cnt_out, hipStream_t st);
+// Numeric binning from the symbolic pass's per-row products p and terms nt.
+void launch_rebin(const int64_t* p, const int32_t* nt, const int64_t* c_rowptr, int64_t nrows, const Policy& pol,
+                  uint8_t* bin, int32_t* hist, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                  int32_t* list, hipStream_t st);
 int64_t analyze_blocks(int64_t nrows);
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,
                         hipStream_t st);
