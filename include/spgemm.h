@@ -115,8 +115,10 @@ sg_status sg_handle_destroy(sg_handle* h);
  * more products take the column-tiled dense path; <= 4096), "force_path"
  * ("auto", "small", "hash", "dense": route every row that the path can take
  * through it), "validate" (0/1), "timing" (0/1: record per-phase HIP events,
- * see sg_handle_timings).  Returns SG_ERR_INVALID for an unknown name or a
- * bad value. */
+ * see sg_handle_timings), "dense_tile_min" (1..2048: a dense row's column tile
+ * with at least this many output entries is accumulated in a dense LDS array,
+ * smaller ones in an LDS hash table).  Returns SG_ERR_INVALID for an unknown
+ * name or a bad value. */
 sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value);
 
 /* Pass 1 of C = A (x).(+) B (structure only; independent of the semiring).
@@ -130,7 +132,10 @@ sg_status sg_spgemm_symbolic(sg_handle* h, const sg_csr* A, const sg_csr* B, int
 /* Pass 2: fills C->col and C->val (device, caller-allocated with nnz(C)
  * entries) given C->rowptr from pass 1 on the same A and B.  Rows of C come
  * out sorted by column.  Does not wait for `stream`.  C->nrows must equal
- * A.nrows, C->ncols B.ncols, C->nnz the value pass 1 returned. */
+ * A.nrows, C->ncols B.ncols, C->nnz the value pass 1 returned.  When A and B
+ * are the arrays of the handle's last pass 1, their row offsets and column
+ * ids must be unchanged since then (values may change): the saved per-row
+ * product counts and dense-row tile offsets are reused. */
 sg_status sg_spgemm_numeric(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, sg_csr* C,
                             void* stream);
 

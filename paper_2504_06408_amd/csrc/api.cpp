@@ -171,6 +171,7 @@ SgCacheKey product_key(const sg_handle* h, const sg_csr* A, const sg_csr* B) {
   k.w[10] = (uint64_t)B->nnz;
   k.w[11] = (uint64_t)h->force;
   k.w[12] = (uint64_t)h->hash_max;
+  k.w[13] = (uint64_t)h->slab;
   return k;
 }
 
@@ -200,6 +201,38 @@ sg_status upload_parts(sg_handle* h, int nparts, const sg_csr* parts, hipStream_
   return SG_OK;
 }
 
+// Column-slab partition of B for the dense rows of a single product: with
+// cols, the bounds, segment starts and column ids (kept for the numeric pass
+// on the same structure); with vals, the partitioned values (vbytes each).
+sg_status build_slabs(sg_handle* h, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
+                      int64_t* partial, hipStream_t st) {
+  const int32_t ls = slab_log(r.ncols), S = slab_count(r.ncols, ls);
+  const int64_t nb = B->nrows;
+  const size_t ne = (size_t)(B->nnz > 0 ? B->nnz : 1);
+  if (cols) {
+    SG_HIP(h, h->bnd_buf.ensure(sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
+    SG_HIP(h, h->prow_buf.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
+    SG_HIP(h, h->pcol_buf.ensure(sizeof(int32_t) * ne));
+  }
+  if (vals) SG_HIP(h, h->pval_buf.ensure((size_t)vbytes * ne));
+  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, ls, S, (int32_t*)h->bnd_buf.p,
+                        (int64_t*)h->prow_buf.p, partial, (int32_t*)h->pcol_buf.p, vals ? h->pval_buf.p : nullptr,
+                        cols, vals, h->d_flags, h->cus, st);
+  r.prow = (const int64_t*)h->prow_buf.p;
+  r.pcol = (const int32_t*)h->pcol_buf.p;
+  r.pval = vals ? h->pval_buf.p : nullptr;
+  r.ls = ls;
+  r.S = S;
+  r.qctr = h->d_flags + kCtrBase;
+  return SG_OK;
+}
+
+size_t slab_partials(const sg_handle* h, const RowSource& r) {
+  if (r.mode != kModeProduct || !h->slab) return 0;
+  const int32_t ls = slab_log(r.ncols);
+  return (size_t)scan_partials_len((int64_t)slab_count(r.ncols, ls) * r.b_nrows);
+}
+
 // Shared body of the two symbolic entry points: counts into C_rowptr[1..n],
 // dense-row tile offsets into the handle's cache, scan, readback of nnz.
 sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_rowptr, int64_t* nnzC,
@@ -208,6 +241,7 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   SgArena measure;
   measure.off = plan_rows_bytes(n);
   measure.take<int64_t>(scan_partials_len(n));
+  measure.take<int64_t>(slab_partials(h, r));
   SG_HIP(h, h->ws.ensure(measure.off));
   SgArena ar;
   ar.base = (char*)h->ws.p;
@@ -222,21 +256,24 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   mk.mark(kPhSymAnalyze, 0);
   const int32_t nd = plan.ndense();
   int32_t* off2 = nullptr;
+  int64_t* partial = ar.take<int64_t>(scan_partials_len(n));
+  int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
   if (nd > 0) {
-    if (r.mode == kModeProduct && r.T > 1) {
-      SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
-      r.rp2 = (const int32_t*)h->rp2_buf.p;
-      mk.mark(kPhSymBounds, 1);
-      launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
-      mk.mark(kPhSymBounds, 0);
-    }
+    const bool tiles = r.mode == kModeProduct && r.T > 1;
+    if (tiles) SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
     SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
     off2 = (int32_t*)h->off2_buf.p;
+    mk.mark(kPhSymBounds, 1);
+    if (tiles) {
+      r.rp2 = (const int32_t*)h->rp2_buf.p;
+      launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
+    }
+    if (r.mode == kModeProduct && h->slab) SG_TRY(build_slabs(h, r, B, 0, true, false, spartial, st));
+    mk.mark(kPhSymBounds, 0);
   }
   launch_symbolic(r, plan, C_rowptr + 1, off2, h->cus, mk, st);
   mk.mark(kPhSymScan, 1);
   launch_fill_i64(C_rowptr, 1, 0, st);
-  int64_t* partial = ar.take<int64_t>(scan_partials_len(n));
   launch_scan_inclusive(C_rowptr + 1, n, partial, st);
   mk.mark(kPhSymScan, 0);
   SG_HIP(h, hipGetLastError());
@@ -257,6 +294,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   SgArena measure;
   measure.off = plan_rows_bytes(n);
   measure.take<int64_t>(n);
+  measure.take<int64_t>(slab_partials(h, r));
   SG_HIP(h, h->ws.ensure(measure.off));
   SgArena ar;
   ar.base = (char*)h->ws.p;
@@ -284,6 +322,11 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
       }
       r.rp2 = (const int32_t*)h->rp2_buf.p;
     }
+    if (r.mode == kModeProduct && h->slab) {
+      // structure from the last symbolic pass when cached; values every call
+      int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
+      SG_TRY(build_slabs(h, r, B, sr->value_bytes, !cached, true, spartial, st));
+    }
     if (!cached) {
       SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
       int64_t* scratch = ar.take<int64_t>(n);
@@ -298,7 +341,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.C = OutC{C->rowptr, C->col, C->val};
   c.off2 = (const int32_t*)h->off2_buf.p;
   c.err = h->d_flags;
-  c.task_ctr = h->d_flags + 8;
+  c.task_ctr = h->d_flags + kCtrBase;
   c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;
   SG_HIP(h, h->task_buf.ensure(task_buffer_bytes(c.task_cap, r.T)));
   c.tasks = (Task*)h->task_buf.p;
@@ -354,6 +397,9 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
       return sg_fail(h, SG_ERR_INVALID, "dense_tile_min must be in [1, 2048]");
     h->tile_min = (int32_t)x;
     return SG_OK;
+  } else if (n == "dense_slab") {
+    if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "dense_slab must be 0 or 1");
+    h->slab = v == "1";
   } else if (n == "force_path") {
     if (v == "auto") h->force = kForceAuto;
     else if (v == "small") h->force = kForceSmall;
@@ -397,11 +443,11 @@ sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out)
     return SG_ERR_HIP;
   }
   h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  if (hipMalloc(&h->d_flags, 64 * sizeof(int32_t)) != hipSuccess) {
+  if (hipMalloc(&h->d_flags, kFlagInts * sizeof(int32_t)) != hipSuccess) {
     delete h;
     return SG_ERR_NOMEM;
   }
-  (void)hipMemset(h->d_flags, 0, 64 * sizeof(int32_t));
+  (void)hipMemset(h->d_flags, 0, kFlagInts * sizeof(int32_t));
   if (hipHostMalloc(&h->h_pin, 4096, hipHostMallocDefault) != hipSuccess) {
     (void)hipFree(h->d_flags);
     delete h;
@@ -441,6 +487,10 @@ sg_status sg_handle_destroy(sg_handle* h) {
   h->task_buf.release();
   h->p_buf.release();
   h->nt_buf.release();
+  h->bnd_buf.release();
+  h->prow_buf.release();
+  h->pcol_buf.release();
+  h->pval_buf.release();
   h->rp2_buf.release();
   h->off2_buf.release();
   h->parts_buf.release();

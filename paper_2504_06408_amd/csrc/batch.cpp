@@ -114,7 +114,7 @@ struct sg_plan {
   int64_t *d_rbase_p = nullptr, *d_rbase_m = nullptr, *d_lbase_p = nullptr, *d_lbase_m = nullptr;
   int64_t *d_lrow_p = nullptr, *d_lrow_m = nullptr;
   int64_t ltot_p = 0, ltot_m = 0;
-  int32_t* d_flag = nullptr;  // [0] pool overflow, [1] consistency, [4..7] task counters
+  int32_t* d_flag = nullptr;  // [0] pool overflow, [1] consistency, [kCtrBase, ...) task counters
   std::vector<SgBuf> rp2;     // one per distinct B with more than one column tile
   std::vector<std::tuple<const int64_t*, const int32_t*, int64_t, int32_t, int32_t*>> bounds;  // B rows -> rp2
   Stage prod, merg;
@@ -193,7 +193,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   c.C = OutC{S.off, (int32_t*)S.col_buf.p, S.val_buf.p};
   c.off2 = (const int32_t*)S.off2_buf.p;
   c.err = P->d_flag + 1;
-  c.task_ctr = P->d_flag + 4;
+  c.task_ctr = P->d_flag + kCtrBase;
   c.task_cap = (int64_t)(S.nd > 0 ? S.nd : 1) * S.src.T;
   c.tasks = (Task*)S.task_buf.p;
   c.tile_min = h->tile_min;
@@ -254,7 +254,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   m.take<int64_t>((size_t)ng + 1);
   m.take<int64_t>((size_t)P->ltot_p);
   m.take<int64_t>((size_t)(P->ltot_m > 0 ? P->ltot_m : 1));
-  m.take<int32_t>(8);
+  m.take<int32_t>(kFlagInts);
   SG_HIP(h, P->tables.ensure(m.off));
   SgArena a;
   a.base = (char*)P->tables.p;
@@ -267,7 +267,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   P->d_lbase_m = a.take<int64_t>((size_t)ng + 1);
   P->d_lrow_p = a.take<int64_t>((size_t)P->ltot_p);
   P->d_lrow_m = a.take<int64_t>((size_t)(P->ltot_m > 0 ? P->ltot_m : 1));
-  P->d_flag = a.take<int32_t>(8);
+  P->d_flag = a.take<int32_t>(kFlagInts);
 
   // distinct B operands that need column-tile bounds
   std::map<std::tuple<const int64_t*, const int32_t*, int64_t>, int32_t*> seen;

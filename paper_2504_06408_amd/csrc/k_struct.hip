@@ -46,14 +46,14 @@ __global__ __launch_bounds__(1024) void k_bin_offsets(const int32_t* hist, int32
 // Per B row, rp2[k*(T+1) + t] = number of entries of row k with column below
 // t*16384 (t = 0..T).  One wavefront per row, lanes over t, binary search.
 __global__ __launch_bounds__(256) void k_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows,
-                                                     int32_t T, int32_t* rp2) {
+                                                     int32_t T, int32_t lg, int32_t* rp2) {
   const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * 256) >> 6;
   for (int64_t k = w0; k < nrows; k += nw) {
     const int64_t s = rowptr[k], e = rowptr[k + 1];
     int32_t* r = rp2 + k * (T + 1);
     for (int t = lane_id(); t <= T; t += kWave) {
-      const int64_t pos = (t == 0) ? s : (t == T ? e : lower_bound_col(col, s, e, (int64_t)t << kTileLog));
+      const int64_t pos = (t == 0) ? s : (t == T ? e : lower_bound_col(col, s, e, (int64_t)t << lg));
       r[t] = (int32_t)(pos - s);
     }
   }
@@ -142,7 +142,7 @@ void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int
 
 template <class Rows>
 void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
-                   const Marks& marks, hipStream_t st) {
+                   const Marks& marks, hipStream_t st, bool dense) {
   marks.mark(kPhSymSmall, 1);
   if (plan.count[kBinSmall]) {
     auto k = k_sym_small<Rows>;
@@ -160,10 +160,34 @@ void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int3
   sym_hash_one<Rows, 12, 512>(rows, plan, kBinHash0 + 5, cnt_out, cus, st);
   sym_hash_one<Rows, 13, 512>(rows, plan, kBinHash0 + 6, cnt_out, cus, st);
   marks.mark(kPhSymHash, 0);
+  if (!dense) return;
   marks.mark(kPhSymDense, 1);
   sym_dense_rows(rows, plan, cnt_out, off2, cus, st);
   marks.mark(kPhSymDense, 0);
 }
+
+// Dense rows of a single product over the column-slab partition.
+void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus, hipStream_t st) {
+  const int nd = plan.ndense();
+  if (nd == 0) return;
+  using Src = SlabSrc<uint8_t, false>;
+  Src s{};
+  s.a_rowptr = r.a_rowptr;
+  s.a_col = r.a_col;
+  s.prow = r.prow;
+  s.pcol = r.pcol;
+  s.nb = r.b_nrows;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, r.qctr, (int64_t)kCtrInts,
+                     (int32_t)0);
+  auto k = k_sym_slab<Src, 512>;
+  static int occ = occupancy(k, 512);
+  const int grid = cus * occ > kQueues ? cus * occ : kQueues;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, s, plan.bins, r.S, r.ls, r.T, r.T, off2, r.qctr);
+  hipLaunchKernelGGL(k_off2_finish<256>, dim3(grid_for(nd, 4, cus * 16)), dim3(256), 0, st, plan.bins, off2, r.T, r.T,
+                     cnt_out);
+}
+
+bool use_slab(const RowSource& r) { return r.mode == kModeProduct && r.S > 0; }
 
 __global__ __launch_bounds__(256) void k_validate(const int64_t* rowptr, const int32_t* col, int64_t nrows,
                                                   int64_t ncols, int64_t nnz, int32_t* flag) {
@@ -208,16 +232,64 @@ void launch_rebin(const int64_t* p, const int32_t* nt, const int64_t* c_rowptr, 
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,
                         hipStream_t st) {
   if (nrows == 0) return;
-  hipLaunchKernelGGL(k_tile_bounds, dim3(grid_for(nrows, 4, cus * 16)), dim3(256), 0, st, rowptr, col, nrows, T, rp2);
+  hipLaunchKernelGGL(k_tile_bounds, dim3(grid_for(nrows, 4, cus * 16)), dim3(256), 0, st, rowptr, col, nrows, T,
+                     (int32_t)kTileLog, rp2);
+}
+
+template <class V>
+void slab_scatter(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int64_t nb, int32_t ls,
+                  int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pcol, void* pval, bool cols, bool vals,
+                  int32_t* err, int cus, hipStream_t st) {
+  const dim3 g(grid_for(nb, 4, cus * 16)), b(256);
+  const V* bv = (const V*)b_val;
+  V* pv = (V*)pval;
+  if (cols && vals)
+    hipLaunchKernelGGL((k_slab_scatter<V, true, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow, pcol,
+                       pv, err);
+  else if (cols)
+    hipLaunchKernelGGL((k_slab_scatter<V, true, false>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
+                       pcol, pv, err);
+  else if (vals)
+    hipLaunchKernelGGL((k_slab_scatter<V, false, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
+                       pcol, pv, err);
+}
+
+void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
+                           int32_t ls, int32_t S, int32_t* bnd, int64_t* prow, int64_t* partial, int32_t* pcol,
+                           void* pval, bool cols, bool vals, int32_t* err, int cus, hipStream_t st) {
+  if (nb <= 0) return;
+  if (cols) {
+    hipLaunchKernelGGL(k_tile_bounds, dim3(grid_for(nb, 4, cus * 16)), dim3(256), 0, st, b_rowptr, b_col, nb, S, ls,
+                       bnd);
+    hipLaunchKernelGGL(k_slab_counts<256>, dim3(grid_for((int64_t)S * nb, 256, cus * 16)), dim3(256), 0, st,
+                       (const int32_t*)bnd, nb, S, prow);
+    launch_scan_inclusive(prow + 1, (int64_t)S * nb, partial, st);
+  }
+  switch (vbytes) {
+    case 1: slab_scatter<uint8_t>(b_rowptr, b_col, b_val, nb, ls, S, bnd, prow, pcol, pval, cols, vals, err, cus, st); break;
+    case 4: slab_scatter<uint32_t>(b_rowptr, b_col, b_val, nb, ls, S, bnd, prow, pcol, pval, cols, vals, err, cus, st); break;
+    default: slab_scatter<uint64_t>(b_rowptr, b_col, b_val, nb, ls, S, bnd, prow, pcol, pval, cols, vals, err, cus, st); break;
+  }
 }
 
 void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                      const Marks& marks, hipStream_t st) {
-  with_rows<uint8_t, false>(r, [&](const auto& rows) { symbolic_rows(rows, plan, cnt_out, off2, cus, marks, st); });
+  const bool slab = use_slab(r);
+  with_rows<uint8_t, false>(r,
+                            [&](const auto& rows) { symbolic_rows(rows, plan, cnt_out, off2, cus, marks, st, !slab); });
+  if (slab) {
+    marks.mark(kPhSymDense, 1);
+    sym_slab(r, plan, cnt_out, off2, cus, st);
+    marks.mark(kPhSymDense, 0);
+  }
 }
 
 void launch_symbolic_dense(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                            hipStream_t st) {
+  if (use_slab(r)) {
+    sym_slab(r, plan, cnt_out, off2, cus, st);
+    return;
+  }
   with_rows<uint8_t, false>(r, [&](const auto& rows) { sym_dense_rows(rows, plan, cnt_out, off2, cus, st); });
 }
 

@@ -10,6 +10,11 @@
 #include "../../include/spgemm.h"
 #include "sg_launch.hpp"
 
+// Device flag block of a handle or plan: error flags in the first ints, the
+// task-queue counter block (sg::kCtrInts ints) from kCtrBase.
+constexpr int kCtrBase = 256;
+constexpr int kFlagInts = kCtrBase + sg::kCtrInts;
+
 // Grow-only device buffer.
 struct SgBuf {
   void* p = nullptr;
@@ -73,13 +78,16 @@ struct sg_handle {
   SgBuf parts_buf;           // device table of merge parts
   SgBuf task_buf;            // dense-row task lists of the numeric pass
   SgBuf p_buf, nt_buf;       // per-row products and terms from symbolic, reused to re-bin numeric
+  SgBuf bnd_buf, prow_buf;   // column-slab partition of B: per-row slab bounds, segment starts
+  SgBuf pcol_buf, pval_buf;  //   and the partitioned entries
+  int slab = 1;              // dense rows of single products use the column-slab path
   int32_t tile_min = sg::kTileMinDefault;
   std::vector<sg::PartDesc> parts_host;
   bool cache_valid = false;
   SgCacheKey cache_key{};
   int32_t cache_T = 0, cache_nd = 0;
   int64_t cache_n = -1;
-  int32_t* d_flags = nullptr;  // [0] consistency error, [2] validation, [8..11] task counters
+  int32_t* d_flags = nullptr;  // kFlagInts: [0] consistency error, [2] validation, task counters from kCtrBase
   int64_t* h_pin = nullptr;    // pinned readback area (>= 256 int64)
 };
 

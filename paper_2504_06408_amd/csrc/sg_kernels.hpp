@@ -784,63 +784,122 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
   }
 }
 
+// ---- persistent work distribution -------------------------------------------
+// Task lists are served through kQueues interleaved queues: task g belongs to
+// queue g % kQueues, workgroup b serves queue b % kQueues (consecutive
+// workgroups are dispatched round-robin over gfx950's 8 XCDs, so a queue's
+// workgroups share one L2) and takes kGrab consecutive queue slots per atomic.
+// Counter block layout (int32, zeroed before each use):
+//   [0, 3)                      totals of the tile, range and slab task lists
+//   kCtrQueue0 + (l*kQueues + q)*kCtrStride   queue q of list l (l = 3: slab symbolic)
+constexpr int kQueues = 8;
+constexpr int kGrab = 4;
+constexpr int kCtrStride = 16;  // 64 bytes between counters
+constexpr int kCtrQueue0 = 64;
+constexpr int kCtrLists = 4;
+constexpr int kCtrInts = kCtrQueue0 + kCtrLists * kQueues * kCtrStride;
+enum { kListTile = 0, kListRange = 1, kListSlab = 2, kListSymSlab = 3 };
+
+SG_DEV int32_t* queue_ctr(int32_t* ctr, int list, int q) {
+  return ctr + kCtrQueue0 + (list * kQueues + q) * kCtrStride;
+}
+
+// Calls task(g) for every task g < ntask of this workgroup's queue.  All
+// threads of the block call it; task() must be block-uniform.
+template <class F>
+SG_DEV void for_each_queued(int32_t* ctr, int list, int64_t ntask, int64_t* s_slot, F&& task) {
+  const int q = (int)(blockIdx.x % kQueues);
+  int32_t* qc = queue_ctr(ctr, list, q);
+  const int64_t nq = ntask > q ? (ntask - q + kQueues - 1) / kQueues : 0;
+  while (true) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(qc, kGrab);
+    __syncthreads();
+    const int64_t j0 = *s_slot;
+    __syncthreads();
+    if (j0 >= nq) break;
+    const int64_t j1 = (j0 + kGrab) < nq ? (j0 + kGrab) : nq;
+    for (int64_t j = j0; j < j1; ++j) task(q + j * kQueues);
+  }
+}
+
 // Numeric dense-row work is cut into tasks from the symbolic pass's per-tile
-// counts: a tile holding at least tile_min entries becomes a dense-tile task
-// (dense LDS accumulator, written in column order without a sort); runs of
-// sparser tiles are grouped into range tasks of at most range_cap entries
-// (LDS hash + radix sort).  One thread per dense row puts its tasks into
-// per-tile buckets (bucket t of a list holds nd slots; a range goes to the
-// bucket of its first tile); the task kernels then walk the buckets in tile
-// order, so at any time all workgroups gather from the same narrow column
-// slice of B and it stays cache resident.
-//   book[0, Tmax)            tasks per tile bucket (tile list)
-//   book[Tmax, 2Tmax)        tasks per tile bucket (range list)
-//   book[2Tmax, 3Tmax+1)     bucket offsets (tile list)
-//   book[3Tmax+1, 4Tmax+2)   bucket offsets (range list)
-//   ctr[0], ctr[1]           task totals; ctr[2], ctr[3] the kernels' cursors
+// counts.  With column slabs of G tiles (G > 0: single products), a slab
+// holding at most slab_cap entries becomes one slab task (bitmap + rank
+// accumulator over the slab).  Other tiles: a tile holding at least tile_min
+// entries becomes a dense-tile task (dense LDS accumulator, written in column
+// order with no sort); runs of sparser tiles inside one slab are grouped into
+// range tasks of at most range_cap entries (LDS hash + radix sort).  One
+// thread per dense row puts its tasks into per-bucket slots (bucket t of a
+// list holds nd slots; tile and range tasks go to the bucket of their first
+// tile, slab tasks to their slab); the task kernels walk the buckets in
+// order, so all workgroups gather from one narrow column slice of B at a
+// time and it stays cache resident.
+//   book[l*Tmax + t]                    tasks in bucket t of list l (l = 0, 1, 2)
+//   book[3*Tmax + l*(Tmax+1) + t]       bucket offsets of list l
+//   ctr[l]                              task total of list l
 struct Task {
   int32_t h, t0, t1;
 };
 
+__host__ __device__ inline int32_t* book_off(int32_t* book, int32_t Tmax, int list) {
+  return book + 3 * Tmax + list * (Tmax + 1);
+}
+__host__ __device__ inline const int32_t* book_off(const int32_t* book, int32_t Tmax, int list) {
+  return book + 3 * Tmax + list * (Tmax + 1);
+}
+
 template <int BS>
-__global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t tile_min,
-                                                    int32_t range_cap, Task* tiles, Task* ranges, int32_t* book) {
+__global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t G,
+                                                    int32_t slab_cap, int32_t tile_min, int32_t range_cap,
+                                                    Task* tiles, Task* ranges, Task* slabs, int32_t* book) {
   const int32_t nd = dense_rows(bins);
   int32_t* cnt_t = book;
   int32_t* cnt_r = book + Tmax;
+  int32_t* cnt_s = book + 2 * Tmax;
+  const int32_t span = G > 0 ? G : Tmax;
   for (int h = blockIdx.x * BS + threadIdx.x; h < nd; h += gridDim.x * BS) {
     const int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
-    int32_t r0 = -1, rlast = -1, racc = 0;
-    for (int t = 0; t < Tmax; ++t) {
-      const int32_t c = o2[t + 1] - o2[t];
-      if (c == 0) continue;
-      if (c >= tile_min) {
-        if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
-        r0 = -1;
-        racc = 0;
-        tiles[(int64_t)t * nd + atomicAdd(&cnt_t[t], 1)] = Task{h, t, t + 1};
+    for (int32_t ta = 0; ta < Tmax; ta += span) {
+      const int32_t tb = (ta + span) < Tmax ? (ta + span) : Tmax;
+      const int32_t ms = o2[tb] - o2[ta];
+      if (ms == 0) continue;
+      if (G > 0 && ms <= slab_cap) {
+        const int32_t s = ta / G;
+        slabs[(int64_t)s * nd + atomicAdd(&cnt_s[s], 1)] = Task{h, ta, tb};
         continue;
       }
-      if (r0 >= 0 && racc + c > range_cap) {
-        ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
-        r0 = -1;
-        racc = 0;
+      int32_t r0 = -1, rlast = -1, racc = 0;
+      for (int t = ta; t < tb; ++t) {
+        const int32_t c = o2[t + 1] - o2[t];
+        if (c == 0) continue;
+        if (c >= tile_min) {
+          if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
+          r0 = -1;
+          racc = 0;
+          tiles[(int64_t)t * nd + atomicAdd(&cnt_t[t], 1)] = Task{h, t, t + 1};
+          continue;
+        }
+        if (r0 >= 0 && racc + c > range_cap) {
+          ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
+          r0 = -1;
+          racc = 0;
+        }
+        if (r0 < 0) r0 = t;
+        rlast = t;
+        racc += c;
       }
-      if (r0 < 0) r0 = t;
-      rlast = t;
-      racc += c;
+      if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
     }
-    if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
   }
 }
 
-// Exclusive scans of the two bucket-count arrays (one block) and the totals.
+// Exclusive scans of the three bucket-count arrays (one block) and the totals.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_task_offsets(int32_t* book, int32_t Tmax, int32_t* ctr) {
   __shared__ int32_t s_wave[BS / kWave];
-  for (int list = 0; list < 2; ++list) {
+  for (int list = 0; list < 3; ++list) {
     const int32_t* cnt = book + list * Tmax;
-    int32_t* off = book + 2 * Tmax + list * (Tmax + 1);
+    int32_t* off = book_off(book, Tmax, list);
     int32_t carry = 0;
     for (int t0 = 0; t0 < Tmax; t0 += BS) {
       const int t = t0 + threadIdx.x;
@@ -885,20 +944,14 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
   __shared__ uint32_t s_bm[kTileWords];
   __shared__ Item s_item[BS];
   __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
-  __shared__ int32_t s_task;
+  __shared__ int64_t s_slot;
   for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
   for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
-  const int32_t ntask = ctr[0];
   const int32_t nd = dense_rows(bins);
-  while (true) {
-    if (threadIdx.x == 0) s_task = atomicAdd(&ctr[2], 1);
-    __syncthreads();
-    const int32_t task = s_task;
-    __syncthreads();
-    if (task >= ntask) break;
-    const Task tk = bucket_task(tasks, book + 2 * Tmax, Tmax, nd, task);
+  for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &s_slot, [&](int64_t g) {
+    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListTile), Tmax, nd, (int32_t)g);
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];
@@ -935,7 +988,7 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
       s_bm[threadIdx.x] = 0u;
     }
     __syncthreads();
-  }
+  });
 }
 
 // Range tasks: persistent workgroups, one hash task per range of tiles.
@@ -945,18 +998,12 @@ __global__ __launch_bounds__(BS) void k_num_ranges(Rows rows, Bins bins, OutC C,
                                                    int32_t* err) {
   using Src = typename Rows::Src;
   __shared__ HashSmem<Sr, Src, LGS, BS> sm;
-  __shared__ int32_t s_task;
+  __shared__ int64_t s_slot;
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
-  const int32_t ntask = ctr[1];
   const int32_t nd = dense_rows(bins);
-  while (true) {
-    if (threadIdx.x == 0) s_task = atomicAdd(&ctr[3], 1);
-    __syncthreads();
-    const int32_t task = s_task;
-    __syncthreads();
-    if (task >= ntask) break;
-    const Task tk = bucket_task(tasks, book + 3 * Tmax + 1, Tmax, nd, task);
+  for_each_queued(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, [&](int64_t g) {
+    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g);
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];
@@ -964,7 +1011,7 @@ __global__ __launch_bounds__(BS) void k_num_ranges(Rows rows, Bins bins, OutC C,
     int64_t li;
     rows.get(i, s, li);
     hash_task<Sr, Src, LGS, BS>(sm, s, li, tk.t0, tk.t1, C.rowptr[i] + lo, hi - lo, C, err);
-  }
+  });
 }
 
 }  // namespace sg

@@ -6,7 +6,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sg_kernels.hpp"
+#include "sg_slab.hpp"
 
 namespace sg {
 
@@ -36,6 +39,12 @@ struct RowSource {
   int64_t nrows;  // (global) rows
   int64_t ncols;  // columns of C (single modes)
   int32_t T;      // column tiles (single modes) or the largest over the batch
+  // column-slab partition of B (single product; S = 0: not used)
+  const int64_t* prow;
+  const int32_t* pcol;
+  const void* pval;
+  int32_t ls, S;
+  int32_t* qctr;  // counter block (kCtrInts ints) of the slab symbolic pass
 };
 
 struct BinPlan {
@@ -70,20 +79,31 @@ struct NumCtx {
   OutC C;
   const int32_t* off2;
   int32_t* err;
-  int32_t* task_ctr;  // 4 counters: tile tasks, range tasks, and their cursors
-  Task* tasks;        // tile tasks [0, task_cap), range tasks [task_cap, 2*task_cap)
+  int32_t* task_ctr;  // counter block of kCtrInts ints (list totals, queue cursors)
+  Task* tasks;        // tile, range and slab task lists of task_cap entries each
   int64_t task_cap;   // >= dense rows x tiles
   int32_t tile_min;
   int cus;
   int comp_dense;  // float sums: dense rows use compensated accumulation
 };
 
-// Bytes of the dense-row task buffer: two task lists of task_cap entries and
-// the bucket bookkeeping (4*T + 2 ints) after them.
+// Bytes of the dense-row task buffer: three task lists of task_cap entries
+// and the bucket bookkeeping (6*T + 3 ints) after them.
 inline size_t task_buffer_bytes(int64_t task_cap, int32_t T) {
-  return sizeof(Task) * 2 * (size_t)task_cap + sizeof(int32_t) * (4 * (size_t)T + 2);
+  return sizeof(Task) * 3 * (size_t)task_cap + sizeof(int32_t) * (6 * (size_t)T + 3);
 }
-inline int32_t* task_book(const NumCtx& c) { return (int32_t*)(c.tasks + 2 * c.task_cap); }
+inline int32_t* task_book(const NumCtx& c) { return (int32_t*)(c.tasks + 3 * c.task_cap); }
+
+// Slab width 2^ls for a product with ncols columns: about an eighth of the
+// columns, clamped to 1..8 column tiles.
+inline int32_t slab_log(int64_t ncols) {
+  int32_t ls = kSlabLogMin;
+  while (ls < kSlabLogMax && ((int64_t)1 << ls) * 8 < ncols) ++ls;
+  return ls;
+}
+inline int32_t slab_count(int64_t ncols, int32_t ls) {
+  return (int32_t)((ncols + ((int64_t)1 << ls) - 1) >> ls);
+}
 
 template <class V, bool kVals>
 inline SpgemmSrc<V, kVals> make_spgemm_src(const RowSource& r) {
@@ -164,25 +184,54 @@ constexpr int kTileMinDefault = 1024; // entries that make a tile a dense-tile t
 template <class Sr, class Rows>
 inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) {
   if (c.plan.ndense() == 0) return;
+  using V = typename Sr::V;
+  constexpr bool kProduct = std::is_same_v<Rows, OneRows<SpgemmSrc<V, true>>>;
+  const bool slab = kProduct && c.src.mode == kModeProduct && c.src.S > 0;
+  const int32_t G = slab ? (1 << (c.src.ls - kTileLog)) : 0;
+  constexpr int kSlabCap = slab_cap<Sr>();
   int32_t* book = task_book(c);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, c.task_ctr, (int64_t)4, (int32_t)0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(2 * (int64_t)rows.Tmax, 256, 1024)), dim3(256), 0, st, book,
-                     2 * (int64_t)rows.Tmax, (int32_t)0);
+  const int32_t Tmax = rows.Tmax;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, c.task_ctr,
+                     (int64_t)kCtrInts, (int32_t)0);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)Tmax, 256, 1024)), dim3(256), 0, st, book,
+                     3 * (int64_t)Tmax, (int32_t)0);
   hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
-                     c.plan.bins, c.off2, rows.Tmax, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap, book);
-  hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, rows.Tmax, c.task_ctr);
+                     c.plan.bins, c.off2, Tmax, G, kSlabCap, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
+                     c.tasks + 2 * c.task_cap, book);
+  hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, Tmax, c.task_ctr);
+  if constexpr (kProduct) {
+    if (slab) {
+      using Src = SlabSrc<V, true>;
+      Src s{};
+      s.a_rowptr = c.src.a_rowptr;
+      s.a_col = c.src.a_col;
+      s.a_val = (const V*)c.src.a_val;
+      s.prow = c.src.prow;
+      s.pcol = c.src.pcol;
+      s.pval = (const V*)c.src.pval;
+      s.nb = c.src.b_nrows;
+      auto k = k_num_slab<Sr, Src, 512, kSlabCap>;
+      static int occ = occupancy(k, 512);
+      const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
+      hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, s, c.plan.bins, c.C, c.off2, Tmax, c.src.ls,
+                         (const Task*)(c.tasks + 2 * c.task_cap), (const int32_t*)book_off(book, Tmax, kListSlab),
+                         c.task_ctr, c.err);
+    }
+  }
   // 8-byte accumulators need the whole LDS for one 16384-slot tile: use a
   // 1024-thread workgroup (16 waves) when the per-source items are small.
   constexpr int BS =
       (sizeof(typename Sr::Acc) >= 8 && sizeof(typename Rows::Src::Item) <= 8) ? 1024 : 512;
   auto k = k_num_tiles<Sr, Rows, BS>;
   static int occ = occupancy(k, BS);
-  hipLaunchKernelGGL(k, dim3(c.cus * occ), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks,
+  const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks,
                      (const int32_t*)book, c.task_ctr, c.err);
   constexpr int RBS = sizeof(typename Sr::Acc) >= 8 ? 256 : 512;
   auto k2 = k_num_ranges<Sr, Rows, kRangeLg, RBS>;
   static int occ2 = occupancy(k2, RBS);
-  hipLaunchKernelGGL(k2, dim3(c.cus * occ2), dim3(RBS), 0, st, rows, c.plan.bins, c.C, c.off2,
+  const int grid2 = c.cus * occ2 > kQueues ? c.cus * occ2 : kQueues;
+  hipLaunchKernelGGL(k2, dim3(grid2), dim3(RBS), 0, st, rows, c.plan.bins, c.C, c.off2,
                      c.tasks + c.task_cap, (const int32_t*)book, c.task_ctr, c.err);
 }
 
@@ -225,6 +274,14 @@ void launch_rebin(const int64_t* p, const int32_t* nt, const int64_t* c_rowptr, 
 int64_t analyze_blocks(int64_t nrows);
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,
                         hipStream_t st);
+// Column-slab partition of B (slabs of 2^ls columns, S of them): with cols
+// set, the bounds bnd (S+1 ints per B row), the segment starts prow
+// (S*nb + 1) and pcol; with vals set, pval (vbytes per entry).  partial:
+// scan_partials_len(S*nb) int64 of scratch; err: flag set on entries that
+// contradict the bounds (unsorted or out-of-range columns).
+void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
+                           int32_t ls, int32_t S, int32_t* bnd, int64_t* prow, int64_t* partial, int32_t* pcol,
+                           void* pval, bool cols, bool vals, int32_t* err, int cus, hipStream_t st);
 void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                      const Marks& marks, hipStream_t st);
 void launch_symbolic_dense(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,

@@ -1,0 +1,109 @@
+"""GPU parity of the column-slab dense path against the CPU oracle.
+
+The dense rows of a single product run per (row, column slab) tasks over a
+slab partition of B; slabs holding more entries than a task's LDS value
+array go to the tile and range tasks.  These cases make every kind of task
+appear: slabs under and over the cap, dense and sparse tiles inside
+over-cap slabs, a ragged last slab, and values that change between the
+symbolic and the numeric pass (the cached partition structure with fresh
+values)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from helpers import ALL, EXACT, F64, I64, MINPLUS, with_vals
+from gpu_helpers import check_product, compare, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_2504_06408_amd as sg
+    hd = sg.Handle(0)
+    yield hd
+    hd.close()
+
+
+def _reset(h):
+    h.set_option("force_path", "auto")
+    h.set_option("hash_max_products", 4096)
+    h.set_option("dense_slab", 1)
+
+
+def _hstack(blocks, sr, seed):
+    """Column concatenation of synth CSR blocks (structure only), values per
+    semiring drawn afterwards."""
+    mats = [sp.csr_matrix((np.ones(b.nnz), np.asarray(b.col), np.asarray(b.rowptr)), shape=(b.nrows, b.ncols))
+            for b in blocks]
+    M = sp.hstack(mats, format="csr")
+    M.sort_indices()
+    S = synth.CSR(M.shape[0], M.shape[1], M.indptr.astype(np.int64), M.indices.astype(np.int32),
+                  np.zeros(M.nnz, np.float64))
+    return with_vals(S, sr, seed)
+
+
+@pytest.mark.parametrize("sr", ALL)
+@pytest.mark.parametrize("slab", [0, 1])
+def test_slab_and_tile_paths(h, sr, slab):
+    """R-MAT s12 A.A with every row forced dense, through each dense path."""
+    _reset(h)
+    h.set_option("dense_slab", slab)
+    h.set_option("force_path", "dense")
+    try:
+        A = with_vals(synth.rmat(12, 16, seed=90), sr, 91)
+        check_product(h, sr, A, A, what=f"rmat12 dense slab={slab}")
+    finally:
+        _reset(h)
+
+
+@pytest.mark.parametrize("sr", ALL)
+def test_over_cap_slabs_mix_all_tasks(h, sr):
+    """B = [dense 16384-column block | sparse 180000-column block]: C's rows
+    hold ~10k entries in the first tile (over the slab cap: dense-tile task)
+    and a few hundred spread over the other tiles (slab tasks, and range
+    tasks inside the over-cap slab)."""
+    _reset(h)
+    A = with_vals(synth.er(64, 160, 40, 200), sr, 201)
+    B = _hstack([synth.er(160, 16384, 3000, 202), synth.er(160, 180000, 40, 203)], sr, 204)
+    check_product(h, sr, A, B, what="over-cap mix")
+
+
+@pytest.mark.parametrize("sr", [MINPLUS, F64])
+def test_ragged_last_slab_wide(h, sr):
+    """1,200,001 columns: slabs of 2^17 columns, the last one holds a single
+    column tile's remainder."""
+    _reset(h)
+    A = with_vals(synth.er(80, 300, 60, 210), sr, 211)
+    B = with_vals(synth.er(300, 1_200_001, 900, 212), sr, 213)
+    check_product(h, sr, A, B, what="ragged wide")
+
+
+@pytest.mark.parametrize("sr", EXACT)
+def test_values_change_between_passes(h, sr):
+    """Numeric after symbolic on the same arrays with new values: the slab
+    partition's structure is reused and its values rebuilt."""
+    import torch
+    import paper_2504_06408_amd as sg
+    import oracle
+    _reset(h)
+    A = with_vals(synth.rmat(11, 16, seed=220), sr, 221)
+    dA = to_dev(A)
+    rowptr, nnz = h.symbolic(dA, dA)
+    A2 = with_vals(A, sr, 222)
+    dA.val.copy_(torch.from_numpy(np.ascontiguousarray(A2.val)).to(dA.val.device))
+    vdt = dA.val.dtype
+    C = sg.DeviceCSR(A.nrows, A.ncols, rowptr, torch.empty(nnz, dtype=torch.int32, device="cuda"),
+                     torch.empty(nnz, dtype=vdt, device="cuda"))
+    h.numeric(sg.semiring(sr), dA, dA, C)
+    torch.cuda.synchronize()
+    h.check()
+    rp, cl, vl = C.to_numpy()
+    compare(sr, rp, cl, vl, oracle.get().spgemm(sr, A2, A2), "values changed")
+
+
+def test_dense_slab_option_errors(h):
+    import paper_2504_06408_amd as sg
+    with pytest.raises(sg.SgError):
+        h.set_option("dense_slab", 2)
