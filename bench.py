@@ -283,26 +283,24 @@ def main():
     b_alg = b_sym + b_num
 
     phases = {k: float(np.mean([r[k] for r in phase_runs])) for k in phase_runs[0]}
-    dom = max(phases, key=phases.get)
-    # algorithmic bytes of the dominant kernel: the per-output-entry figure
-    # (4 + value bytes) times the entries it writes, plus one read of the A
-    # rows it handles and one read of B (col + value), plus row offsets
-    rp_host = C.rowptr.cpu().numpy()
-    m_row = np.diff(rp_host)
+    stats = h.stats()
+    # Roofline of the dominant single-kernel phase.  Algorithmic bytes per
+    # launch: the output entries that kernel writes ((4 + value bytes) each)
+    # plus one read of its inputs: the A rows it handles (col + value), B
+    # (col + value; col only in the symbolic pass) and 8 B of row offsets per
+    # dense row.
     hm = 4096 if args.hash_max is None else args.hash_max
     dense = p > hm
-    small = p <= 64
-    hashr = (~dense) & (~small) & (p > 0)
-    sel = {"num_dense": dense, "num_hash": hashr, "num_small": small & (p > 0),
-           "sym_dense": dense, "sym_hash": hashr, "sym_small": small & (p > 0)}.get(dom)
-    if sel is not None:
-        a_rows = np.diff(A.rowptr)[sel].sum()
-        if dom.startswith("num"):
-            kb = (4 + vb) * int(m_row[sel].sum()) + (4 + vb) * int(a_rows) + (4 + vb) * nnzB + 16 * int(sel.sum())
-        else:
-            kb = 4 * int(a_rows) + 4 * nnzB + 16 * int(sel.sum()) + 8 * int(sel.sum())
-    else:
-        kb = b_alg
+    nd = int(dense.sum())
+    a_dense = int(np.diff(A.rowptr)[dense].sum())
+    kernels = {
+        "sym_dense_bitmap": 4 * a_dense + 4 * nnzB + 8 * nd,
+        "num_dense_slab": (4 + vb) * (stats["slab_entries"] + a_dense + nnzB) + 8 * nd,
+        "num_dense_tiles": (4 + vb) * (stats["tile_entries"] + a_dense + nnzB) + 8 * nd,
+        "num_dense_ranges": (4 + vb) * (stats["range_entries"] + a_dense + nnzB) + 8 * nd,
+    }
+    dom = max(kernels, key=lambda k: phases.get(k, 0.0))
+    kb = kernels[dom]
     achieved = kb / (phases[dom] * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_launch": int(kb),
@@ -327,6 +325,7 @@ def main():
         "hbm_frac_model": round(b_alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
         "bytes_alg": int(b_alg),
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "dense_stats": stats,
         "roofline": roof,
     }
     t_par = time.perf_counter()

@@ -115,7 +115,10 @@ sg_status sg_handle_destroy(sg_handle* h);
  * more products take the column-tiled dense path; <= 4096), "force_path"
  * ("auto", "small", "hash", "dense": route every row that the path can take
  * through it), "validate" (0/1), "timing" (0/1: record per-phase HIP events,
- * see sg_handle_timings), "dense_tile_min" (1..2048: a dense row's column tile
+ * see sg_handle_timings), "dense_slab" (0/1, default 1: dense rows of a single
+ * product run per column slab of B over a slab partition of B; 0: per
+ * column tile through a per-B-row tile offset table), "dense_tile_min"
+ * (1..2048: a dense row's column tile
  * with at least this many output entries is accumulated in a dense LDS array,
  * smaller ones in an LDS hash table).  Returns SG_ERR_INVALID for an unknown
  * name or a bad value. */
@@ -176,19 +179,24 @@ sg_status sg_plan_destroy(sg_plan* plan);
 sg_status sg_tune(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, const char* out_json);
 
 /* Phases timed when the handle option "timing" is "1" (a pair of HIP events
- * is recorded on the call's stream around each phase). */
+ * is recorded on the call's stream around each phase).  Phases 10..13 are
+ * single kernels nested inside phases 4 and 9. */
 enum {
   SG_PHASE_SYM_ANALYZE = 0, /* row analysis + binning of the symbolic pass */
-  SG_PHASE_SYM_BOUNDS = 1,  /* per-B-row column-tile offsets */
+  SG_PHASE_SYM_BOUNDS = 1,  /* per-B-row column-tile offsets and the column-slab partition of B */
   SG_PHASE_SYM_SMALL = 2,   /* wavefront rows */
   SG_PHASE_SYM_HASH = 3,    /* LDS hash rows */
-  SG_PHASE_SYM_DENSE = 4,   /* bitmap rows (one kernel) */
+  SG_PHASE_SYM_DENSE = 4,   /* bitmap rows: bitmap kernel + per-row tile offsets */
   SG_PHASE_SYM_SCAN = 5,    /* prefix sum into C.rowptr */
-  SG_PHASE_NUM_ANALYZE = 6, /* row analysis + binning of the numeric pass */
+  SG_PHASE_NUM_ANALYZE = 6, /* row binning of the numeric pass (+ value partition of B) */
   SG_PHASE_NUM_SMALL = 7,
   SG_PHASE_NUM_HASH = 8,
-  SG_PHASE_NUM_DENSE = 9,   /* dense-tile rows (one kernel) */
-  SG_NPHASES = 10
+  SG_PHASE_NUM_DENSE = 9,         /* dense rows: task building + the three task kernels */
+  SG_PHASE_SYM_DENSE_BITMAP = 10, /* the dense-row bitmap kernel alone */
+  SG_PHASE_NUM_DENSE_SLAB = 11,   /* slab tasks (bitmap + rank accumulator) */
+  SG_PHASE_NUM_DENSE_TILES = 12,  /* dense-tile tasks */
+  SG_PHASE_NUM_DENSE_RANGES = 13, /* range tasks (hash + sort) */
+  SG_NPHASES = 14
 };
 
 /* Device milliseconds of each phase of the most recent symbolic and numeric
@@ -196,6 +204,13 @@ enum {
  * min(n, SG_NPHASES) values; a phase that did not run reports 0.  Waits for
  * the recorded events.  Requires the "timing" option. */
 sg_status sg_handle_timings(sg_handle* h, double* ms, int n);
+
+/* Dense-row work of the most recent numeric call on this handle (waits for
+ * the device): out[0..n) receives min(n, SG_NSTATS) values, in this order:
+ * dense rows, slab tasks, dense-tile tasks, range tasks, and the output
+ * entries written by each of the three task kinds (slab, tile, range). */
+enum { SG_NSTATS = 7 };
+sg_status sg_handle_stats(sg_handle* h, int64_t* out, int n);
 
 /* Wait for all work of the handle's device, then report any device-side
  * consistency error (a numeric pass that filled a different number of

@@ -32,10 +32,11 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID", -2: "SG_ERR_SHAPE", -3: "SG_ERR_SEMI
 EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_handle_set_option",
            "sg_spgemm_symbolic", "sg_spgemm_numeric", "sg_spgemm_merge_symbolic", "sg_spgemm_merge_numeric",
            "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune",
-           "sg_handle_check", "sg_handle_timings", "sg_status_string", "sg_last_error")
+           "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error")
 
 PHASES = ("sym_analyze", "sym_bounds", "sym_small", "sym_hash", "sym_dense", "sym_scan", "num_analyze", "num_small",
-          "num_hash", "num_dense")
+          "num_hash", "num_dense", "sym_dense_bitmap", "num_dense_slab", "num_dense_tiles", "num_dense_ranges")
+STATS = ("dense_rows", "slab_tasks", "tile_tasks", "range_tasks", "slab_entries", "tile_entries", "range_entries")
 
 
 class SgError(RuntimeError):
@@ -86,6 +87,7 @@ def lib():
             "sg_tune": ([P, SR, CSR, CSR, ctypes.c_char_p], ci),
             "sg_handle_check": ([P], ci),
             "sg_handle_timings": ([P, ctypes.POINTER(ctypes.c_double), ci], ci),
+            "sg_handle_stats": ([P, ctypes.POINTER(i64), ci], ci),
             "sg_status_string": ([ci], ctypes.c_char_p),
             "sg_last_error": ([P], ctypes.c_char_p),
         }
@@ -237,6 +239,12 @@ class Handle:
         arr = (ctypes.c_double * len(PHASES))()
         self._rc(lib().sg_handle_timings(self.ptr, arr, len(PHASES)))
         return dict(zip(PHASES, list(arr)))
+
+    def stats(self) -> dict:
+        """Dense-row task split of the last numeric call (waits for the device)."""
+        arr = (ctypes.c_int64 * len(STATS))()
+        self._rc(lib().sg_handle_stats(self.ptr, arr, len(STATS)))
+        return dict(zip(STATS, list(arr)))
 
     # ---- product -------------------------------------------------------------
     def symbolic(self, A: DeviceCSR, B: DeviceCSR, stream=None):

@@ -209,21 +209,33 @@ sg_status build_slabs(sg_handle* h, RowSource& r, const sg_csr* B, int vbytes, b
   const int32_t ls = slab_log(r.ncols), S = slab_count(r.ncols, ls);
   const int64_t nb = B->nrows;
   const size_t ne = (size_t)(B->nnz > 0 ? B->nnz : 1);
+  const int32_t G = 1 << (ls - kTileLog);
   if (cols) {
     SG_HIP(h, h->bnd_buf.ensure(sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
+    SG_HIP(h, h->rpt_buf.ensure(sizeof(int32_t) * (size_t)S * (size_t)nb * (size_t)(G + 1)));
     SG_HIP(h, h->prow_buf.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
     SG_HIP(h, h->pcol_buf.ensure(sizeof(int32_t) * ne));
   }
   if (vals) SG_HIP(h, h->pval_buf.ensure((size_t)vbytes * ne));
-  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, ls, S, (int32_t*)h->bnd_buf.p,
-                        (int64_t*)h->prow_buf.p, partial, (int32_t*)h->pcol_buf.p, vals ? h->pval_buf.p : nullptr,
-                        cols, vals, h->d_flags, h->cus, st);
+  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, ls, S, r.T, (int32_t*)h->bnd_buf.p,
+                        (int32_t*)h->rpt_buf.p, (int64_t*)h->prow_buf.p, partial, (int32_t*)h->pcol_buf.p,
+                        vals ? h->pval_buf.p : nullptr, cols, vals, h->d_flags, h->cus, st);
+  r.rpt = (const int32_t*)h->rpt_buf.p;
   r.prow = (const int64_t*)h->prow_buf.p;
   r.pcol = (const int32_t*)h->pcol_buf.p;
   r.pval = vals ? h->pval_buf.p : nullptr;
   r.ls = ls;
   r.S = S;
   r.qctr = h->d_flags + kCtrBase;
+  return SG_OK;
+}
+
+// Per dense row of the plan: its A row (first entry, length, row id).
+sg_status build_dense_rows(sg_handle* h, RowSource& r, const BinPlan& plan, hipStream_t st) {
+  const int32_t nd = plan.ndense();
+  SG_HIP(h, h->dr_buf.ensure(sizeof(DenseRow) * (size_t)(nd > 0 ? nd : 1)));
+  launch_dense_rows(plan, r.a_rowptr, (DenseRow*)h->dr_buf.p, h->cus, st);
+  r.drow = (const DenseRow*)h->dr_buf.p;
   return SG_OK;
 }
 
@@ -248,6 +260,7 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   BinPlan plan;
   const Policy pol = make_policy(h, 0, nullptr);
   clear_phases(h, kPhSymAnalyze, kPhNumAnalyze);
+  clear_phases(h, kPhSymDenseBitmap, kPhSymDenseBitmap + 1);
   const Marks mk = handle_marks(h, st);
   SG_HIP(h, h->p_buf.ensure(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)));
   SG_HIP(h, h->nt_buf.ensure(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
@@ -259,7 +272,8 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   int64_t* partial = ar.take<int64_t>(scan_partials_len(n));
   int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
   if (nd > 0) {
-    const bool tiles = r.mode == kModeProduct && r.T > 1;
+    const bool slab = r.mode == kModeProduct && h->slab;
+    const bool tiles = !slab && r.mode == kModeProduct && r.T > 1;
     if (tiles) SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
     SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
     off2 = (int32_t*)h->off2_buf.p;
@@ -268,7 +282,10 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
       r.rp2 = (const int32_t*)h->rp2_buf.p;
       launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
     }
-    if (r.mode == kModeProduct && h->slab) SG_TRY(build_slabs(h, r, B, 0, true, false, spartial, st));
+    if (slab) {
+      SG_TRY(build_slabs(h, r, B, 0, true, false, spartial, st));
+      SG_TRY(build_dense_rows(h, r, plan, st));
+    }
     mk.mark(kPhSymBounds, 0);
   }
   launch_symbolic(r, plan, C_rowptr + 1, off2, h->cus, mk, st);
@@ -300,7 +317,8 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   ar.base = (char*)h->ws.p;
   BinPlan plan;
   const Policy pol = make_policy(h, 1, sr);
-  clear_phases(h, kPhNumAnalyze, kNPhases);
+  clear_phases(h, kPhNumAnalyze, kPhSymDenseBitmap);
+  clear_phases(h, kPhNumDenseSlab, kNPhases);
   const Marks mk = handle_marks(h, st);
   // Same structure as the last symbolic call: its per-row counts give the bins
   // without touching A or B again.  Dense classification depends only on the
@@ -311,21 +329,21 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
     SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st, (int64_t*)h->p_buf.p, (int32_t*)h->nt_buf.p, true));
   else
     SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st));
-  mk.mark(kPhNumAnalyze, 0);
   const int32_t nd = plan.ndense();
   const bool cached = same && h->cache_nd == nd;
+  const bool slab = r.mode == kModeProduct && h->slab && nd > 0;
   if (nd > 0) {
-    if (r.mode == kModeProduct && r.T > 1) {
+    if (slab) {
+      // structure from the last symbolic pass when cached; values every call
+      int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
+      SG_TRY(build_slabs(h, r, B, sr->value_bytes, !cached, true, spartial, st));
+      SG_TRY(build_dense_rows(h, r, plan, st));
+    } else if (r.mode == kModeProduct && r.T > 1) {
       if (!cached) {
         SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
         launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
       }
       r.rp2 = (const int32_t*)h->rp2_buf.p;
-    }
-    if (r.mode == kModeProduct && h->slab) {
-      // structure from the last symbolic pass when cached; values every call
-      int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
-      SG_TRY(build_slabs(h, r, B, sr->value_bytes, !cached, true, spartial, st));
     }
     if (!cached) {
       SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
@@ -334,6 +352,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
       h->cache_valid = false;  // off2 now belongs to this call's inputs only
     }
   }
+  mk.mark(kPhNumAnalyze, 0);
   NumCtx c{};
   c.marks = mk;
   c.src = r;
@@ -343,11 +362,19 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.err = h->d_flags;
   c.task_ctr = h->d_flags + kCtrBase;
   c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;
-  SG_HIP(h, h->task_buf.ensure(task_buffer_bytes(c.task_cap, r.T)));
-  c.tasks = (Task*)h->task_buf.p;
+  if (slab) {
+    const size_t tb = sizeof(SlabTask) * (size_t)nd * (size_t)r.S;
+    SG_HIP(h, h->task_buf.ensure(tb + sizeof(int32_t) * (6 * (size_t)r.T + 3)));
+    c.slab_tasks = (SlabTask*)h->task_buf.p;
+    c.slab_book = (int32_t*)((char*)h->task_buf.p + tb);
+  } else {
+    SG_HIP(h, h->task_buf.ensure(task_buffer_bytes(c.task_cap, r.T)));
+    c.tasks = (Task*)h->task_buf.p;
+  }
   c.tile_min = h->tile_min;
   c.cus = h->cus;
   c.comp_dense = pol.comp_mode != kCompNone;
+  h->last_nd = nd;
   switch (sr->id) {
     case SG_PLUS_TIMES_I64: launch_numeric_i64(c, st); break;
     case SG_PLUS_TIMES_F32: launch_numeric_f32(c, st); break;
@@ -488,6 +515,8 @@ sg_status sg_handle_destroy(sg_handle* h) {
   h->p_buf.release();
   h->nt_buf.release();
   h->bnd_buf.release();
+  h->rpt_buf.release();
+  h->dr_buf.release();
   h->prow_buf.release();
   h->pcol_buf.release();
   h->pval_buf.release();
@@ -640,7 +669,9 @@ sg_status sg_handle_check(sg_handle* h) {
   SG_HIP(h, hipMemcpy(&v, h->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (v) {
     SG_HIP(h, hipMemset(h->d_flags, 0, sizeof(int32_t)));
-    return sg_fail(h, SG_ERR_INVALID, "a numeric pass filled a different number of entries than its symbolic pass");
+    return sg_fail(h, SG_ERR_INVALID,
+                   "inconsistent structure: a numeric pass filled a different number of entries than its symbolic "
+                   "pass, or B holds unsorted or out-of-range columns");
   }
   return SG_OK;
 }
@@ -657,6 +688,20 @@ sg_status sg_handle_timings(sg_handle* h, double* ms, int n) {
     SG_HIP(h, hipEventElapsedTime(&t, h->ev[p][0], h->ev[p][1]));
     ms[p] = t;
   }
+  return SG_OK;
+}
+
+sg_status sg_handle_stats(sg_handle* h, int64_t* out, int n) {
+  if (!h || !out || n < 0) return SG_ERR_INVALID;
+  SG_HIP(h, hipSetDevice(h->device));
+  SG_HIP(h, hipDeviceSynchronize());
+  int32_t blk[kCtrEntries + 6] = {};
+  SG_HIP(h, hipMemcpy(blk, h->d_flags + kCtrBase, sizeof(blk), hipMemcpyDeviceToHost));
+  uint64_t ent[3];
+  std::memcpy(ent, blk + kCtrEntries, sizeof(ent));
+  const int64_t v[SG_NSTATS] = {h->last_nd, blk[kListSlab], blk[kListTile], blk[kListRange],
+                                (int64_t)ent[kListSlab], (int64_t)ent[kListTile], (int64_t)ent[kListRange]};
+  for (int i = 0; i < n && i < SG_NSTATS; ++i) out[i] = v[i];
   return SG_OK;
 }
 

@@ -162,29 +162,33 @@ void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int3
   marks.mark(kPhSymHash, 0);
   if (!dense) return;
   marks.mark(kPhSymDense, 1);
+  marks.mark(kPhSymDenseBitmap, 1);
   sym_dense_rows(rows, plan, cnt_out, off2, cus, st);
+  marks.mark(kPhSymDenseBitmap, 0);
   marks.mark(kPhSymDense, 0);
 }
 
 // Dense rows of a single product over the column-slab partition.
-void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus, hipStream_t st) {
+void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus, const Marks& marks,
+              hipStream_t st) {
   const int nd = plan.ndense();
   if (nd == 0) return;
-  using Src = SlabSrc<uint8_t, false>;
-  Src s{};
-  s.a_rowptr = r.a_rowptr;
+  SlabSrc s{};
+  s.drow = r.drow;
   s.a_col = r.a_col;
   s.prow = r.prow;
   s.pcol = r.pcol;
   s.nb = r.b_nrows;
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, r.qctr, (int64_t)kCtrInts,
                      (int32_t)0);
-  auto k = k_sym_slab<Src, 512>;
+  auto k = k_sym_slab<512>;
   static int occ = occupancy(k, 512);
   const int grid = cus * occ > kQueues ? cus * occ : kQueues;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, s, plan.bins, r.S, r.ls, r.T, r.T, off2, r.qctr);
-  hipLaunchKernelGGL(k_off2_finish<256>, dim3(grid_for(nd, 4, cus * 16)), dim3(256), 0, st, plan.bins, off2, r.T, r.T,
-                     cnt_out);
+  marks.mark(kPhSymDenseBitmap, 1);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, s, plan.bins, r.S, r.ls, r.T, off2, r.qctr);
+  marks.mark(kPhSymDenseBitmap, 0);
+  hipLaunchKernelGGL(k_off2_finish<256>, dim3(grid_for(nd, 4, cus * 16)), dim3(256), 0, st, plan.bins, r.drow, off2,
+                     r.T, cnt_out);
 }
 
 bool use_slab(const RowSource& r) { return r.mode == kModeProduct && r.S > 0; }
@@ -255,12 +259,13 @@ void slab_scatter(const int64_t* b_rowptr, const int32_t* b_col, const void* b_v
 }
 
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
-                           int32_t ls, int32_t S, int32_t* bnd, int64_t* prow, int64_t* partial, int32_t* pcol,
-                           void* pval, bool cols, bool vals, int32_t* err, int cus, hipStream_t st) {
+                           int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
+                           int64_t* partial, int32_t* pcol, void* pval, bool cols, bool vals, int32_t* err, int cus,
+                           hipStream_t st) {
   if (nb <= 0) return;
   if (cols) {
-    hipLaunchKernelGGL(k_tile_bounds, dim3(grid_for(nb, 4, cus * 16)), dim3(256), 0, st, b_rowptr, b_col, nb, S, ls,
-                       bnd);
+    hipLaunchKernelGGL(k_slab_bounds<256>, dim3(grid_for(nb, 4, cus * 16)), dim3(256), 0, st, b_rowptr, b_col, nb, T,
+                       (int32_t)(1 << (ls - kTileLog)), S, bnd, rpt);
     hipLaunchKernelGGL(k_slab_counts<256>, dim3(grid_for((int64_t)S * nb, 256, cus * 16)), dim3(256), 0, st,
                        (const int32_t*)bnd, nb, S, prow);
     launch_scan_inclusive(prow + 1, (int64_t)S * nb, partial, st);
@@ -279,7 +284,7 @@ void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, 
                             [&](const auto& rows) { symbolic_rows(rows, plan, cnt_out, off2, cus, marks, st, !slab); });
   if (slab) {
     marks.mark(kPhSymDense, 1);
-    sym_slab(r, plan, cnt_out, off2, cus, st);
+    sym_slab(r, plan, cnt_out, off2, cus, marks, st);
     marks.mark(kPhSymDense, 0);
   }
 }
@@ -287,10 +292,16 @@ void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, 
 void launch_symbolic_dense(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                            hipStream_t st) {
   if (use_slab(r)) {
-    sym_slab(r, plan, cnt_out, off2, cus, st);
+    sym_slab(r, plan, cnt_out, off2, cus, Marks{}, st);
     return;
   }
   with_rows<uint8_t, false>(r, [&](const auto& rows) { sym_dense_rows(rows, plan, cnt_out, off2, cus, st); });
+}
+
+void launch_dense_rows(const BinPlan& plan, const int64_t* a_rowptr, DenseRow* dr, int cus, hipStream_t st) {
+  const int nd = plan.ndense();
+  if (nd == 0) return;
+  hipLaunchKernelGGL(k_dense_rows<256>, dim3(grid_for(nd, 256, cus * 8)), dim3(256), 0, st, plan.bins, a_rowptr, dr);
 }
 
 int64_t scan_partials_len(int64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }

@@ -78,7 +78,8 @@ struct sg_handle {
   SgBuf parts_buf;           // device table of merge parts
   SgBuf task_buf;            // dense-row task lists of the numeric pass
   SgBuf p_buf, nt_buf;       // per-row products and terms from symbolic, reused to re-bin numeric
-  SgBuf bnd_buf, prow_buf;   // column-slab partition of B: per-row slab bounds, segment starts
+  SgBuf bnd_buf, prow_buf;   // column-slab partition of B: per-row slab bounds, segment starts,
+  SgBuf rpt_buf, dr_buf;     //   tile offsets inside the segments; the dense rows' A rows
   SgBuf pcol_buf, pval_buf;  //   and the partitioned entries
   int slab = 1;              // dense rows of single products use the column-slab path
   int32_t tile_min = sg::kTileMinDefault;
@@ -87,6 +88,7 @@ struct sg_handle {
   SgCacheKey cache_key{};
   int32_t cache_T = 0, cache_nd = 0;
   int64_t cache_n = -1;
+  int64_t last_nd = 0;  // dense rows of the last numeric call
   int32_t* d_flags = nullptr;  // kFlagInts: [0] consistency error, [2] validation, task counters from kCtrBase
   int64_t* h_pin = nullptr;    // pinned readback area (>= 256 int64)
 };

@@ -791,10 +791,12 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
 // workgroups share one L2) and takes kGrab consecutive queue slots per atomic.
 // Counter block layout (int32, zeroed before each use):
 //   [0, 3)                      totals of the tile, range and slab task lists
+//   [8, 14)                     entries of each list (three uint64)
 //   kCtrQueue0 + (l*kQueues + q)*kCtrStride   queue q of list l (l = 3: slab symbolic)
 constexpr int kQueues = 8;
 constexpr int kGrab = 4;
 constexpr int kCtrStride = 16;  // 64 bytes between counters
+constexpr int kCtrEntries = 8;  // [8, 14): three uint64 sums of entries per task list (statistics)
 constexpr int kCtrQueue0 = 64;
 constexpr int kCtrLists = 4;
 constexpr int kCtrInts = kCtrQueue0 + kCtrLists * kQueues * kCtrStride;
@@ -851,7 +853,12 @@ __host__ __device__ inline const int32_t* book_off(const int32_t* book, int32_t 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t G,
                                                     int32_t slab_cap, int32_t tile_min, int32_t range_cap,
-                                                    Task* tiles, Task* ranges, Task* slabs, int32_t* book) {
+                                                    Task* tiles, Task* ranges, Task* slabs, int32_t* book,
+                                                    int32_t* ctr) {
+  __shared__ unsigned long long s_ent[3];
+  if (threadIdx.x < 3) s_ent[threadIdx.x] = 0ull;
+  __syncthreads();
+  unsigned long long ent[3] = {0ull, 0ull, 0ull};
   const int32_t nd = dense_rows(bins);
   int32_t* cnt_t = book;
   int32_t* cnt_r = book + Tmax;
@@ -866,6 +873,7 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
       if (G > 0 && ms <= slab_cap) {
         const int32_t s = ta / G;
         slabs[(int64_t)s * nd + atomicAdd(&cnt_s[s], 1)] = Task{h, ta, tb};
+        ent[kListSlab] += (unsigned long long)ms;
         continue;
       }
       int32_t r0 = -1, rlast = -1, racc = 0;
@@ -877,8 +885,10 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
           r0 = -1;
           racc = 0;
           tiles[(int64_t)t * nd + atomicAdd(&cnt_t[t], 1)] = Task{h, t, t + 1};
+          ent[kListTile] += (unsigned long long)c;
           continue;
         }
+        ent[kListRange] += (unsigned long long)c;
         if (r0 >= 0 && racc + c > range_cap) {
           ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
           r0 = -1;
@@ -891,6 +901,14 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
       if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
     }
   }
+  // entries per task kind (statistics): block sums, one atomic each
+  for (int l = 0; l < 3; ++l) {
+    const unsigned long long v = wave_sum(ent[l]);
+    if (lane_id() == 0 && v) atomicAdd(&s_ent[l], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 && s_ent[threadIdx.x])
+    atomicAdd((unsigned long long*)(ctr + kCtrEntries) + threadIdx.x, s_ent[threadIdx.x]);
 }
 
 // Exclusive scans of the three bucket-count arrays (one block) and the totals.

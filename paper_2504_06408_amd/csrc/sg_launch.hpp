@@ -43,6 +43,8 @@ struct RowSource {
   const int64_t* prow;
   const int32_t* pcol;
   const void* pval;
+  const int32_t* rpt;     // tile offsets inside each slab segment
+  const DenseRow* drow;   // per dense row: its A row
   int32_t ls, S;
   int32_t* qctr;  // counter block (kCtrInts ints) of the slab symbolic pass
 };
@@ -70,7 +72,7 @@ struct Marks {
 
 // phase ids (mirror SG_PHASE_* of the public header)
 enum { kPhSymAnalyze = 0, kPhSymBounds, kPhSymSmall, kPhSymHash, kPhSymDense, kPhSymScan, kPhNumAnalyze, kPhNumSmall,
-       kPhNumHash, kPhNumDense, kNPhases };
+       kPhNumHash, kPhNumDense, kPhSymDenseBitmap, kPhNumDenseSlab, kPhNumDenseTiles, kPhNumDenseRanges, kNPhases };
 
 struct NumCtx {
   Marks marks;
@@ -82,6 +84,8 @@ struct NumCtx {
   int32_t* task_ctr;  // counter block of kCtrInts ints (list totals, queue cursors)
   Task* tasks;        // tile, range and slab task lists of task_cap entries each
   int64_t task_cap;   // >= dense rows x tiles
+  SlabTask* slab_tasks;  // slab path: dense rows x slabs tasks ...
+  int32_t* slab_book;    // ... and their bucket bookkeeping (6*T + 3 ints)
   int32_t tile_min;
   int cus;
   int comp_dense;  // float sums: dense rows use compensated accumulation
@@ -189,6 +193,30 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
   const bool slab = kProduct && c.src.mode == kModeProduct && c.src.S > 0;
   const int32_t G = slab ? (1 << (c.src.ls - kTileLog)) : 0;
   constexpr int kSlabCap = slab_cap<Sr>();
+  if constexpr (kProduct) {
+    if (slab) {
+      const int32_t T = c.src.T;
+      const int32_t nd = c.plan.ndense();
+      int32_t* sbook = c.slab_book;
+      hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, c.task_ctr,
+                         (int64_t)kCtrInts, (int32_t)0);
+      hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)T, 256, 1024)), dim3(256), 0, st, sbook,
+                         3 * (int64_t)T, (int32_t)0);
+      hipLaunchKernelGGL(k_slab_tasks<256>, dim3(grid_for(nd, 256, c.cus * 8)), dim3(256), 0, st, c.plan.bins,
+                         c.src.drow, c.off2, T, G, (const int64_t*)c.C.rowptr, c.slab_tasks, sbook, c.task_ctr);
+      hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, sbook, T, c.task_ctr);
+      SlabB<V> b{c.src.prow, c.src.pcol, (const V*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
+      auto k = k_num_slab<Sr, V, 512, kSlabCap>;
+      static int occ = occupancy(k, 512);
+      const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
+      c.marks.mark(kPhNumDenseSlab, 1);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.off2, c.C,
+                         (const SlabTask*)c.slab_tasks, (const int32_t*)book_off(sbook, T, kListSlab), c.src.S, nd,
+                         c.task_ctr, c.err);
+      c.marks.mark(kPhNumDenseSlab, 0);
+      return;
+    }
+  }
   int32_t* book = task_book(c);
   const int32_t Tmax = rows.Tmax;
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, c.task_ctr,
@@ -196,28 +224,9 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)Tmax, 256, 1024)), dim3(256), 0, st, book,
                      3 * (int64_t)Tmax, (int32_t)0);
   hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
-                     c.plan.bins, c.off2, Tmax, G, kSlabCap, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
-                     c.tasks + 2 * c.task_cap, book);
+                     c.plan.bins, c.off2, Tmax, 0, 0, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
+                     c.tasks + 2 * c.task_cap, book, c.task_ctr);
   hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, Tmax, c.task_ctr);
-  if constexpr (kProduct) {
-    if (slab) {
-      using Src = SlabSrc<V, true>;
-      Src s{};
-      s.a_rowptr = c.src.a_rowptr;
-      s.a_col = c.src.a_col;
-      s.a_val = (const V*)c.src.a_val;
-      s.prow = c.src.prow;
-      s.pcol = c.src.pcol;
-      s.pval = (const V*)c.src.pval;
-      s.nb = c.src.b_nrows;
-      auto k = k_num_slab<Sr, Src, 512, kSlabCap>;
-      static int occ = occupancy(k, 512);
-      const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
-      hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, s, c.plan.bins, c.C, c.off2, Tmax, c.src.ls,
-                         (const Task*)(c.tasks + 2 * c.task_cap), (const int32_t*)book_off(book, Tmax, kListSlab),
-                         c.task_ctr, c.err);
-    }
-  }
   // 8-byte accumulators need the whole LDS for one 16384-slot tile: use a
   // 1024-thread workgroup (16 waves) when the per-source items are small.
   constexpr int BS =
@@ -225,14 +234,18 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
   auto k = k_num_tiles<Sr, Rows, BS>;
   static int occ = occupancy(k, BS);
   const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
+  c.marks.mark(kPhNumDenseTiles, 1);
   hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks,
                      (const int32_t*)book, c.task_ctr, c.err);
+  c.marks.mark(kPhNumDenseTiles, 0);
   constexpr int RBS = sizeof(typename Sr::Acc) >= 8 ? 256 : 512;
   auto k2 = k_num_ranges<Sr, Rows, kRangeLg, RBS>;
   static int occ2 = occupancy(k2, RBS);
   const int grid2 = c.cus * occ2 > kQueues ? c.cus * occ2 : kQueues;
+  c.marks.mark(kPhNumDenseRanges, 1);
   hipLaunchKernelGGL(k2, dim3(grid2), dim3(RBS), 0, st, rows, c.plan.bins, c.C, c.off2,
                      c.tasks + c.task_cap, (const int32_t*)book, c.task_ctr, c.err);
+  c.marks.mark(kPhNumDenseRanges, 0);
 }
 
 // Numeric pass for semiring Sr (SrC: its compensated variant, or Sr).
@@ -280,8 +293,11 @@ void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows
 // scan_partials_len(S*nb) int64 of scratch; err: flag set on entries that
 // contradict the bounds (unsorted or out-of-range columns).
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
-                           int32_t ls, int32_t S, int32_t* bnd, int64_t* prow, int64_t* partial, int32_t* pcol,
-                           void* pval, bool cols, bool vals, int32_t* err, int cus, hipStream_t st);
+                           int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
+                           int64_t* partial, int32_t* pcol, void* pval, bool cols, bool vals, int32_t* err, int cus,
+                           hipStream_t st);
+// Per dense row of the plan: its A row (the slab path's row table).
+void launch_dense_rows(const BinPlan& plan, const int64_t* a_rowptr, DenseRow* dr, int cus, hipStream_t st);
 void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                      const Marks& marks, hipStream_t st);
 void launch_symbolic_dense(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
