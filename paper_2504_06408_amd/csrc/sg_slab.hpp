@@ -240,18 +240,34 @@ struct SlabTask {
   int32_t m;      // C entries in the slab
 };
 
-// One thread per dense row; slab tasks go to per-slab buckets of nd slots
-// (book[2*T + s] counts bucket s), entries are summed for the statistics.
+// Entries of a light task's LDS value array (32 KB of accumulators).
+template <class Sr>
+constexpr int slab_cap() {
+  return 32768 / (int)sizeof(typename Sr::Acc);
+}
+
+// Column tiles per window of a heavy task's dense accumulator (128 KB or
+// less of accumulators).
+template <class Sr>
+constexpr int heavy_tiles() {
+  return sizeof(typename Sr::Acc) >= 8 ? 1 : (sizeof(typename Sr::Acc) >= 4 ? 2 : 4);
+}
+
+// One thread per dense row.  A slab with at most `cap` entries becomes a
+// light task (list kListSlab), a fuller one a heavy task (list kListTile);
+// both lists hold per-slab buckets of nd slots (book[l*T + s] counts bucket
+// s of list l).  Entries per list are summed for the statistics.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr, const int32_t* off2, int32_t T,
-                                                   int32_t G, const int64_t* c_rowptr, SlabTask* tasks,
-                                                   int32_t* book, int32_t* ctr) {
-  __shared__ unsigned long long s_ent;
-  if (threadIdx.x == 0) s_ent = 0ull;
+                                                   int32_t G, int32_t cap, const int64_t* c_rowptr,
+                                                   SlabTask* light, SlabTask* heavy, int32_t* book, int32_t* ctr) {
+  __shared__ unsigned long long s_ent[2];
+  if (threadIdx.x < 2) s_ent[threadIdx.x] = 0ull;
   __syncthreads();
   const int64_t nd = dense_rows(bins);
-  int32_t* cnt = book + 2 * T;
-  unsigned long long ent = 0ull;
+  int32_t* cnt_l = book + kListSlab * T;
+  int32_t* cnt_h = book + kListTile * T;
+  unsigned long long el = 0ull, eh = 0ull;
   for (int64_t h = (int64_t)blockIdx.x * BS + threadIdx.x; h < nd; h += (int64_t)gridDim.x * BS) {
     const DenseRow d = dr[h];
     const int32_t* o2 = off2 + h * (T + 1);
@@ -261,14 +277,24 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
       const int32_t tb = ta + G < T ? ta + G : T;
       const int32_t lo = o2[ta], m = o2[tb] - lo;
       if (m <= 0) continue;
-      tasks[(int64_t)s * nd + atomicAdd(&cnt[s], 1)] = SlabTask{(int32_t)h, s, base + lo, d.a0, d.nsrc, m};
-      ent += (unsigned long long)m;
+      const SlabTask tk{(int32_t)h, s, base + lo, d.a0, d.nsrc, m};
+      if (m <= cap) {
+        light[(int64_t)s * nd + atomicAdd(&cnt_l[s], 1)] = tk;
+        el += (unsigned long long)m;
+      } else {
+        heavy[(int64_t)s * nd + atomicAdd(&cnt_h[s], 1)] = tk;
+        eh += (unsigned long long)m;
+      }
     }
   }
-  ent = wave_sum(ent);
-  if (lane_id() == 0 && ent) atomicAdd(&s_ent, ent);
+  el = wave_sum(el);
+  eh = wave_sum(eh);
+  if (lane_id() == 0 && el) atomicAdd(&s_ent[0], el);
+  if (lane_id() == 0 && eh) atomicAdd(&s_ent[1], eh);
   __syncthreads();
-  if (threadIdx.x == 0 && s_ent) atomicAdd((unsigned long long*)(ctr + kCtrEntries) + kListSlab, s_ent);
+  unsigned long long* ent = (unsigned long long*)(ctr + kCtrEntries);
+  if (threadIdx.x == 0 && s_ent[0]) atomicAdd(ent + kListSlab, s_ent[0]);
+  if (threadIdx.x == 1 && s_ent[1]) atomicAdd(ent + kListTile, s_ent[1]);
 }
 
 template <class V>
@@ -281,217 +307,295 @@ struct SlabB {
   int32_t G, T;
 };
 
-// Entries of a task's LDS value array (32 KB of accumulators).
-template <class Sr>
-constexpr int slab_cap() {
-  return 32768 / (int)sizeof(typename Sr::Acc);
-}
-
 constexpr int kBoffCache = 256;  // slab-bucket offsets kept in LDS
 
+// LDS of a numeric slab task: its sources (A entry's value and column, the
+// slab segment's start and length) and the current window's per-source
+// offsets.
+template <class V, int BS>
+struct SlabLds {
+  V a[BS];
+  int32_t k[BS], slen[BS], wo[BS];
+  int64_t sst[BS], off[BS], wave[BS / kWave];
+  int32_t tc[kSlabTilesMax + 1];
+  int32_t boff[kBoffCache + 1];
+  int64_t slot;
+};
+
+// Task g of a slab-bucketed list: its bucket is the last s with boff[s] <= g.
+template <class V, int BS>
+SG_DEV SlabTask slab_task(const SlabTask* tasks, const int32_t* boff, const SlabLds<V, BS>& L, bool bcache,
+                          int32_t S, int32_t nd, int64_t g) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((bcache ? L.boff[mid] : boff[mid]) <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return tasks[(int64_t)lo * nd + (g - (bcache ? L.boff[lo] : boff[lo]))];
+}
+
+// Sources [c0, c0 + nc) of task tk into LDS (one per thread).
+template <class V, int BS>
+SG_DEV void slab_load_sources(const SlabB<V>& b, const int32_t* a_col, const V* a_val, const SlabTask& tk,
+                              int64_t c0, int nc, SlabLds<V, BS>& L) {
+  if ((int)threadIdx.x < nc) {
+    const int64_t e = tk.a0 + c0 + threadIdx.x;
+    const int32_t k = a_col[e];
+    L.k[threadIdx.x] = k;
+    L.a[threadIdx.x] = a_val[e];
+    const int64_t* pr = b.prow + (int64_t)tk.s * b.nb + k;
+    const int64_t st = pr[0];
+    L.sst[threadIdx.x] = st;
+    L.slen[threadIdx.x] = (int32_t)(pr[1] - st);
+  }
+}
+
+// Every product of window [t0, t1) (tiles, inside the task's slab whose first
+// tile is ts0) of task tk: fetch(owner, index into pcol/pval) returns a
+// product, apply(product) folds it into LDS.  With `one` the task's sources
+// are already in LDS; otherwise they are loaded chunk by chunk.  Sources'
+// window segments come from rpt unless the window is the whole slab.  Lanes
+// take consecutive products (coalesced gathers), kUnroll loads in flight each.
+template <int BS, class V, class Fetch, class Apply>
+SG_DEV void slab_window(const SlabB<V>& b, const int32_t* a_col, const V* a_val, const SlabTask& tk, int ts0,
+                        int t0, int t1, bool whole, bool one, SlabLds<V, BS>& L, Fetch& fetch, Apply& apply) {
+  constexpr int NW = BS / kWave;
+  constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
+  using P = decltype(fetch(0, (int64_t)0));
+  const int wv = wave_id();
+  for (int64_t c0 = 0; c0 < tk.nsrc; c0 += BS) {
+    const int nc = (int)((tk.nsrc - c0) < BS ? (tk.nsrc - c0) : BS);
+    if (!one) {
+      __syncthreads();
+      slab_load_sources<V, BS>(b, a_col, a_val, tk, c0, nc, L);
+      __syncthreads();
+    }
+    int64_t len = 0;
+    int32_t wo = 0;
+    if ((int)threadIdx.x < nc) {
+      if (whole) {
+        len = L.slen[threadIdx.x];
+      } else {
+        const int32_t* r = b.rpt + ((int64_t)tk.s * b.nb + L.k[threadIdx.x]) * (b.G + 1);
+        wo = r[t0 - ts0];
+        len = r[t1 - ts0] - wo;
+      }
+    }
+    int64_t total;
+    const int64_t off = block_excl_scan<NW, int64_t>(len, L.wave, &total);
+    L.off[threadIdx.x] = off;
+    L.wo[threadIdx.x] = wo;
+    __syncthreads();
+    for (int64_t qb = (int64_t)wv * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
+      const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
+      int a = 0, bb = nc - 1;
+      while (a < bb) {
+        const int mid = (a + bb + 1) >> 1;
+        if (L.off[mid] <= qb) a = mid;
+        else bb = mid - 1;
+      }
+      int e = a, f = nc - 1;
+      while (e < f) {
+        const int mid = (e + f + 1) >> 1;
+        if (L.off[mid] <= qe) e = mid;
+        else f = mid - 1;
+      }
+      P pp[kUnroll];
+      bool ok[kUnroll];
+      int ow = a;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t q = qb + u * kWave + lane_id();
+        ok[u] = q < total;
+        if (ok[u]) {
+          int h2 = e;
+          while (ow < h2) {
+            const int mid = (ow + h2 + 1) >> 1;
+            if (L.off[mid] <= q) ow = mid;
+            else h2 = mid - 1;
+          }
+          pp[u] = fetch(ow, L.sst[ow] + L.wo[ow] + (q - L.off[ow]));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ok[u]) apply(pp[u]);
+    }
+    __syncthreads();
+  }
+}
+
+// Light tasks (at most CAP entries in the slab): one window, bitmap + rank.
 template <class Sr, class V, int BS, int CAP>
-__global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val,
-                                                 const int32_t* off2, OutC C, const SlabTask* tasks,
-                                                 const int32_t* boff, int32_t S, int32_t nd, int32_t* ctr,
-                                                 int32_t* err) {
+__global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
+                                                 const SlabTask* tasks, const int32_t* boff, int32_t S, int32_t nd,
+                                                 int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
   static_assert(NW * kWave <= kTileWords, "each wavefront owns a multiple of 64 words of a window");
   static_assert(CAP <= 65535, "ranks are 16-bit");
   using Acc = typename Sr::Acc;
-  constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
   __shared__ uint32_t s_bits[kSlabWordsMax];
   __shared__ uint16_t s_rank[kSlabWordsMax];
   __shared__ Acc s_val[CAP];
-  __shared__ V s_a[BS];
-  __shared__ int32_t s_k[BS], s_slen[BS], s_wo[BS];
-  __shared__ int64_t s_sst[BS], s_off[BS], s_wave[NW];
+  __shared__ SlabLds<V, BS> L;
   __shared__ int32_t s_wt[NW];
-  __shared__ int32_t s_tc[kSlabTilesMax + 1];
-  __shared__ int32_t s_boff[kBoffCache + 1];
-  __shared__ int64_t s_slot;
   const int T = b.T, G = b.G;
   for (int x = threadIdx.x; x < kSlabWordsMax; x += BS) s_bits[x] = 0u;
   const bool bcache = S < kBoffCache;
   if (bcache)
-    for (int x = threadIdx.x; x <= S; x += BS) s_boff[x] = boff[x];
+    for (int x = threadIdx.x; x <= S; x += BS) L.boff[x] = boff[x];
   __syncthreads();
   const int wv = wave_id();
-  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &s_slot, [&](int64_t g) {
-    // task g: its slab bucket is the last s with boff[s] <= g
-    int lo = 0, hi = S - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((bcache ? s_boff[mid] : boff[mid]) <= g) lo = mid;
-      else hi = mid - 1;
-    }
-    const SlabTask tk = tasks[(int64_t)lo * nd + (g - (bcache ? s_boff[lo] : boff[lo]))];
-    const int s = tk.s;
-    const int ts0 = s * G, ts1 = ts0 + G < T ? ts0 + G : T;
-    const bool split = tk.m > CAP;
-    if (split && threadIdx.x <= ts1 - ts0) {
-      const int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
-      s_tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
-    }
-    auto load_src = [&](int64_t c0, int nc) {
-      if (threadIdx.x < nc) {
-        const int64_t e = tk.a0 + c0 + threadIdx.x;
-        const int32_t k = a_col[e];
-        s_k[threadIdx.x] = k;
-        s_a[threadIdx.x] = a_val[e];
-        const int64_t* pr = b.prow + (int64_t)s * b.nb + k;
-        const int64_t st = pr[0];
-        s_sst[threadIdx.x] = st;
-        s_slen[threadIdx.x] = (int32_t)(pr[1] - st);
-      }
-    };
+  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &L.slot, [&](int64_t g) {
+    const SlabTask tk = slab_task<V, BS>(tasks, boff, L, bcache, S, nd, g);
+    const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
+    const int32_t m = tk.m < CAP ? tk.m : CAP;
+    if (threadIdx.x == 0 && tk.m > CAP) atomicOr(err, 1);
     const bool one = tk.nsrc <= BS;
-    if (one) load_src(0, tk.nsrc);
+    if (one) slab_load_sources<V, BS>(b, a_col, a_val, tk, 0, tk.nsrc, L);
     __syncthreads();
-    int t0 = ts0;
-    while (t0 < ts1) {
-      int t1 = ts1;
-      int32_t rel0 = 0, mw = tk.m;
-      if (split) {
-        t1 = t0 + 1;
-        while (t1 < ts1 && s_tc[t1 + 1 - ts0] - s_tc[t0 - ts0] <= CAP) ++t1;
-        rel0 = s_tc[t0 - ts0];
-        mw = s_tc[t1 - ts0] - rel0;
+    const int64_t cw0 = (int64_t)ts0 << kTileLog;
+    const int nwords = (ts1 - ts0) * kTileWords;
+    const int wpw = nwords / NW;
+    const uint32_t cmax = (uint32_t)nwords * 32u;
+    // pass 1: the slab's column set
+    auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - cw0); };
+    auto a1 = [&](int32_t c) {
+      if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
+    };
+    slab_window<BS, V>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f1, a1);
+    // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
+    int32_t run = 0;
+    for (int it = 0; it < wpw; it += kWave) {
+      const int w = wv * wpw + it + lane_id();
+      const int32_t pc = __popc(s_bits[w]);
+      const int32_t inc = wave_incl_scan(pc);
+      s_rank[w] = (uint16_t)(run + inc - pc);
+      run += shfl(inc, kWave - 1);
+    }
+    if (lane_id() == 0) s_wt[wv] = run;
+    for (int x = threadIdx.x; x < m; x += BS) s_val[x] = Sr::ident();
+    __syncthreads();
+    int32_t wbase = 0, tot = 0;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      const int32_t v = s_wt[u];
+      wbase += u < wv ? v : 0;
+      tot += v;
+    }
+    if (threadIdx.x == 0 && tot != tk.m) atomicOr(err, 1);
+    if (wbase)
+      for (int it = 0; it < wpw; it += kWave) {
+        const int w = wv * wpw + it + lane_id();
+        s_rank[w] = (uint16_t)(s_rank[w] + wbase);
       }
-      if (mw > 0) {
-        const int64_t cw0 = (int64_t)t0 << kTileLog;
-        const int nwords = (t1 - t0) * kTileWords;
-        const int wpw = nwords / NW;
-        const uint32_t cmax = (uint32_t)nwords * 32u;
-        // products of the window, source chunk by source chunk; pass 1 sets
-        // the bitmap, pass 2 folds values whose rank lies in [r0, r0 + mc)
-        auto gather = [&](bool vals, int32_t r0, int32_t mc) {
-          for (int64_t c0 = 0; c0 < tk.nsrc; c0 += BS) {
-            const int nc = (int)((tk.nsrc - c0) < BS ? (tk.nsrc - c0) : BS);
-            if (!one) {
-              __syncthreads();
-              load_src(c0, nc);
-              __syncthreads();
-            }
-            int64_t len = 0;
-            int32_t wo = 0;
-            if (threadIdx.x < nc) {
-              if (!split) {
-                len = s_slen[threadIdx.x];
-              } else {
-                const int32_t* r = b.rpt + ((int64_t)s * b.nb + s_k[threadIdx.x]) * (G + 1);
-                wo = r[t0 - ts0];
-                len = r[t1 - ts0] - wo;
-              }
-            }
-            int64_t total;
-            const int64_t off = block_excl_scan<NW, int64_t>(len, s_wave, &total);
-            s_off[threadIdx.x] = off;
-            s_wo[threadIdx.x] = wo;
-            __syncthreads();
-            for (int64_t qb = (int64_t)wv * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
-              const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
-              int a = 0, bb = nc - 1;
-              while (a < bb) {
-                const int mid = (a + bb + 1) >> 1;
-                if (s_off[mid] <= qb) a = mid;
-                else bb = mid - 1;
-              }
-              int e = a, f = nc - 1;
-              while (e < f) {
-                const int mid = (e + f + 1) >> 1;
-                if (s_off[mid] <= qe) e = mid;
-                else f = mid - 1;
-              }
-              int32_t cc[kUnroll];
-              Acc vv[kUnroll];
-              int ow = a;
-#pragma unroll
-              for (int u = 0; u < kUnroll; ++u) {
-                const int64_t q = qb + u * kWave + lane_id();
-                cc[u] = -1;
-                if (q < total) {
-                  int h2 = e;
-                  while (ow < h2) {
-                    const int mid = (ow + h2 + 1) >> 1;
-                    if (s_off[mid] <= q) ow = mid;
-                    else h2 = mid - 1;
-                  }
-                  const int64_t idx = s_sst[ow] + s_wo[ow] + (q - s_off[ow]);
-                  cc[u] = (int32_t)(b.pcol[idx] - cw0);
-                  if (vals) vv[u] = Sr::mul(s_a[ow], b.pval[idx]);
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < kUnroll; ++u) {
-                const int32_t c = cc[u];
-                if ((uint32_t)c >= cmax) continue;
-                if (!vals) {
-                  atomicOr(&s_bits[c >> 5], 1u << (c & 31));
-                } else {
-                  const int w = c >> 5;
-                  const int32_t rr = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (c & 31)) - 1u)) - r0;
-                  if ((uint32_t)rr < (uint32_t)mc) Sr::lds_acc(&s_val[rr], vv[u]);
-                }
-              }
-            }
-            __syncthreads();
-          }
-        };
-        gather(false, 0, 0);
-        // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
-        int32_t run = 0;
-        for (int it = 0; it < wpw; it += kWave) {
-          const int w = wv * wpw + it + lane_id();
-          const int32_t pc = __popc(s_bits[w]);
-          const int32_t inc = wave_incl_scan(pc);
-          s_rank[w] = (uint16_t)(run + inc - pc);
-          run += shfl(inc, kWave - 1);
+    __syncthreads();
+    // pass 2: fold every product into its compacted slot
+    auto f2 = [&](int ow, int64_t idx) {
+      return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+    };
+    auto a2 = [&](const ColVal<Acc>& p) {
+      if ((uint32_t)p.c >= cmax) return;
+      const int w = p.c >> 5;
+      const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
+      if (r < m) Sr::lds_acc(&s_val[r], p.v);
+    };
+    slab_window<BS, V>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f2, a2);
+    // column-ordered write-out; clears the bitmap for the next task
+    for (int it = 0; it < wpw; it += kWave) {
+      const int w = wv * wpw + it + lane_id();
+      uint32_t bits = s_bits[w];
+      int32_t r = s_rank[w];
+      while (bits) {
+        const int bt = __ffs((int)bits) - 1;
+        bits &= bits - 1u;
+        if (r < m) {
+          C.col[tk.out + r] = (int32_t)(cw0 + w * 32 + bt);
+          ((V*)C.val)[tk.out + r] = Sr::out(s_val[r]);
         }
-        if (lane_id() == 0) s_wt[wv] = run;
-        __syncthreads();
-        int32_t wbase = 0, tot = 0;
-#pragma unroll
-        for (int u = 0; u < NW; ++u) {
-          const int32_t v = s_wt[u];
-          wbase += u < wv ? v : 0;
-          tot += v;
-        }
-        if (threadIdx.x == 0 && tot != mw) atomicOr(err, 1);
-        if (wbase)
-          for (int it = 0; it < wpw; it += kWave) {
-            const int w = wv * wpw + it + lane_id();
-            s_rank[w] = (uint16_t)(s_rank[w] + wbase);
-          }
-        for (int32_t r0 = 0; r0 < mw; r0 += CAP) {
-          const int32_t mc = (mw - r0) < CAP ? (mw - r0) : CAP;
-          const bool last = r0 + mc >= mw;
-          for (int x = threadIdx.x; x < mc; x += BS) s_val[x] = Sr::ident();
-          __syncthreads();
-          gather(true, r0, mc);
-          // column-ordered write-out of ranks [r0, r0 + mc)
-          for (int it = 0; it < wpw; it += kWave) {
-            const int w = wv * wpw + it + lane_id();
-            uint32_t bits = s_bits[w];
-            int32_t r = s_rank[w];
-            if (r + __popc(bits) > r0 && r < r0 + mc) {
-              while (bits) {
-                const int bt = __ffs((int)bits) - 1;
-                bits &= bits - 1u;
-                const int32_t rr = r - r0;
-                if ((uint32_t)rr < (uint32_t)mc) {
-                  const int64_t pos = tk.out + rel0 + r;
-                  C.col[pos] = (int32_t)(cw0 + w * 32 + bt);
-                  ((V*)C.val)[pos] = Sr::out(s_val[rr]);
-                }
-                ++r;
-              }
-            }
-            if (last) s_bits[w] = 0u;
-          }
-          __syncthreads();
-        }
+        ++r;
       }
-      t0 = t1;
+      s_bits[w] = 0u;
+    }
+    __syncthreads();
+  });
+}
+
+// Heavy tasks: the task's sources are read once; the slab is swept in
+// windows of WD column tiles, each folded in a single pass into a dense LDS
+// accumulator with an occupancy bitmap, then compacted in column order
+// (touched slots are reset to the identity as they are written out).
+template <class Sr, class V, int BS, int WD>
+__global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
+                                                       const int32_t* off2, OutC C, const SlabTask* tasks,
+                                                       const int32_t* boff, int32_t S, int32_t nd, int32_t* ctr,
+                                                       int32_t* err) {
+  constexpr int NW = BS / kWave;
+  constexpr int kW = WD * kTile;
+  constexpr int kWW = WD * kTileWords;
+  static_assert(kWW % BS == 0, "whole words per thread");
+  using Acc = typename Sr::Acc;
+  __shared__ Acc s_acc[kW];
+  __shared__ uint32_t s_bm[kWW];
+  __shared__ SlabLds<V, BS> L;
+  __shared__ int32_t s_wave32[NW];
+  const int T = b.T, G = b.G;
+  for (int x = threadIdx.x; x < kW; x += BS) s_acc[x] = Sr::ident();
+  for (int x = threadIdx.x; x < kWW; x += BS) s_bm[x] = 0u;
+  const bool bcache = S < kBoffCache;
+  if (bcache)
+    for (int x = threadIdx.x; x <= S; x += BS) L.boff[x] = boff[x];
+  __syncthreads();
+  for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, [&](int64_t g) {
+    const SlabTask tk = slab_task<V, BS>(tasks, boff, L, bcache, S, nd, g);
+    const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
+    if ((int)threadIdx.x <= ts1 - ts0) {
+      const int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
+      L.tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
+    }
+    const bool one = tk.nsrc <= BS;
+    if (one) slab_load_sources<V, BS>(b, a_col, a_val, tk, 0, tk.nsrc, L);
+    __syncthreads();
+    for (int t0 = ts0; t0 < ts1; t0 += WD) {
+      const int t1 = t0 + WD < ts1 ? t0 + WD : ts1;
+      const int32_t rel0 = L.tc[t0 - ts0], mw = L.tc[t1 - ts0] - rel0;
+      if (mw <= 0) continue;
+      const int64_t cw0 = (int64_t)t0 << kTileLog;
+      const int nwords = (t1 - t0) * kTileWords;
+      auto f = [&](int ow, int64_t idx) {
+        return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+      };
+      auto ap = [&](const ColVal<Acc>& p) {
+        if ((uint32_t)p.c >= (uint32_t)kW) return;
+        Sr::lds_acc(&s_acc[p.c], p.v);
+        atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
+      };
+      slab_window<BS, V>(b, a_col, a_val, tk, ts0, t0, t1, t0 == ts0 && t1 == ts1, one, L, f, ap);
+      // compaction: round it takes words [it*BS, (it+1)*BS), consecutive
+      // threads on consecutive words
+      int32_t carry = 0;
+      for (int w0 = 0; w0 < nwords; w0 += BS) {
+        const int w = w0 + threadIdx.x;
+        uint32_t bits = w < nwords ? s_bm[w] : 0u;
+        int32_t tot;
+        int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
+        while (bits) {
+          const int bt = __ffs((int)bits) - 1;
+          bits &= bits - 1u;
+          const int c = w * 32 + bt;
+          if (r < mw) {
+            C.col[tk.out + rel0 + r] = (int32_t)(cw0 + c);
+            ((V*)C.val)[tk.out + rel0 + r] = Sr::out(s_acc[c]);
+          }
+          s_acc[c] = Sr::ident();
+          ++r;
+        }
+        if (w < nwords) s_bm[w] = 0u;
+        carry += tot;
+      }
+      if (threadIdx.x == 0 && carry != mw) atomicOr(err, 1);
+      __syncthreads();
     }
   });
 }
