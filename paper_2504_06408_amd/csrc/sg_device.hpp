@@ -87,6 +87,25 @@ SG_DEV T block_sum(T v, T* s_wave) {
 
 SG_DEV int ceil_log2_u64(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll((long long)(x - 1)); }
 
+// Sets bit (c & 31) of bm[c >> 5] for every lane with `valid`.  Lanes of a
+// wavefront that hold the same word are combined first by a segmented OR scan
+// (lanes walking one sorted segment mostly share words), so one lane per run
+// of equal words issues the LDS atomic instead of up to 32 colliding ones.
+// Every lane of the wavefront must call it.
+SG_DEV void wave_or_bits(uint32_t* bm, int32_t c, bool valid) {
+  const int l = lane_id();
+  const int32_t w = valid ? (c >> 5) : -1 - l;
+  uint32_t m = valid ? (1u << (c & 31)) : 0u;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t wo = __shfl_up(w, (unsigned)d, kWave);
+    const uint32_t mo = __shfl_up(m, (unsigned)d, kWave);
+    if (l >= d && wo == w) m |= mo;
+  }
+  const int32_t wn = __shfl_down(w, 1u, kWave);
+  if (valid && (l == kWave - 1 || wn != w)) atomicOr(&bm[w], m);
+}
+
 // ---------------------------------------------------------------------------
 // LDS hash of int32 column ids, linear probing, power-of-two size 2^lgS.
 // Multiplicative hashing spreads the clustered low column ids of power-law

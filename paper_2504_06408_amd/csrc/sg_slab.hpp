@@ -128,82 +128,6 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, con
   }
 }
 
-// Row i of A (x) B restricted to one slab (structure only): one source per
-// stored A_ik, its segment = the slab part of B_k in the partition.
-struct SlabSrc {
-  const DenseRow* drow;
-  const int32_t* a_col;
-  const int64_t* prow;
-  const int32_t* pcol;
-  int64_t nb;
-  int64_t a0;
-  int64_t sb;
-
-  struct Item {
-    uint8_t unused;
-  };
-
-  SG_DEV int64_t bind(int64_t h, int32_t s) {
-    const DenseRow d = drow[h];
-    a0 = d.a0;
-    sb = (int64_t)s * nb;
-    return d.nsrc;
-  }
-  SG_DEV void load(int64_t j, Item&, int64_t& start, int64_t& len) const {
-    const int32_t k = a_col[a0 + j];
-    const int64_t* r = prow + sb + k;
-    start = r[0];
-    len = r[1] - start;
-  }
-  SG_DEV int32_t col(const Item&, int64_t idx) const { return pcol[idx]; }
-};
-
-// ---- symbolic --------------------------------------------------------------------
-// Task g = (slab s, dense row h) with s = g / nd: per-tile popcounts of the
-// slab's bitmap are written raw to off2[h*(T+1) + t]; k_off2_finish turns
-// them into per-row offsets.
-template <int BS>
-__global__ __launch_bounds__(BS) void k_sym_slab(SlabSrc src0, Bins bins, int32_t S, int32_t ls, int32_t T,
-                                                 int32_t* off2, int32_t* ctr) {
-  constexpr int NW = BS / kWave;
-  using Item = SlabSrc::Item;
-  __shared__ uint32_t s_bm[kSlabWordsMax];
-  __shared__ Item s_item[BS];
-  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
-  __shared__ int64_t s_slot;
-  const int nwords = 1 << (ls - 5);
-  const int G = 1 << (ls - kTileLog);
-  for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
-  const int64_t nd = dense_rows(bins);
-  const uint32_t cmax = (uint32_t)nwords * 32u;
-  for_each_queued(ctr, kListSymSlab, nd * S, &s_slot, [&](int64_t g) {
-    const int32_t s = (int32_t)(g / nd);
-    const int64_t h = g - (int64_t)s * nd;
-    SlabSrc sr = src0;
-    const int64_t nsrc = sr.bind(h, s);
-    const int64_t c0 = (int64_t)s << ls;
-    __syncthreads();
-    auto fetch = [&](const Item& it, int64_t idx) { return (int32_t)(sr.col(it, idx) - c0); };
-    auto apply = [&](int32_t c) {
-      if ((uint32_t)c < cmax) atomicOr(&s_bm[c >> 5], 1u << (c & 31));
-    };
-    for_each_product<BS, kUnroll>(sr, nsrc, s_item, s_start, s_off, s_wave, fetch, apply);
-    __syncthreads();
-    int32_t* o2 = off2 + h * (T + 1);
-    for (int tl = wave_id(); tl < G; tl += NW) {
-      int32_t c = 0;
-      for (int x = lane_id(); x < kTileWords; x += kWave) {
-        const int wx = tl * kTileWords + x;
-        c += __popc(s_bm[wx]);
-        s_bm[wx] = 0u;
-      }
-      c = wave_sum(c);
-      const int t = s * G + tl;
-      if (lane_id() == 0 && t < T) o2[t] = c;
-    }
-  });
-}
-
 // One wavefront per dense row: raw per-tile counts -> exclusive offsets,
 // entry T = the row's count, which also goes to cnt_out.
 template <int BS>
@@ -229,15 +153,15 @@ __global__ __launch_bounds__(BS) void k_off2_finish(Bins bins, const DenseRow* d
   }
 }
 
-// ---- numeric ---------------------------------------------------------------------
-// One numeric task per non-empty (dense row, slab), with everything the
-// kernel needs up front (no dependent lookups before the sources).
+// ---- tasks ------------------------------------------------------------------------
+// A task is one (dense row, slab) with everything its kernel needs up front
+// (no dependent lookups before the sources).
 struct SlabTask {
   int32_t h, s;   // position in the dense list, slab
-  int64_t out;    // C position of the slab's first entry
+  int64_t out;    // C position of the slab's first entry (numeric)
   int64_t a0;     // first A entry of the row
   int32_t nsrc;   // A entries of the row
-  int32_t m;      // C entries in the slab
+  int32_t m;      // C entries in the slab (numeric)
 };
 
 // Entries of a light task's LDS value array (32 KB of accumulators).
@@ -309,9 +233,8 @@ struct SlabB {
 
 constexpr int kBoffCache = 256;  // slab-bucket offsets kept in LDS
 
-// LDS of a numeric slab task: its sources (A entry's value and column, the
-// slab segment's start and length) and the current window's per-source
-// offsets.
+// LDS of a slab task: its sources (A entry's value and column, the slab
+// segment's start and length) and the current window's per-source offsets.
 template <class V, int BS>
 struct SlabLds {
   V a[BS];
@@ -335,15 +258,49 @@ SG_DEV SlabTask slab_task(const SlabTask* tasks, const int32_t* boff, const Slab
   return tasks[(int64_t)lo * nd + (g - (bcache ? L.boff[lo] : boff[lo]))];
 }
 
+// The next task of a workgroup, fetched in three dependent stages (record,
+// A entries, slab segments) that ride along with the current task's own
+// memory waits; commit() moves the sources into LDS when the task starts.
+// Only tasks whose sources fit one workgroup chunk are prefetched.
+template <class V, bool kVals, int BS>
+struct SlabNext {
+  SlabTask tk;
+  int32_t k;
+  V a;
+  int64_t sst;
+  int32_t slen;
+  bool has;
+  SG_DEV bool mine() const { return has && tk.nsrc <= BS && (int)threadIdx.x < tk.nsrc; }
+  SG_DEV void sources(const int32_t* a_col, const V* a_val) {
+    if (!mine()) return;
+    const int64_t e = tk.a0 + threadIdx.x;
+    k = a_col[e];
+    if constexpr (kVals) a = a_val[e];
+  }
+  SG_DEV void segments(const SlabB<V>& b) {
+    if (!mine()) return;
+    const int64_t* pr = b.prow + (int64_t)tk.s * b.nb + k;
+    sst = pr[0];
+    slen = (int32_t)(pr[1] - sst);
+  }
+  SG_DEV void commit(SlabLds<V, BS>& L) const {
+    if (!mine()) return;
+    L.k[threadIdx.x] = k;
+    if constexpr (kVals) L.a[threadIdx.x] = a;
+    L.sst[threadIdx.x] = sst;
+    L.slen[threadIdx.x] = slen;
+  }
+};
+
 // Sources [c0, c0 + nc) of task tk into LDS (one per thread).
-template <class V, int BS>
+template <class V, bool kVals, int BS>
 SG_DEV void slab_load_sources(const SlabB<V>& b, const int32_t* a_col, const V* a_val, const SlabTask& tk,
                               int64_t c0, int nc, SlabLds<V, BS>& L) {
   if ((int)threadIdx.x < nc) {
     const int64_t e = tk.a0 + c0 + threadIdx.x;
     const int32_t k = a_col[e];
     L.k[threadIdx.x] = k;
-    L.a[threadIdx.x] = a_val[e];
+    if constexpr (kVals) L.a[threadIdx.x] = a_val[e];
     const int64_t* pr = b.prow + (int64_t)tk.s * b.nb + k;
     const int64_t st = pr[0];
     L.sst[threadIdx.x] = st;
@@ -353,11 +310,13 @@ SG_DEV void slab_load_sources(const SlabB<V>& b, const int32_t* a_col, const V* 
 
 // Every product of window [t0, t1) (tiles, inside the task's slab whose first
 // tile is ts0) of task tk: fetch(owner, index into pcol/pval) returns a
-// product, apply(product) folds it into LDS.  With `one` the task's sources
-// are already in LDS; otherwise they are loaded chunk by chunk.  Sources'
-// window segments come from rpt unless the window is the whole slab.  Lanes
-// take consecutive products (coalesced gathers), kUnroll loads in flight each.
-template <int BS, class V, class Fetch, class Apply>
+// product and apply(product, valid) folds it into LDS; apply is called by
+// every lane, with valid false where a lane has no product.  With `one` the
+// task's sources are already in LDS; otherwise they are loaded chunk by
+// chunk.  Sources' window segments come from rpt unless the window is the
+// whole slab.  Lanes take consecutive products (coalesced gathers), kUnroll
+// loads in flight each.
+template <int BS, class V, bool kVals, class Fetch, class Apply>
 SG_DEV void slab_window(const SlabB<V>& b, const int32_t* a_col, const V* a_val, const SlabTask& tk, int ts0,
                         int t0, int t1, bool whole, bool one, SlabLds<V, BS>& L, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
@@ -368,7 +327,7 @@ SG_DEV void slab_window(const SlabB<V>& b, const int32_t* a_col, const V* a_val,
     const int nc = (int)((tk.nsrc - c0) < BS ? (tk.nsrc - c0) : BS);
     if (!one) {
       __syncthreads();
-      slab_load_sources<V, BS>(b, a_col, a_val, tk, c0, nc, L);
+      slab_load_sources<V, kVals, BS>(b, a_col, a_val, tk, c0, nc, L);
       __syncthreads();
     }
     int64_t len = 0;
@@ -419,18 +378,78 @@ SG_DEV void slab_window(const SlabB<V>& b, const int32_t* a_col, const V* a_val,
         }
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (ok[u]) apply(pp[u]);
+      for (int u = 0; u < kUnroll; ++u) apply(pp[u], ok[u]);
     }
     __syncthreads();
   }
 }
 
+// ---- symbolic --------------------------------------------------------------------
+// Task g = (slab s = g / nd, dense row h = g % nd), tasks in slab-major order,
+// workgroup b takes tasks b, b + grid, ... (the next one prefetched).  The
+// per-tile popcounts of the slab's bitmap are written raw to
+// off2[h*(T+1) + t]; k_off2_finish turns them into per-row offsets.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
+                                                 Bins bins, int32_t S, int32_t* off2) {
+  constexpr int NW = BS / kWave;
+  __shared__ uint32_t s_bm[kSlabWordsMax];
+  __shared__ SlabLds<uint8_t, BS> L;
+  const int T = b.T, G = b.G;
+  const int nwords = G * kTileWords;
+  for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
+  const int64_t nd = dense_rows(bins);
+  const int64_t ntask = nd * S;
+  const uint32_t cmax = (uint32_t)nwords * 32u;
+  auto record = [&](int64_t g, SlabNext<uint8_t, false, BS>& nx) {
+    nx.has = g < ntask;
+    if (!nx.has) return;
+    const int32_t s = (int32_t)(g / nd);
+    const int64_t h = g - (int64_t)s * nd;
+    const DenseRow d = dr[h];
+    nx.tk = SlabTask{(int32_t)h, s, 0, d.a0, d.nsrc, 0};
+  };
+  SlabNext<uint8_t, false, BS> nx;
+  record(blockIdx.x, nx);
+  nx.sources(a_col, nullptr);
+  nx.segments(b);
+  for (int64_t g = blockIdx.x; g < ntask; g += gridDim.x) {
+    const SlabTask tk = nx.tk;
+    nx.commit(L);
+    __syncthreads();
+    const bool one = tk.nsrc <= BS;
+    record(g + gridDim.x, nx);
+    const int ts0 = tk.s * G;
+    const int64_t c0 = (int64_t)ts0 << kTileLog;
+    auto fetch = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - c0); };
+    auto apply = [&](int32_t c, bool ok) { wave_or_bits(s_bm, c, ok && (uint32_t)c < cmax); };
+    slab_window<BS, uint8_t, false>(b, a_col, nullptr, tk, ts0, ts0, ts0 + G, true, one, L, fetch, apply);
+    nx.sources(a_col, nullptr);
+    int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
+    for (int tl = wave_id(); tl < G; tl += NW) {
+      int32_t c = 0;
+      for (int x = lane_id(); x < kTileWords; x += kWave) {
+        const int wx = tl * kTileWords + x;
+        c += __popc(s_bm[wx]);
+        s_bm[wx] = 0u;
+      }
+      c = wave_sum(c);
+      const int t = ts0 + tl;
+      if (lane_id() == 0 && t < T) o2[t] = c;
+    }
+    nx.segments(b);
+    __syncthreads();
+  }
+}
+
+// ---- numeric ---------------------------------------------------------------------
 // Light tasks (at most CAP entries in the slab): one window, bitmap + rank.
+// Workgroup b takes tasks b, b + grid, ... of the slab-major list, the next
+// one prefetched.
 template <class Sr, class V, int BS, int CAP>
 __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
                                                  const SlabTask* tasks, const int32_t* boff, int32_t S, int32_t nd,
-                                                 int32_t* ctr, int32_t* err) {
+                                                 const int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
   static_assert(NW * kWave <= kTileWords, "each wavefront owns a multiple of 64 words of a window");
   static_assert(CAP <= 65535, "ranks are 16-bit");
@@ -446,25 +465,34 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
   if (bcache)
     for (int x = threadIdx.x; x <= S; x += BS) L.boff[x] = boff[x];
   __syncthreads();
+  const int64_t ntask = ctr[kListSlab];
   const int wv = wave_id();
-  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &L.slot, [&](int64_t g) {
-    const SlabTask tk = slab_task<V, BS>(tasks, boff, L, bcache, S, nd, g);
+  auto record = [&](int64_t g, SlabNext<V, true, BS>& nx) {
+    nx.has = g < ntask;
+    if (nx.has) nx.tk = slab_task<V, BS>(tasks, boff, L, bcache, S, nd, g);
+  };
+  SlabNext<V, true, BS> nx;
+  record(blockIdx.x, nx);
+  nx.sources(a_col, a_val);
+  nx.segments(b);
+  for (int64_t g = blockIdx.x; g < ntask; g += gridDim.x) {
+    const SlabTask tk = nx.tk;
+    nx.commit(L);
+    __syncthreads();
+    record(g + gridDim.x, nx);
     const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
     const int32_t m = tk.m < CAP ? tk.m : CAP;
     if (threadIdx.x == 0 && tk.m > CAP) atomicOr(err, 1);
     const bool one = tk.nsrc <= BS;
-    if (one) slab_load_sources<V, BS>(b, a_col, a_val, tk, 0, tk.nsrc, L);
-    __syncthreads();
     const int64_t cw0 = (int64_t)ts0 << kTileLog;
     const int nwords = (ts1 - ts0) * kTileWords;
     const int wpw = nwords / NW;
     const uint32_t cmax = (uint32_t)nwords * 32u;
     // pass 1: the slab's column set
     auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - cw0); };
-    auto a1 = [&](int32_t c) {
-      if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
-    };
-    slab_window<BS, V>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f1, a1);
+    auto a1 = [&](int32_t c, bool ok) { wave_or_bits(s_bits, c, ok && (uint32_t)c < cmax); };
+    slab_window<BS, V, true>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f1, a1);
+    nx.sources(a_col, a_val);
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
     int32_t run = 0;
     for (int it = 0; it < wpw; it += kWave) {
@@ -495,13 +523,14 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     auto f2 = [&](int ow, int64_t idx) {
       return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
     };
-    auto a2 = [&](const ColVal<Acc>& p) {
-      if ((uint32_t)p.c >= cmax) return;
+    auto a2 = [&](const ColVal<Acc>& p, bool ok) {
+      if (!ok || (uint32_t)p.c >= cmax) return;
       const int w = p.c >> 5;
       const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
       if (r < m) Sr::lds_acc(&s_val[r], p.v);
     };
-    slab_window<BS, V>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f2, a2);
+    slab_window<BS, V, true>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f2, a2);
+    nx.segments(b);
     // column-ordered write-out; clears the bitmap for the next task
     for (int it = 0; it < wpw; it += kWave) {
       const int w = wv * wpw + it + lane_id();
@@ -519,13 +548,14 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       s_bits[w] = 0u;
     }
     __syncthreads();
-  });
+  }
 }
 
 // Heavy tasks: the task's sources are read once; the slab is swept in
 // windows of WD column tiles, each folded in a single pass into a dense LDS
 // accumulator with an occupancy bitmap, then compacted in column order
-// (touched slots are reset to the identity as they are written out).
+// (touched slots are reset to the identity as they are written out).  Tasks
+// vary widely in size, so workgroups take them from the interleaved queues.
 template <class Sr, class V, int BS, int WD>
 __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
                                                        const int32_t* off2, OutC C, const SlabTask* tasks,
@@ -534,7 +564,6 @@ __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t
   constexpr int NW = BS / kWave;
   constexpr int kW = WD * kTile;
   constexpr int kWW = WD * kTileWords;
-  static_assert(kWW % BS == 0, "whole words per thread");
   using Acc = typename Sr::Acc;
   __shared__ Acc s_acc[kW];
   __shared__ uint32_t s_bm[kWW];
@@ -555,7 +584,7 @@ __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t
       L.tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
     }
     const bool one = tk.nsrc <= BS;
-    if (one) slab_load_sources<V, BS>(b, a_col, a_val, tk, 0, tk.nsrc, L);
+    if (one) slab_load_sources<V, true, BS>(b, a_col, a_val, tk, 0, tk.nsrc, L);
     __syncthreads();
     for (int t0 = ts0; t0 < ts1; t0 += WD) {
       const int t1 = t0 + WD < ts1 ? t0 + WD : ts1;
@@ -566,14 +595,14 @@ __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t
       auto f = [&](int ow, int64_t idx) {
         return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
       };
-      auto ap = [&](const ColVal<Acc>& p) {
-        if ((uint32_t)p.c >= (uint32_t)kW) return;
-        Sr::lds_acc(&s_acc[p.c], p.v);
-        atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
+      auto ap = [&](const ColVal<Acc>& p, bool ok) {
+        const bool in = ok && (uint32_t)p.c < (uint32_t)kW;
+        if (in) Sr::lds_acc(&s_acc[p.c], p.v);
+        wave_or_bits(s_bm, p.c, in);
       };
-      slab_window<BS, V>(b, a_col, a_val, tk, ts0, t0, t1, t0 == ts0 && t1 == ts1, one, L, f, ap);
-      // compaction: round it takes words [it*BS, (it+1)*BS), consecutive
-      // threads on consecutive words
+      slab_window<BS, V, true>(b, a_col, a_val, tk, ts0, t0, t1, t0 == ts0 && t1 == ts1, one, L, f, ap);
+      // compaction: round w0 takes words [w0, w0 + BS), consecutive threads
+      // on consecutive words
       int32_t carry = 0;
       for (int w0 = 0; w0 < nwords; w0 += BS) {
         const int w = w0 + threadIdx.x;
