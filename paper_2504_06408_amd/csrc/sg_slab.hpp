@@ -154,14 +154,15 @@ __global__ __launch_bounds__(BS) void k_off2_finish(Bins bins, const DenseRow* d
 }
 
 // ---- tasks ------------------------------------------------------------------------
-// A task is one (dense row, slab) with everything its kernel needs up front
-// (no dependent lookups before the sources).
+// A numeric task is a window of whole column tiles [t0, t1) of one dense row
+// inside one slab, with everything its kernel needs up front.
 struct SlabTask {
-  int32_t h, s;   // position in the dense list, slab
-  int64_t out;    // C position of the slab's first entry (numeric)
-  int64_t a0;     // first A entry of the row
-  int32_t nsrc;   // A entries of the row
-  int32_t m;      // C entries in the slab (numeric)
+  int32_t h, s;    // position in the dense list, slab
+  int32_t t0, t1;  // window tiles
+  int64_t out;     // C position of the window's first entry
+  int64_t a0;      // first A entry of the row
+  int32_t nsrc;    // A entries of the row
+  int32_t m;       // C entries in the window
 };
 
 // Entries of a light task's LDS value array (32 KB of accumulators).
@@ -170,51 +171,66 @@ constexpr int slab_cap() {
   return 32768 / (int)sizeof(typename Sr::Acc);
 }
 
-// Column tiles per window of a heavy task's dense accumulator (128 KB or
-// less of accumulators).
-template <class Sr>
-constexpr int heavy_tiles() {
-  return sizeof(typename Sr::Acc) >= 8 ? 1 : (sizeof(typename Sr::Acc) >= 4 ? 2 : 4);
-}
-
-// One thread per dense row.  A slab with at most `cap` entries becomes a
-// light task (list kListSlab), a fuller one a heavy task (list kListTile);
-// both lists hold per-slab buckets of nd slots (book[l*T + s] counts bucket
-// s of list l).  Entries per list are summed for the statistics.
+// One thread per dense row.  A slab with at most `cap` entries is one light
+// window.  In a fuller slab, every tile with at least `tile_min` entries (or
+// more than `cap`) is a dense-tile task, and runs of the other tiles are
+// light windows of at most `cap` entries.  Both lists hold per-tile buckets
+// of nd slots (a window goes to the bucket of its first tile; book[l*T + t]
+// counts bucket t of list l), so walking them in order is slab-major.
+// Entries per list are summed for the statistics.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr, const int32_t* off2, int32_t T,
-                                                   int32_t G, int32_t cap, const int64_t* c_rowptr,
-                                                   SlabTask* light, SlabTask* heavy, int32_t* book, int32_t* ctr) {
+                                                   int32_t G, int32_t cap, int32_t tile_min,
+                                                   const int64_t* c_rowptr, SlabTask* light, SlabTask* dense,
+                                                   int32_t* book, int32_t* ctr) {
   __shared__ unsigned long long s_ent[2];
   if (threadIdx.x < 2) s_ent[threadIdx.x] = 0ull;
   __syncthreads();
   const int64_t nd = dense_rows(bins);
   int32_t* cnt_l = book + kListSlab * T;
-  int32_t* cnt_h = book + kListTile * T;
-  unsigned long long el = 0ull, eh = 0ull;
+  int32_t* cnt_d = book + kListTile * T;
+  unsigned long long el = 0ull, ed = 0ull;
   for (int64_t h = (int64_t)blockIdx.x * BS + threadIdx.x; h < nd; h += (int64_t)gridDim.x * BS) {
     const DenseRow d = dr[h];
     const int32_t* o2 = off2 + h * (T + 1);
     const int64_t base = c_rowptr[d.i];
+    auto put_light = [&](int32_t s, int32_t t0, int32_t t1) {
+      const int32_t m = o2[t1] - o2[t0];
+      if (m <= 0) return;
+      light[(int64_t)t0 * nd + atomicAdd(&cnt_l[t0], 1)] =
+          SlabTask{(int32_t)h, s, t0, t1, base + o2[t0], d.a0, d.nsrc, m};
+      el += (unsigned long long)m;
+    };
     int32_t s = 0;
     for (int32_t ta = 0; ta < T; ta += G, ++s) {
       const int32_t tb = ta + G < T ? ta + G : T;
-      const int32_t lo = o2[ta], m = o2[tb] - lo;
-      if (m <= 0) continue;
-      const SlabTask tk{(int32_t)h, s, base + lo, d.a0, d.nsrc, m};
-      if (m <= cap) {
-        light[(int64_t)s * nd + atomicAdd(&cnt_l[s], 1)] = tk;
-        el += (unsigned long long)m;
-      } else {
-        heavy[(int64_t)s * nd + atomicAdd(&cnt_h[s], 1)] = tk;
-        eh += (unsigned long long)m;
+      const int32_t ms = o2[tb] - o2[ta];
+      if (ms <= 0) continue;
+      if (ms <= cap) {
+        put_light(s, ta, tb);
+        continue;
       }
+      int32_t w0 = ta;  // pending light window [w0, t)
+      for (int32_t t = ta; t < tb; ++t) {
+        const int32_t c = o2[t + 1] - o2[t];
+        if (c >= tile_min || c > cap) {
+          put_light(s, w0, t);
+          dense[(int64_t)t * nd + atomicAdd(&cnt_d[t], 1)] =
+              SlabTask{(int32_t)h, s, t, t + 1, base + o2[t], d.a0, d.nsrc, c};
+          ed += (unsigned long long)c;
+          w0 = t + 1;
+        } else if (o2[t + 1] - o2[w0] > cap) {
+          put_light(s, w0, t);
+          w0 = t;
+        }
+      }
+      put_light(s, w0, tb);
     }
   }
   el = wave_sum(el);
-  eh = wave_sum(eh);
+  ed = wave_sum(ed);
   if (lane_id() == 0 && el) atomicAdd(&s_ent[0], el);
-  if (lane_id() == 0 && eh) atomicAdd(&s_ent[1], eh);
+  if (lane_id() == 0 && ed) atomicAdd(&s_ent[1], ed);
   __syncthreads();
   unsigned long long* ent = (unsigned long long*)(ctr + kCtrEntries);
   if (threadIdx.x == 0 && s_ent[0]) atomicAdd(ent + kListSlab, s_ent[0]);
@@ -231,25 +247,24 @@ struct SlabB {
   int32_t G, T;
 };
 
-constexpr int kBoffCache = 256;  // slab-bucket offsets kept in LDS
+constexpr int kBoffCache = 256;  // bucket offsets kept in LDS
 
-// LDS of a slab task: its sources (A entry's value and column, the slab
-// segment's start and length) and the current window's per-source offsets.
+// LDS of one chunk of a task's sources: the A value, the start of the
+// source's window segment in pcol/pval, and the exclusive prefix of the
+// segment lengths.
 template <class V, int BS>
-struct SlabLds {
+struct SrcLds {
   V a[BS];
-  int32_t k[BS], slen[BS], wo[BS];
-  int64_t sst[BS], off[BS], wave[BS / kWave];
-  int32_t tc[kSlabTilesMax + 1];
+  int64_t st[BS], off[BS], wave[BS / kWave];
   int32_t boff[kBoffCache + 1];
   int64_t slot;
 };
 
-// Task g of a slab-bucketed list: its bucket is the last s with boff[s] <= g.
+// Task g of a bucketed list: its bucket is the last t with boff[t] <= g.
 template <class V, int BS>
-SG_DEV SlabTask slab_task(const SlabTask* tasks, const int32_t* boff, const SlabLds<V, BS>& L, bool bcache,
-                          int32_t S, int32_t nd, int64_t g) {
-  int lo = 0, hi = S - 1;
+SG_DEV SlabTask bucket_slab_task(const SlabTask* tasks, const int32_t* boff, const SrcLds<V, BS>& L, bool bcache,
+                                 int32_t nb, int32_t nd, int64_t g) {
+  int lo = 0, hi = nb - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if ((bcache ? L.boff[mid] : boff[mid]) <= g) lo = mid;
@@ -258,174 +273,130 @@ SG_DEV SlabTask slab_task(const SlabTask* tasks, const int32_t* boff, const Slab
   return tasks[(int64_t)lo * nd + (g - (bcache ? L.boff[lo] : boff[lo]))];
 }
 
-// The next task of a workgroup, fetched in three dependent stages (record,
-// A entries, slab segments) that ride along with the current task's own
-// memory waits; commit() moves the sources into LDS when the task starts.
-// Only tasks whose sources fit one workgroup chunk are prefetched.
+// Sources [c0, c0 + nc) of the row starting at A entry a0, restricted to
+// tiles [s*G + tr0, s*G + tr1) of slab s (whole: the full slab segment, from
+// prow alone; otherwise prow + the tile offsets rpt), one per thread, then a
+// block scan of the segment lengths.  Returns the chunk's product count.
 template <class V, bool kVals, int BS>
-struct SlabNext {
-  SlabTask tk;
-  int32_t k;
-  V a;
-  int64_t sst;
-  int32_t slen;
-  bool has;
-  SG_DEV bool mine() const { return has && tk.nsrc <= BS && (int)threadIdx.x < tk.nsrc; }
-  SG_DEV void sources(const int32_t* a_col, const V* a_val) {
-    if (!mine()) return;
-    const int64_t e = tk.a0 + threadIdx.x;
-    k = a_col[e];
-    if constexpr (kVals) a = a_val[e];
-  }
-  SG_DEV void segments(const SlabB<V>& b) {
-    if (!mine()) return;
-    const int64_t* pr = b.prow + (int64_t)tk.s * b.nb + k;
-    sst = pr[0];
-    slen = (int32_t)(pr[1] - sst);
-  }
-  SG_DEV void commit(SlabLds<V, BS>& L) const {
-    if (!mine()) return;
-    L.k[threadIdx.x] = k;
-    if constexpr (kVals) L.a[threadIdx.x] = a;
-    L.sst[threadIdx.x] = sst;
-    L.slen[threadIdx.x] = slen;
-  }
-};
-
-// Sources [c0, c0 + nc) of task tk into LDS (one per thread).
-template <class V, bool kVals, int BS>
-SG_DEV void slab_load_sources(const SlabB<V>& b, const int32_t* a_col, const V* a_val, const SlabTask& tk,
-                              int64_t c0, int nc, SlabLds<V, BS>& L) {
+SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t s,
+                          int32_t tr0, int32_t tr1, bool whole, int64_t c0, int nc, SrcLds<V, BS>& L) {
+  int64_t st = 0, len = 0;
   if ((int)threadIdx.x < nc) {
-    const int64_t e = tk.a0 + c0 + threadIdx.x;
+    const int64_t e = a0 + c0 + threadIdx.x;
     const int32_t k = a_col[e];
-    L.k[threadIdx.x] = k;
     if constexpr (kVals) L.a[threadIdx.x] = a_val[e];
-    const int64_t* pr = b.prow + (int64_t)tk.s * b.nb + k;
-    const int64_t st = pr[0];
-    L.sst[threadIdx.x] = st;
-    L.slen[threadIdx.x] = (int32_t)(pr[1] - st);
+    const int64_t* pr = b.prow + (int64_t)s * b.nb + k;
+    st = pr[0];
+    if (whole) {
+      len = pr[1] - st;
+    } else {
+      const int32_t* r = b.rpt + ((int64_t)s * b.nb + k) * (b.G + 1);
+      const int32_t w0 = r[tr0];
+      st += w0;
+      len = r[tr1] - w0;
+    }
   }
+  int64_t total;
+  const int64_t off = block_excl_scan<BS / kWave, int64_t>(len, L.wave, &total);
+  L.st[threadIdx.x] = st;
+  L.off[threadIdx.x] = off;
+  __syncthreads();
+  return total;
 }
 
-// Every product of window [t0, t1) (tiles, inside the task's slab whose first
-// tile is ts0) of task tk: fetch(owner, index into pcol/pval) returns a
-// product and apply(product, valid) folds it into LDS; apply is called by
-// every lane, with valid false where a lane has no product.  With `one` the
-// task's sources are already in LDS; otherwise they are loaded chunk by
-// chunk.  Sources' window segments come from rpt unless the window is the
-// whole slab.  Lanes take consecutive products (coalesced gathers), kUnroll
-// loads in flight each.
-template <int BS, class V, bool kVals, class Fetch, class Apply>
-SG_DEV void slab_window(const SlabB<V>& b, const int32_t* a_col, const V* a_val, const SlabTask& tk, int ts0,
-                        int t0, int t1, bool whole, bool one, SlabLds<V, BS>& L, Fetch& fetch, Apply& apply) {
+// Flattened walk over the chunk's `total` products: wavefront w takes blocks
+// of 64*kUnroll consecutive products, lane l products q = qb + u*64 + l, so
+// every load instruction is coalesced; owners are found by a search narrowed
+// to the block's first and last owner.  fetch(owner, index into pcol/pval)
+// returns a product, apply(product) folds it into LDS.
+template <int BS, class V, class Fetch, class Apply>
+SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
   constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
   using P = decltype(fetch(0, (int64_t)0));
-  const int wv = wave_id();
-  for (int64_t c0 = 0; c0 < tk.nsrc; c0 += BS) {
-    const int nc = (int)((tk.nsrc - c0) < BS ? (tk.nsrc - c0) : BS);
-    if (!one) {
-      __syncthreads();
-      slab_load_sources<V, kVals, BS>(b, a_col, a_val, tk, c0, nc, L);
-      __syncthreads();
+  for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
+    const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
+    int a = 0, bb = nc - 1;
+    while (a < bb) {
+      const int mid = (a + bb + 1) >> 1;
+      if (L.off[mid] <= qb) a = mid;
+      else bb = mid - 1;
     }
-    int64_t len = 0;
-    int32_t wo = 0;
-    if ((int)threadIdx.x < nc) {
-      if (whole) {
-        len = L.slen[threadIdx.x];
-      } else {
-        const int32_t* r = b.rpt + ((int64_t)tk.s * b.nb + L.k[threadIdx.x]) * (b.G + 1);
-        wo = r[t0 - ts0];
-        len = r[t1 - ts0] - wo;
-      }
+    int e = a, f = nc - 1;
+    while (e < f) {
+      const int mid = (e + f + 1) >> 1;
+      if (L.off[mid] <= qe) e = mid;
+      else f = mid - 1;
     }
-    int64_t total;
-    const int64_t off = block_excl_scan<NW, int64_t>(len, L.wave, &total);
-    L.off[threadIdx.x] = off;
-    L.wo[threadIdx.x] = wo;
-    __syncthreads();
-    for (int64_t qb = (int64_t)wv * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
-      const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
-      int a = 0, bb = nc - 1;
-      while (a < bb) {
-        const int mid = (a + bb + 1) >> 1;
-        if (L.off[mid] <= qb) a = mid;
-        else bb = mid - 1;
-      }
-      int e = a, f = nc - 1;
-      while (e < f) {
-        const int mid = (e + f + 1) >> 1;
-        if (L.off[mid] <= qe) e = mid;
-        else f = mid - 1;
-      }
-      P pp[kUnroll];
-      bool ok[kUnroll];
-      int ow = a;
+    P pp[kUnroll];
+    bool ok[kUnroll];
+    int ow = a;
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int64_t q = qb + u * kWave + lane_id();
-        ok[u] = q < total;
-        if (ok[u]) {
-          int h2 = e;
-          while (ow < h2) {
-            const int mid = (ow + h2 + 1) >> 1;
-            if (L.off[mid] <= q) ow = mid;
-            else h2 = mid - 1;
-          }
-          pp[u] = fetch(ow, L.sst[ow] + L.wo[ow] + (q - L.off[ow]));
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t q = qb + u * kWave + lane_id();
+      ok[u] = q < total;
+      if (ok[u]) {
+        int h2 = e;
+        while (ow < h2) {
+          const int mid = (ow + h2 + 1) >> 1;
+          if (L.off[mid] <= q) ow = mid;
+          else h2 = mid - 1;
         }
+        pp[u] = fetch(ow, L.st[ow] + (q - L.off[ow]));
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) apply(pp[u], ok[u]);
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (ok[u]) apply(pp[u]);
+  }
+}
+
+// All products of a window of task (a0, nsrc, s, tr0, tr1): chunk by chunk
+// unless the caller already loaded the single chunk (`loaded`, total).
+template <int BS, class V, bool kVals, class Fetch, class Apply>
+SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
+                          int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int64_t total,
+                          SrcLds<V, BS>& L, Fetch& fetch, Apply& apply) {
+  if (loaded) {
+    slab_iterate<BS, V>(L, nsrc, total, fetch, apply);
+    return;
+  }
+  for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
+    const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
     __syncthreads();
+    const int64_t tc = slab_chunk<V, kVals, BS>(b, a_col, a_val, a0, s, tr0, tr1, whole, c0, nc, L);
+    slab_iterate<BS, V>(L, nc, tc, fetch, apply);
   }
 }
 
 // ---- symbolic --------------------------------------------------------------------
-// Task g = (slab s = g / nd, dense row h = g % nd), tasks in slab-major order,
-// workgroup b takes tasks b, b + grid, ... (the next one prefetched).  The
-// per-tile popcounts of the slab's bitmap are written raw to
-// off2[h*(T+1) + t]; k_off2_finish turns them into per-row offsets.
+// Task g = (slab s = g / nd, dense row h = g % nd), slab-major, from the
+// interleaved queues.  The per-tile popcounts of the slab's bitmap are written
+// raw to off2[h*(T+1) + t]; k_off2_finish turns them into per-row offsets.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
-                                                 Bins bins, int32_t S, int32_t* off2) {
+                                                 Bins bins, int32_t S, int32_t* off2, int32_t* ctr) {
   constexpr int NW = BS / kWave;
   __shared__ uint32_t s_bm[kSlabWordsMax];
-  __shared__ SlabLds<uint8_t, BS> L;
+  __shared__ SrcLds<uint8_t, BS> L;
   const int T = b.T, G = b.G;
   const int nwords = G * kTileWords;
   for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
   const int64_t nd = dense_rows(bins);
-  const int64_t ntask = nd * S;
   const uint32_t cmax = (uint32_t)nwords * 32u;
-  auto record = [&](int64_t g, SlabNext<uint8_t, false, BS>& nx) {
-    nx.has = g < ntask;
-    if (!nx.has) return;
+  for_each_queued(ctr, kListSymSlab, nd * S, &L.slot, [&](int64_t g) {
     const int32_t s = (int32_t)(g / nd);
     const int64_t h = g - (int64_t)s * nd;
     const DenseRow d = dr[h];
-    nx.tk = SlabTask{(int32_t)h, s, 0, d.a0, d.nsrc, 0};
-  };
-  SlabNext<uint8_t, false, BS> nx;
-  record(blockIdx.x, nx);
-  nx.sources(a_col, nullptr);
-  nx.segments(b);
-  for (int64_t g = blockIdx.x; g < ntask; g += gridDim.x) {
-    const SlabTask tk = nx.tk;
-    nx.commit(L);
-    __syncthreads();
-    const bool one = tk.nsrc <= BS;
-    record(g + gridDim.x, nx);
-    const int ts0 = tk.s * G;
+    const int ts0 = s * G;
     const int64_t c0 = (int64_t)ts0 << kTileLog;
     auto fetch = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - c0); };
-    auto apply = [&](int32_t c, bool ok) { wave_or_bits(s_bm, c, ok && (uint32_t)c < cmax); };
-    slab_window<BS, uint8_t, false>(b, a_col, nullptr, tk, ts0, ts0, ts0 + G, true, one, L, fetch, apply);
-    nx.sources(a_col, nullptr);
-    int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
+    auto apply = [&](int32_t c) {
+      if ((uint32_t)c < cmax) atomicOr(&s_bm[c >> 5], 1u << (c & 31));
+    };
+    slab_products<BS, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, L, fetch, apply);
+    __syncthreads();
+    int32_t* o2 = off2 + h * (T + 1);
     for (int tl = wave_id(); tl < G; tl += NW) {
       int32_t c = 0;
       for (int x = lane_id(); x < kTileWords; x += kWave) {
@@ -437,19 +408,16 @@ __global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRo
       const int t = ts0 + tl;
       if (lane_id() == 0 && t < T) o2[t] = c;
     }
-    nx.segments(b);
-    __syncthreads();
-  }
+  });
 }
 
 // ---- numeric ---------------------------------------------------------------------
-// Light tasks (at most CAP entries in the slab): one window, bitmap + rank.
-// Workgroup b takes tasks b, b + grid, ... of the slab-major list, the next
-// one prefetched.
+// Light windows (at most CAP entries): bitmap + rank, two passes over the
+// products (sources loaded once when one chunk holds them).
 template <class Sr, class V, int BS, int CAP>
 __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
-                                                 const SlabTask* tasks, const int32_t* boff, int32_t S, int32_t nd,
-                                                 const int32_t* ctr, int32_t* err) {
+                                                 const SlabTask* tasks, const int32_t* boff, int32_t nd,
+                                                 int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
   static_assert(NW * kWave <= kTileWords, "each wavefront owns a multiple of 64 words of a window");
   static_assert(CAP <= 65535, "ranks are 16-bit");
@@ -457,42 +425,37 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
   __shared__ uint32_t s_bits[kSlabWordsMax];
   __shared__ uint16_t s_rank[kSlabWordsMax];
   __shared__ Acc s_val[CAP];
-  __shared__ SlabLds<V, BS> L;
+  __shared__ SrcLds<V, BS> L;
   __shared__ int32_t s_wt[NW];
   const int T = b.T, G = b.G;
   for (int x = threadIdx.x; x < kSlabWordsMax; x += BS) s_bits[x] = 0u;
-  const bool bcache = S < kBoffCache;
+  const bool bcache = T < kBoffCache;
   if (bcache)
-    for (int x = threadIdx.x; x <= S; x += BS) L.boff[x] = boff[x];
+    for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
   __syncthreads();
-  const int64_t ntask = ctr[kListSlab];
   const int wv = wave_id();
-  auto record = [&](int64_t g, SlabNext<V, true, BS>& nx) {
-    nx.has = g < ntask;
-    if (nx.has) nx.tk = slab_task<V, BS>(tasks, boff, L, bcache, S, nd, g);
-  };
-  SlabNext<V, true, BS> nx;
-  record(blockIdx.x, nx);
-  nx.sources(a_col, a_val);
-  nx.segments(b);
-  for (int64_t g = blockIdx.x; g < ntask; g += gridDim.x) {
-    const SlabTask tk = nx.tk;
-    nx.commit(L);
-    __syncthreads();
-    record(g + gridDim.x, nx);
+  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &L.slot, [&](int64_t g) {
+    const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
     const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
+    const bool whole = tk.t0 == ts0 && tk.t1 == ts1;
+    const int32_t tr0 = tk.t0 - ts0, tr1 = tk.t1 - ts0;
     const int32_t m = tk.m < CAP ? tk.m : CAP;
     if (threadIdx.x == 0 && tk.m > CAP) atomicOr(err, 1);
-    const bool one = tk.nsrc <= BS;
-    const int64_t cw0 = (int64_t)ts0 << kTileLog;
-    const int nwords = (ts1 - ts0) * kTileWords;
+    const int64_t cw0 = (int64_t)tk.t0 << kTileLog;
+    const int nwords = (tk.t1 - tk.t0) * kTileWords;
     const int wpw = nwords / NW;
     const uint32_t cmax = (uint32_t)nwords * 32u;
-    // pass 1: the slab's column set
+    const bool one = tk.nsrc <= BS;
+    int64_t total = 0;
+    __syncthreads();
+    if (one) total = slab_chunk<V, true, BS>(b, a_col, a_val, tk.a0, tk.s, tr0, tr1, whole, 0, tk.nsrc, L);
+    // pass 1: the window's column set
     auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - cw0); };
-    auto a1 = [&](int32_t c, bool ok) { wave_or_bits(s_bits, c, ok && (uint32_t)c < cmax); };
-    slab_window<BS, V, true>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f1, a1);
-    nx.sources(a_col, a_val);
+    auto a1 = [&](int32_t c) {
+      if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
+    };
+    slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f1, a1);
+    __syncthreads();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
     int32_t run = 0;
     for (int it = 0; it < wpw; it += kWave) {
@@ -523,14 +486,14 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     auto f2 = [&](int ow, int64_t idx) {
       return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
     };
-    auto a2 = [&](const ColVal<Acc>& p, bool ok) {
-      if (!ok || (uint32_t)p.c >= cmax) return;
+    auto a2 = [&](const ColVal<Acc>& p) {
+      if ((uint32_t)p.c >= cmax) return;
       const int w = p.c >> 5;
       const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
       if (r < m) Sr::lds_acc(&s_val[r], p.v);
     };
-    slab_window<BS, V, true>(b, a_col, a_val, tk, ts0, ts0, ts1, true, one, L, f2, a2);
-    nx.segments(b);
+    slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f2, a2);
+    __syncthreads();
     // column-ordered write-out; clears the bitmap for the next task
     for (int it = 0; it < wpw; it += kWave) {
       const int w = wv * wpw + it + lane_id();
@@ -547,85 +510,69 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       }
       s_bits[w] = 0u;
     }
-    __syncthreads();
-  }
+  });
 }
 
-// Heavy tasks: the task's sources are read once; the slab is swept in
-// windows of WD column tiles, each folded in a single pass into a dense LDS
-// accumulator with an occupancy bitmap, then compacted in column order
-// (touched slots are reset to the identity as they are written out).  Tasks
-// vary widely in size, so workgroups take them from the interleaved queues.
-template <class Sr, class V, int BS, int WD>
-__global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
-                                                       const int32_t* off2, OutC C, const SlabTask* tasks,
-                                                       const int32_t* boff, int32_t S, int32_t nd, int32_t* ctr,
-                                                       int32_t* err) {
+// Dense-tile tasks (one 16384-column tile holding many entries): one pass
+// into a dense LDS accumulator with an occupancy bitmap, then compaction in
+// column order (touched slots are reset to the identity as they are
+// written out).
+template <class Sr, class V, int BS>
+__global__ __launch_bounds__(BS) void k_num_slab_tile(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
+                                                      const SlabTask* tasks, const int32_t* boff, int32_t nd,
+                                                      int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
-  constexpr int kW = WD * kTile;
-  constexpr int kWW = WD * kTileWords;
+  static_assert(kTileWords % BS == 0 || BS % kTileWords == 0, "compaction rounds");
   using Acc = typename Sr::Acc;
-  __shared__ Acc s_acc[kW];
-  __shared__ uint32_t s_bm[kWW];
-  __shared__ SlabLds<V, BS> L;
+  __shared__ Acc s_acc[kTile];
+  __shared__ uint32_t s_bm[kTileWords];
+  __shared__ SrcLds<V, BS> L;
   __shared__ int32_t s_wave32[NW];
   const int T = b.T, G = b.G;
-  for (int x = threadIdx.x; x < kW; x += BS) s_acc[x] = Sr::ident();
-  for (int x = threadIdx.x; x < kWW; x += BS) s_bm[x] = 0u;
-  const bool bcache = S < kBoffCache;
+  for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
+  for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
+  const bool bcache = T < kBoffCache;
   if (bcache)
-    for (int x = threadIdx.x; x <= S; x += BS) L.boff[x] = boff[x];
+    for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
   __syncthreads();
   for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, [&](int64_t g) {
-    const SlabTask tk = slab_task<V, BS>(tasks, boff, L, bcache, S, nd, g);
+    const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
     const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
-    if ((int)threadIdx.x <= ts1 - ts0) {
-      const int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
-      L.tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
-    }
-    const bool one = tk.nsrc <= BS;
-    if (one) slab_load_sources<V, true, BS>(b, a_col, a_val, tk, 0, tk.nsrc, L);
+    const bool whole = tk.t0 == ts0 && tk.t1 == ts1;
+    const int64_t cw0 = (int64_t)tk.t0 << kTileLog;
+    auto f = [&](int ow, int64_t idx) {
+      return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+    };
+    auto ap = [&](const ColVal<Acc>& p) {
+      if ((uint32_t)p.c >= (uint32_t)kTile) return;
+      Sr::lds_acc(&s_acc[p.c], p.v);
+      atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
+    };
+    slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tk.t0 - ts0, tk.t1 - ts0, whole, false, 0, L,
+                               f, ap);
     __syncthreads();
-    for (int t0 = ts0; t0 < ts1; t0 += WD) {
-      const int t1 = t0 + WD < ts1 ? t0 + WD : ts1;
-      const int32_t rel0 = L.tc[t0 - ts0], mw = L.tc[t1 - ts0] - rel0;
-      if (mw <= 0) continue;
-      const int64_t cw0 = (int64_t)t0 << kTileLog;
-      const int nwords = (t1 - t0) * kTileWords;
-      auto f = [&](int ow, int64_t idx) {
-        return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
-      };
-      auto ap = [&](const ColVal<Acc>& p, bool ok) {
-        const bool in = ok && (uint32_t)p.c < (uint32_t)kW;
-        if (in) Sr::lds_acc(&s_acc[p.c], p.v);
-        wave_or_bits(s_bm, p.c, in);
-      };
-      slab_window<BS, V, true>(b, a_col, a_val, tk, ts0, t0, t1, t0 == ts0 && t1 == ts1, one, L, f, ap);
-      // compaction: round w0 takes words [w0, w0 + BS), consecutive threads
-      // on consecutive words
-      int32_t carry = 0;
-      for (int w0 = 0; w0 < nwords; w0 += BS) {
-        const int w = w0 + threadIdx.x;
-        uint32_t bits = w < nwords ? s_bm[w] : 0u;
-        int32_t tot;
-        int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
-        while (bits) {
-          const int bt = __ffs((int)bits) - 1;
-          bits &= bits - 1u;
-          const int c = w * 32 + bt;
-          if (r < mw) {
-            C.col[tk.out + rel0 + r] = (int32_t)(cw0 + c);
-            ((V*)C.val)[tk.out + rel0 + r] = Sr::out(s_acc[c]);
-          }
-          s_acc[c] = Sr::ident();
-          ++r;
+    // compaction: consecutive threads on consecutive words
+    int32_t carry = 0;
+    for (int w0 = 0; w0 < kTileWords; w0 += BS) {
+      const int w = w0 + threadIdx.x;
+      uint32_t bits = w < kTileWords ? s_bm[w] : 0u;
+      int32_t tot;
+      int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
+      while (bits) {
+        const int bt = __ffs((int)bits) - 1;
+        bits &= bits - 1u;
+        const int c = w * 32 + bt;
+        if (r < tk.m) {
+          C.col[tk.out + r] = (int32_t)(cw0 + c);
+          ((V*)C.val)[tk.out + r] = Sr::out(s_acc[c]);
         }
-        if (w < nwords) s_bm[w] = 0u;
-        carry += tot;
+        s_acc[c] = Sr::ident();
+        ++r;
       }
-      if (threadIdx.x == 0 && carry != mw) atomicOr(err, 1);
-      __syncthreads();
+      if (w < kTileWords) s_bm[w] = 0u;
+      carry += tot;
     }
+    if (threadIdx.x == 0 && carry != tk.m) atomicOr(err, 1);
   });
 }
 
