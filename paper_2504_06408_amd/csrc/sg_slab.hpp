@@ -304,47 +304,55 @@ SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_va
   return total;
 }
 
-// Flattened walk over the chunk's `total` products: wavefront w takes blocks
-// of 64*kUnroll consecutive products, lane l products q = qb + u*64 + l, so
-// every load instruction is coalesced; owners are found by a search narrowed
-// to the block's first and last owner.  fetch(owner, index into pcol/pval)
-// returns a product, apply(product) folds it into LDS.
+// One block of 64*kUnroll consecutive products [qb, qb + 64*kUnroll) of a
+// chunk: lane l takes q = qb + u*64 + l (u < kUnroll), so every load
+// instruction is coalesced; owners are found by a search narrowed to the
+// block's first and last owner.  fetch(owner, index into pcol/pval) returns
+// a product; ok[u] tells which pp[u] hold one.
+template <int BS, class V, class Fetch, class P>
+SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, Fetch& fetch, P* pp, bool* ok) {
+  constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
+  const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
+  int a = 0, bb = nc - 1;
+  while (a < bb) {
+    const int mid = (a + bb + 1) >> 1;
+    if (L.off[mid] <= qb) a = mid;
+    else bb = mid - 1;
+  }
+  int e = a, f = nc - 1;
+  while (e < f) {
+    const int mid = (e + f + 1) >> 1;
+    if (L.off[mid] <= qe) e = mid;
+    else f = mid - 1;
+  }
+  int ow = a;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int64_t q = qb + u * kWave + lane_id();
+    ok[u] = q < total;
+    if (ok[u]) {
+      int h2 = e;
+      while (ow < h2) {
+        const int mid = (ow + h2 + 1) >> 1;
+        if (L.off[mid] <= q) ow = mid;
+        else h2 = mid - 1;
+      }
+      pp[u] = fetch(ow, L.st[ow] + (q - L.off[ow]));
+    }
+  }
+}
+
+// Flattened walk over the chunk's `total` products: wavefront w takes the
+// blocks w, w + NW, ... and folds each product with apply(product).
 template <int BS, class V, class Fetch, class Apply>
 SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
   constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
   using P = decltype(fetch(0, (int64_t)0));
   for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
-    const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
-    int a = 0, bb = nc - 1;
-    while (a < bb) {
-      const int mid = (a + bb + 1) >> 1;
-      if (L.off[mid] <= qb) a = mid;
-      else bb = mid - 1;
-    }
-    int e = a, f = nc - 1;
-    while (e < f) {
-      const int mid = (e + f + 1) >> 1;
-      if (L.off[mid] <= qe) e = mid;
-      else f = mid - 1;
-    }
     P pp[kUnroll];
     bool ok[kUnroll];
-    int ow = a;
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t q = qb + u * kWave + lane_id();
-      ok[u] = q < total;
-      if (ok[u]) {
-        int h2 = e;
-        while (ow < h2) {
-          const int mid = (ow + h2 + 1) >> 1;
-          if (L.off[mid] <= q) ow = mid;
-          else h2 = mid - 1;
-        }
-        pp[u] = fetch(ow, L.st[ow] + (q - L.off[ow]));
-      }
-    }
+    slab_round<BS, V>(L, nc, total, qb, fetch, pp, ok);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       if (ok[u]) apply(pp[u]);
@@ -449,12 +457,33 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     int64_t total = 0;
     __syncthreads();
     if (one) total = slab_chunk<V, true, BS>(b, a_col, a_val, tk.a0, tk.s, tr0, tr1, whole, 0, tk.nsrc, L);
-    // pass 1: the window's column set
+    // With one round of products per wavefront the products stay in
+    // registers for pass 2; otherwise pass 2 gathers them again.
+    const bool held = one && total <= (int64_t)NW * kWave * kUnroll;
     auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - cw0); };
     auto a1 = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
     };
-    slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f1, a1);
+    auto f2 = [&](int ow, int64_t idx) {
+      return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+    };
+    auto a2 = [&](const ColVal<Acc>& p) {
+      if ((uint32_t)p.c >= cmax) return;
+      const int w = p.c >> 5;
+      const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
+      if (r < m) Sr::lds_acc(&s_val[r], p.v);
+    };
+    ColVal<Acc> pp[kUnroll];
+    bool ok[kUnroll];
+    // pass 1: the window's column set
+    if (held) {
+      slab_round<BS, V>(L, tk.nsrc, total, (int64_t)wv * kWave * kUnroll, f2, pp, ok);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ok[u]) a1(pp[u].c);
+    } else {
+      slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f1, a1);
+    }
     __syncthreads();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
     int32_t run = 0;
@@ -483,33 +512,31 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       }
     __syncthreads();
     // pass 2: fold every product into its compacted slot
-    auto f2 = [&](int ow, int64_t idx) {
-      return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
-    };
-    auto a2 = [&](const ColVal<Acc>& p) {
-      if ((uint32_t)p.c >= cmax) return;
-      const int w = p.c >> 5;
-      const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
-      if (r < m) Sr::lds_acc(&s_val[r], p.v);
-    };
-    slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f2, a2);
+    if (held) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ok[u]) a2(pp[u]);
+    } else {
+      slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f2, a2);
+    }
     __syncthreads();
-    // column-ordered write-out; clears the bitmap for the next task
+    // write-out: column ids from the bitmap walk (no LDS reads inside the
+    // loop), values in rank order (coalesced); the bitmap is cleared for the
+    // next task
     for (int it = 0; it < wpw; it += kWave) {
       const int w = wv * wpw + it + lane_id();
       uint32_t bits = s_bits[w];
       int32_t r = s_rank[w];
+      const int64_t cbase = cw0 + w * 32;
       while (bits) {
         const int bt = __ffs((int)bits) - 1;
         bits &= bits - 1u;
-        if (r < m) {
-          C.col[tk.out + r] = (int32_t)(cw0 + w * 32 + bt);
-          ((V*)C.val)[tk.out + r] = Sr::out(s_val[r]);
-        }
+        if (r < m) C.col[tk.out + r] = (int32_t)(cbase + bt);
         ++r;
       }
       s_bits[w] = 0u;
     }
+    for (int x = threadIdx.x; x < m; x += BS) ((V*)C.val)[tk.out + x] = Sr::out(s_val[x]);
   });
 }
 
