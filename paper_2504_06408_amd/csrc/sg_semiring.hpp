@@ -20,6 +20,7 @@ struct SrI64 {
   using V = int64_t;
   using Acc = unsigned long long;
   static constexpr int kId = 1;
+  static constexpr bool kValueMarks = false;
   SG_DEV static Acc ident() { return 0ull; }
   SG_DEV static Acc mul(V a, V b) { return (Acc)a * (Acc)b; }
   SG_DEV static Acc lift(V a) { return (Acc)a; }
@@ -33,6 +34,7 @@ struct SrF32 {
   using V = float;
   using Acc = float;
   static constexpr int kId = 2;
+  static constexpr bool kValueMarks = false;
   SG_DEV static Acc ident() { return 0.0f; }
   SG_DEV static Acc mul(V a, V b) { return a * b; }
   SG_DEV static Acc lift(V a) { return a; }
@@ -51,6 +53,7 @@ struct SrF32Comp {
   using V = float;
   using Acc = unsigned long long;  // low word: hi, high word: lo
   static constexpr int kId = 2;
+  static constexpr bool kValueMarks = false;
   SG_DEV static Acc pack(float hi, float lo) {
     return (Acc)__float_as_uint(hi) | ((Acc)__float_as_uint(lo) << 32);
   }
@@ -90,6 +93,7 @@ struct SrF64 {
   using V = double;
   using Acc = double;
   static constexpr int kId = 3;
+  static constexpr bool kValueMarks = false;
   SG_DEV static Acc ident() { return 0.0; }
   SG_DEV static Acc mul(V a, V b) { return a * b; }
   SG_DEV static Acc lift(V a) { return a; }
@@ -104,6 +108,7 @@ struct SrBool {
   using V = uint8_t;
   using Acc = uint8_t;
   static constexpr int kId = 4;
+  static constexpr bool kValueMarks = false;
   SG_DEV static Acc ident() { return 0; }
   SG_DEV static Acc mul(V a, V b) { return (a != 0 && b != 0) ? 1 : 0; }
   SG_DEV static Acc lift(V a) { return a != 0 ? 1 : 0; }
@@ -117,11 +122,14 @@ struct SrBool {
 // (min, +) over binary32.  Accumulators hold an order-preserving unsigned
 // image of the float (negative values bit-inverted, non-negative ones with
 // the sign bit set), so the minimum is a single integer atomic min.  The
-// identity 0xFFFFFFFF lies above the image of +inf.
+// identity 0xFFFFFFFF lies above the image of +inf.  No product maps to the
+// identity, so a slot that still holds it was never reached (kValueMarks):
+// dense accumulators need no separate occupancy bitmap.
 struct SrMinPlus {
   using V = float;
   using Acc = uint32_t;
   static constexpr int kId = 5;
+  static constexpr bool kValueMarks = true;
   SG_DEV static uint32_t key(float f) {
     const uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);

@@ -304,14 +304,14 @@ SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_va
   return total;
 }
 
-// One block of 64*kUnroll consecutive products [qb, qb + 64*kUnroll) of a
-// chunk: lane l takes q = qb + u*64 + l (u < kUnroll), so every load
+// One block of 64*U consecutive products [qb, qb + 64*U) of a chunk: lane
+// l takes q = qb + u*64 + l (u < U), so every load
 // instruction is coalesced; owners are found by a search narrowed to the
 // block's first and last owner.  fetch(owner, index into pcol/pval) returns
 // a product; ok[u] tells which pp[u] hold one.
-template <int BS, class V, class Fetch, class P>
+template <int BS, int U, class V, class Fetch, class P>
 SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, Fetch& fetch, P* pp, bool* ok) {
-  constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
+  constexpr int64_t kBlock = (int64_t)kWave * U;
   const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
   int a = 0, bb = nc - 1;
   while (a < bb) {
@@ -327,7 +327,7 @@ SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb
   }
   int ow = a;
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int64_t q = qb + u * kWave + lane_id();
     ok[u] = q < total;
     if (ok[u]) {
@@ -344,38 +344,42 @@ SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb
 
 // Flattened walk over the chunk's `total` products: wavefront w takes the
 // blocks w, w + NW, ... and folds each product with apply(product).
-template <int BS, class V, class Fetch, class Apply>
+template <int BS, int U, class V, class Fetch, class Apply>
 SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
-  constexpr int64_t kBlock = (int64_t)kWave * kUnroll;
+  constexpr int64_t kBlock = (int64_t)kWave * U;
   using P = decltype(fetch(0, (int64_t)0));
   for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
-    P pp[kUnroll];
-    bool ok[kUnroll];
-    slab_round<BS, V>(L, nc, total, qb, fetch, pp, ok);
+    P pp[U];
+    bool ok[U];
+    slab_round<BS, U, V>(L, nc, total, qb, fetch, pp, ok);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < U; ++u)
       if (ok[u]) apply(pp[u]);
   }
 }
 
 // All products of a window of task (a0, nsrc, s, tr0, tr1): chunk by chunk
 // unless the caller already loaded the single chunk (`loaded`, total).
-template <int BS, class V, bool kVals, class Fetch, class Apply>
+template <int BS, int U, class V, bool kVals, class Fetch, class Apply>
 SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
                           int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int64_t total,
                           SrcLds<V, BS>& L, Fetch& fetch, Apply& apply) {
   if (loaded) {
-    slab_iterate<BS, V>(L, nsrc, total, fetch, apply);
+    slab_iterate<BS, U, V>(L, nsrc, total, fetch, apply);
     return;
   }
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
     const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
     __syncthreads();
     const int64_t tc = slab_chunk<V, kVals, BS>(b, a_col, a_val, a0, s, tr0, tr1, whole, c0, nc, L);
-    slab_iterate<BS, V>(L, nc, tc, fetch, apply);
+    slab_iterate<BS, U, V>(L, nc, tc, fetch, apply);
   }
 }
+
+// Products per lane per gather round in the slab kernels (one round covers
+// 64*kSlabU products per wavefront).
+constexpr int kSlabU = 8;
 
 // ---- symbolic --------------------------------------------------------------------
 // Task g = (slab s = g / nd, dense row h = g % nd), slab-major, from the
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRo
     auto apply = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bm[c >> 5], 1u << (c & 31));
     };
-    slab_products<BS, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, L, fetch, apply);
+    slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, L, fetch, apply);
     __syncthreads();
     int32_t* o2 = off2 + h * (T + 1);
     for (int tl = wave_id(); tl < G; tl += NW) {
@@ -459,7 +463,7 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     if (one) total = slab_chunk<V, true, BS>(b, a_col, a_val, tk.a0, tk.s, tr0, tr1, whole, 0, tk.nsrc, L);
     // With one round of products per wavefront the products stay in
     // registers for pass 2; otherwise pass 2 gathers them again.
-    const bool held = one && total <= (int64_t)NW * kWave * kUnroll;
+    const bool held = one && total <= (int64_t)NW * kWave * kSlabU;
     auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - cw0); };
     auto a1 = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
@@ -473,16 +477,16 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
       if (r < m) Sr::lds_acc(&s_val[r], p.v);
     };
-    ColVal<Acc> pp[kUnroll];
-    bool ok[kUnroll];
+    ColVal<Acc> pp[kSlabU];
+    bool ok[kSlabU];
     // pass 1: the window's column set
     if (held) {
-      slab_round<BS, V>(L, tk.nsrc, total, (int64_t)wv * kWave * kUnroll, f2, pp, ok);
+      slab_round<BS, kSlabU, V>(L, tk.nsrc, total, (int64_t)wv * kWave * kSlabU, f2, pp, ok);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < kSlabU; ++u)
         if (ok[u]) a1(pp[u].c);
     } else {
-      slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f1, a1);
+      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f1, a1);
     }
     __syncthreads();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
@@ -514,10 +518,10 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     // pass 2: fold every product into its compacted slot
     if (held) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < kSlabU; ++u)
         if (ok[u]) a2(pp[u]);
     } else {
-      slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f2, a2);
+      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f2, a2);
     }
     __syncthreads();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
@@ -573,30 +577,54 @@ __global__ __launch_bounds__(BS) void k_num_slab_tile(SlabB<V> b, const int32_t*
     auto ap = [&](const ColVal<Acc>& p) {
       if ((uint32_t)p.c >= (uint32_t)kTile) return;
       Sr::lds_acc(&s_acc[p.c], p.v);
-      atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
+      if constexpr (!Sr::kValueMarks) atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
     };
-    slab_products<BS, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tk.t0 - ts0, tk.t1 - ts0, whole, false, 0, L,
+    slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tk.t0 - ts0, tk.t1 - ts0, whole, false, 0, L,
                                f, ap);
     __syncthreads();
-    // compaction: consecutive threads on consecutive words
+    // compaction: consecutive threads on consecutive words; up to four
+    // accumulators are read per wait
     int32_t carry = 0;
     for (int w0 = 0; w0 < kTileWords; w0 += BS) {
       const int w = w0 + threadIdx.x;
-      uint32_t bits = w < kTileWords ? s_bm[w] : 0u;
+      uint32_t bits = 0u;
+      if (w < kTileWords) {
+        if constexpr (Sr::kValueMarks) {
+          // a slot still at the identity was never reached
+#pragma unroll
+          for (int j = 0; j < 32; ++j) bits |= (s_acc[w * 32 + j] != Sr::ident() ? 1u : 0u) << j;
+        } else {
+          bits = s_bm[w];
+        }
+      }
       int32_t tot;
       int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
       while (bits) {
-        const int bt = __ffs((int)bits) - 1;
-        bits &= bits - 1u;
-        const int c = w * 32 + bt;
-        if (r < tk.m) {
-          C.col[tk.out + r] = (int32_t)(cw0 + c);
-          ((V*)C.val)[tk.out + r] = Sr::out(s_acc[c]);
-        }
-        s_acc[c] = Sr::ident();
-        ++r;
+        int c[4];
+        Acc v[4];
+        int n = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (bits) {
+            const int bt = __ffs((int)bits) - 1;
+            bits &= bits - 1u;
+            c[j] = w * 32 + bt;
+            v[j] = s_acc[c[j]];
+            n = j + 1;
+          }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < n) {
+            if (r < tk.m) {
+              C.col[tk.out + r] = (int32_t)(cw0 + c[j]);
+              ((V*)C.val)[tk.out + r] = Sr::out(v[j]);
+            }
+            s_acc[c[j]] = Sr::ident();
+            ++r;
+          }
       }
-      if (w < kTileWords) s_bm[w] = 0u;
+      if constexpr (!Sr::kValueMarks)
+        if (w < kTileWords) s_bm[w] = 0u;
       carry += tot;
     }
     if (threadIdx.x == 0 && carry != tk.m) atomicOr(err, 1);
