@@ -363,7 +363,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.task_ctr = h->d_flags + kCtrBase;
   c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;
   if (slab) {
-    const size_t tb = 2 * sizeof(SlabTask) * (size_t)nd * (size_t)r.T;  // light-window and dense-tile lists
+    const size_t tb = 2 * sizeof(SlabTask) * (size_t)nd * (size_t)r.S;  // light and heavy lists
     SG_HIP(h, h->task_buf.ensure(tb + sizeof(int32_t) * (6 * (size_t)r.T + 3)));
     c.slab_tasks = (SlabTask*)h->task_buf.p;
     c.slab_book = (int32_t*)((char*)h->task_buf.p + tb);

@@ -199,14 +199,14 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
       const int32_t nd = c.plan.ndense();
       int32_t* sbook = c.slab_book;
       SlabTask* light = c.slab_tasks;
-      SlabTask* dense = c.slab_tasks + (int64_t)nd * T;
+      SlabTask* heavy = c.slab_tasks + (int64_t)nd * c.src.S;
       hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, c.task_ctr,
                          (int64_t)kCtrInts, (int32_t)0);
       hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)T, 256, 1024)), dim3(256), 0, st, sbook,
                          3 * (int64_t)T, (int32_t)0);
       hipLaunchKernelGGL(k_slab_tasks<256>, dim3(grid_for(nd, 256, c.cus * 8)), dim3(256), 0, st, c.plan.bins,
-                         c.src.drow, c.off2, T, G, (int32_t)kSlabCap, c.tile_min, (const int64_t*)c.C.rowptr, light,
-                         dense, sbook, c.task_ctr);
+                         c.src.drow, c.off2, T, G, c.src.S, (int32_t)kSlabCap, (const int64_t*)c.C.rowptr, light,
+                         heavy, sbook, c.task_ctr);
       hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, sbook, T, c.task_ctr);
       SlabB<V> b{c.src.prow, c.src.pcol, (const V*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
       {
@@ -220,12 +220,12 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
         c.marks.mark(kPhNumDenseSlab, 0);
       }
       {
-        auto k = k_num_slab_tile<Sr, V, 512>;
+        auto k = k_num_slab_heavy<Sr, V, 512>;
         static int occ = occupancy(k, 512);
         const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
         c.marks.mark(kPhNumDenseTiles, 1);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.C,
-                           (const SlabTask*)dense, (const int32_t*)book_off(sbook, T, kListTile), nd, c.task_ctr,
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.off2, c.C,
+                           (const SlabTask*)heavy, (const int32_t*)book_off(sbook, T, kListTile), nd, c.task_ctr,
                            c.err);
         c.marks.mark(kPhNumDenseTiles, 0);
       }

@@ -154,15 +154,15 @@ __global__ __launch_bounds__(BS) void k_off2_finish(Bins bins, const DenseRow* d
 }
 
 // ---- tasks ------------------------------------------------------------------------
-// A numeric task is a window of whole column tiles [t0, t1) of one dense row
-// inside one slab, with everything its kernel needs up front.
+// A numeric task is one (dense row, slab) with everything its kernel needs
+// up front.  (t0, t1: the slab's column tiles.)
 struct SlabTask {
   int32_t h, s;    // position in the dense list, slab
-  int32_t t0, t1;  // window tiles
-  int64_t out;     // C position of the window's first entry
+  int32_t t0, t1;  // tiles of the slab
+  int64_t out;     // C position of the slab's first entry
   int64_t a0;      // first A entry of the row
   int32_t nsrc;    // A entries of the row
-  int32_t m;       // C entries in the window
+  int32_t m;       // C entries in the slab
 };
 
 // Entries of a light task's LDS value array (32 KB of accumulators).
@@ -171,70 +171,73 @@ constexpr int slab_cap() {
   return 32768 / (int)sizeof(typename Sr::Acc);
 }
 
-// One thread per dense row.  A slab with at most `cap` entries is one light
-// window.  In a fuller slab, every tile with at least `tile_min` entries (or
-// more than `cap`) is a dense-tile task, and runs of the other tiles are
-// light windows of at most `cap` entries.  Both lists hold per-tile buckets
-// of nd slots (a window goes to the bucket of its first tile; book[l*T + t]
-// counts bucket t of list l), so walking them in order is slab-major.
-// Entries per list are summed for the statistics.
+constexpr int kTaskSlabsLds = 512;  // slabs whose bucket counters a block keeps in LDS
+
+// One thread per dense row: every non-empty slab of the row becomes a light
+// task (at most `cap` entries: bitmap + rank in LDS) or a heavy one (a dense
+// LDS accumulator per tile).  Both lists hold per-slab buckets of nd slots
+// (book[l*T + s] counts bucket s of list l), so walking them in order is
+// slab-major.  A block counts its tasks per (list, slab) in LDS, reserves
+// each range with one global atomic, then writes the tasks.  Entries per
+// list are summed for the statistics.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr, const int32_t* off2, int32_t T,
-                                                   int32_t G, int32_t cap, int32_t tile_min,
-                                                   const int64_t* c_rowptr, SlabTask* light, SlabTask* dense,
-                                                   int32_t* book, int32_t* ctr) {
+                                                   int32_t G, int32_t S, int32_t cap, const int64_t* c_rowptr,
+                                                   SlabTask* light, SlabTask* heavy, int32_t* book, int32_t* ctr) {
+  __shared__ int32_t s_cnt[2][kTaskSlabsLds];
+  __shared__ int32_t s_base[2][kTaskSlabsLds];
   __shared__ unsigned long long s_ent[2];
+  const bool lds = S <= kTaskSlabsLds;
   if (threadIdx.x < 2) s_ent[threadIdx.x] = 0ull;
   __syncthreads();
   const int64_t nd = dense_rows(bins);
-  int32_t* cnt_l = book + kListSlab * T;
-  int32_t* cnt_d = book + kListTile * T;
-  unsigned long long el = 0ull, ed = 0ull;
-  for (int64_t h = (int64_t)blockIdx.x * BS + threadIdx.x; h < nd; h += (int64_t)gridDim.x * BS) {
-    const DenseRow d = dr[h];
-    const int32_t* o2 = off2 + h * (T + 1);
-    const int64_t base = c_rowptr[d.i];
-    auto put_light = [&](int32_t s, int32_t t0, int32_t t1) {
-      const int32_t m = o2[t1] - o2[t0];
-      if (m <= 0) return;
-      light[(int64_t)t0 * nd + atomicAdd(&cnt_l[t0], 1)] =
-          SlabTask{(int32_t)h, s, t0, t1, base + o2[t0], d.a0, d.nsrc, m};
-      el += (unsigned long long)m;
-    };
-    int32_t s = 0;
-    for (int32_t ta = 0; ta < T; ta += G, ++s) {
-      const int32_t tb = ta + G < T ? ta + G : T;
-      const int32_t ms = o2[tb] - o2[ta];
-      if (ms <= 0) continue;
-      if (ms <= cap) {
-        put_light(s, ta, tb);
-        continue;
-      }
-      int32_t w0 = ta;  // pending light window [w0, t)
-      for (int32_t t = ta; t < tb; ++t) {
-        const int32_t c = o2[t + 1] - o2[t];
-        if (c >= tile_min || c > cap) {
-          put_light(s, w0, t);
-          dense[(int64_t)t * nd + atomicAdd(&cnt_d[t], 1)] =
-              SlabTask{(int32_t)h, s, t, t + 1, base + o2[t], d.a0, d.nsrc, c};
-          ed += (unsigned long long)c;
-          w0 = t + 1;
-        } else if (o2[t + 1] - o2[w0] > cap) {
-          put_light(s, w0, t);
-          w0 = t;
+  int32_t* cnt_g[2] = {book + kListSlab * T, book + kListTile * T};
+  unsigned long long ent[2] = {0ull, 0ull};
+  for (int64_t h0 = (int64_t)blockIdx.x * BS; h0 < nd; h0 += (int64_t)gridDim.x * BS) {
+    const int64_t h = h0 + threadIdx.x;
+    const bool mine = h < nd;
+    const int32_t* o2 = off2 + (mine ? h : 0) * (T + 1);
+    if (lds) {
+      for (int x = threadIdx.x; x < 2 * S; x += BS) s_cnt[x / S][x % S] = 0;
+      __syncthreads();
+      if (mine)
+        for (int32_t sl = 0, ta = 0; ta < T; ta += G, ++sl) {
+          const int32_t tb = ta + G < T ? ta + G : T;
+          const int32_t m = o2[tb] - o2[ta];
+          if (m > 0) atomicAdd(&s_cnt[m <= cap ? 0 : 1][sl], 1);
         }
+      __syncthreads();
+      for (int x = threadIdx.x; x < 2 * S; x += BS) {
+        const int l = x / S, sl = x % S;
+        const int32_t c = s_cnt[l][sl];
+        s_base[l][sl] = c ? atomicAdd(&cnt_g[l][sl], c) : 0;
+        s_cnt[l][sl] = 0;
       }
-      put_light(s, w0, tb);
+      __syncthreads();
     }
+    if (mine) {
+      const DenseRow d = dr[h];
+      const int64_t base = c_rowptr[d.i];
+      for (int32_t sl = 0, ta = 0; ta < T; ta += G, ++sl) {
+        const int32_t tb = ta + G < T ? ta + G : T;
+        const int32_t lo = o2[ta], m = o2[tb] - lo;
+        if (m <= 0) continue;
+        const int l = m <= cap ? 0 : 1;
+        const int32_t slot = lds ? s_base[l][sl] + atomicAdd(&s_cnt[l][sl], 1) : atomicAdd(&cnt_g[l][sl], 1);
+        (l == 0 ? light : heavy)[(int64_t)sl * nd + slot] = SlabTask{(int32_t)h, sl, ta, tb, base + lo, d.a0, d.nsrc, m};
+        ent[l] += (unsigned long long)m;
+      }
+    }
+    if (lds) __syncthreads();
   }
-  el = wave_sum(el);
-  ed = wave_sum(ed);
-  if (lane_id() == 0 && el) atomicAdd(&s_ent[0], el);
-  if (lane_id() == 0 && ed) atomicAdd(&s_ent[1], ed);
+  for (int l = 0; l < 2; ++l) {
+    const unsigned long long v = wave_sum(ent[l]);
+    if (lane_id() == 0 && v) atomicAdd(&s_ent[l], v);
+  }
   __syncthreads();
-  unsigned long long* ent = (unsigned long long*)(ctr + kCtrEntries);
-  if (threadIdx.x == 0 && s_ent[0]) atomicAdd(ent + kListSlab, s_ent[0]);
-  if (threadIdx.x == 1 && s_ent[1]) atomicAdd(ent + kListTile, s_ent[1]);
+  unsigned long long* eg = (unsigned long long*)(ctr + kCtrEntries);
+  if (threadIdx.x == 0 && s_ent[0]) atomicAdd(eg + kListSlab, s_ent[0]);
+  if (threadIdx.x == 1 && s_ent[1]) atomicAdd(eg + kListTile, s_ent[1]);
 }
 
 template <class V>
@@ -544,90 +547,131 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
   });
 }
 
-// Dense-tile tasks (one 16384-column tile holding many entries): one pass
-// into a dense LDS accumulator with an occupancy bitmap, then compaction in
-// column order (touched slots are reset to the identity as they are
-// written out).
+// Heavy tasks (a slab holding more entries than a light task's value
+// array): the row's sources are loaded once (A value, column, slab segment
+// start), then each non-empty tile of the slab is folded in one pass into a
+// dense 16384-slot LDS accumulator and compacted in column order; per tile a
+// source only re-reads its two tile offsets.  Touched slots are reset to the
+// identity as they are written out; for semirings whose identity no product
+// reaches (kValueMarks) occupancy is read off the accumulator, otherwise an
+// occupancy bitmap is kept.
 template <class Sr, class V, int BS>
-__global__ __launch_bounds__(BS) void k_num_slab_tile(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
-                                                      const SlabTask* tasks, const int32_t* boff, int32_t nd,
-                                                      int32_t* ctr, int32_t* err) {
+__global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
+                                                       const int32_t* off2, OutC C, const SlabTask* tasks,
+                                                       const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
-  static_assert(kTileWords % BS == 0 || BS % kTileWords == 0, "compaction rounds");
   using Acc = typename Sr::Acc;
   __shared__ Acc s_acc[kTile];
-  __shared__ uint32_t s_bm[kTileWords];
+  __shared__ uint32_t s_bm[Sr::kValueMarks ? 1 : kTileWords];
   __shared__ SrcLds<V, BS> L;
   __shared__ int32_t s_wave32[NW];
+  __shared__ int32_t s_tc[kSlabTilesMax + 1];
   const int T = b.T, G = b.G;
   for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
-  for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
+  if constexpr (!Sr::kValueMarks)
+    for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
   const bool bcache = T < kBoffCache;
   if (bcache)
     for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
   __syncthreads();
   for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, [&](int64_t g) {
     const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
-    const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
-    const bool whole = tk.t0 == ts0 && tk.t1 == ts1;
-    const int64_t cw0 = (int64_t)tk.t0 << kTileLog;
-    auto f = [&](int ow, int64_t idx) {
-      return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
-    };
-    auto ap = [&](const ColVal<Acc>& p) {
-      if ((uint32_t)p.c >= (uint32_t)kTile) return;
-      Sr::lds_acc(&s_acc[p.c], p.v);
-      if constexpr (!Sr::kValueMarks) atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
-    };
-    slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tk.t0 - ts0, tk.t1 - ts0, whole, false, 0, L,
-                               f, ap);
+    const int ts0 = tk.t0, ts1 = tk.t1;
     __syncthreads();
-    // compaction: consecutive threads on consecutive words; up to four
-    // accumulators are read per wait
-    int32_t carry = 0;
-    for (int w0 = 0; w0 < kTileWords; w0 += BS) {
-      const int w = w0 + threadIdx.x;
-      uint32_t bits = 0u;
-      if (w < kTileWords) {
-        if constexpr (Sr::kValueMarks) {
-          // a slot still at the identity was never reached
-#pragma unroll
-          for (int j = 0; j < 32; ++j) bits |= (s_acc[w * 32 + j] != Sr::ident() ? 1u : 0u) << j;
-        } else {
-          bits = s_bm[w];
-        }
-      }
-      int32_t tot;
-      int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
-      while (bits) {
-        int c[4];
-        Acc v[4];
-        int n = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (bits) {
-            const int bt = __ffs((int)bits) - 1;
-            bits &= bits - 1u;
-            c[j] = w * 32 + bt;
-            v[j] = s_acc[c[j]];
-            n = j + 1;
-          }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (j < n) {
-            if (r < tk.m) {
-              C.col[tk.out + r] = (int32_t)(cw0 + c[j]);
-              ((V*)C.val)[tk.out + r] = Sr::out(v[j]);
-            }
-            s_acc[c[j]] = Sr::ident();
-            ++r;
-          }
-      }
-      if constexpr (!Sr::kValueMarks)
-        if (w < kTileWords) s_bm[w] = 0u;
-      carry += tot;
+    if ((int)threadIdx.x <= ts1 - ts0) {
+      const int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
+      s_tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
     }
-    if (threadIdx.x == 0 && carry != tk.m) atomicOr(err, 1);
+    // the row's sources: one per thread when one chunk holds them all
+    const bool one = tk.nsrc <= BS;
+    int32_t k = 0;
+    int64_t sst = 0;
+    if (one && (int)threadIdx.x < tk.nsrc) {
+      const int64_t e = tk.a0 + threadIdx.x;
+      k = a_col[e];
+      L.a[threadIdx.x] = a_val[e];
+      sst = b.prow[(int64_t)tk.s * b.nb + k];
+    }
+    __syncthreads();
+    for (int t = ts0; t < ts1; ++t) {
+      const int32_t rel = s_tc[t - ts0], mt = s_tc[t + 1 - ts0] - rel;
+      if (mt <= 0) continue;
+      const int64_t cw0 = (int64_t)t << kTileLog;
+      auto f = [&](int ow, int64_t idx) {
+        return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+      };
+      auto ap = [&](const ColVal<Acc>& p) {
+        if ((uint32_t)p.c >= (uint32_t)kTile) return;
+        Sr::lds_acc(&s_acc[p.c], p.v);
+        if constexpr (!Sr::kValueMarks) atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
+      };
+      if (one) {
+        int64_t len = 0, st = 0;
+        if ((int)threadIdx.x < tk.nsrc) {
+          const int32_t* r = b.rpt + ((int64_t)tk.s * b.nb + k) * (G + 1) + (t - ts0);
+          const int32_t w0 = r[0];
+          st = sst + w0;
+          len = r[1] - w0;
+        }
+        int64_t total;
+        const int64_t off = block_excl_scan<NW, int64_t>(len, L.wave, &total);
+        L.st[threadIdx.x] = st;
+        L.off[threadIdx.x] = off;
+        __syncthreads();
+        slab_iterate<BS, kSlabU, V>(L, tk.nsrc, total, f, ap);
+      } else {
+        slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false, false,
+                                           0, L, f, ap);
+      }
+      __syncthreads();
+      // compaction: consecutive threads on consecutive words; up to four
+      // accumulators are read per wait
+      int32_t carry = 0;
+      for (int w0 = 0; w0 < kTileWords; w0 += BS) {
+        const int w = w0 + threadIdx.x;
+        uint32_t bits = 0u;
+        if (w < kTileWords) {
+          if constexpr (Sr::kValueMarks) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) bits |= (s_acc[w * 32 + j] != Sr::ident() ? 1u : 0u) << j;
+          } else {
+            bits = s_bm[w];
+          }
+        }
+        int32_t tot;
+        int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
+        const int64_t out = tk.out + rel;
+        while (bits) {
+          int c[4];
+          Acc v[4];
+          int n = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (bits) {
+              const int bt = __ffs((int)bits) - 1;
+              bits &= bits - 1u;
+              c[j] = w * 32 + bt;
+              v[j] = s_acc[c[j]];
+              n = j + 1;
+            }
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < n) {
+              if (r < mt) {
+                C.col[out + r] = (int32_t)(cw0 + c[j]);
+                ((V*)C.val)[out + r] = Sr::out(v[j]);
+              }
+              s_acc[c[j]] = Sr::ident();
+              ++r;
+            }
+        }
+        if constexpr (!Sr::kValueMarks)
+          if (w < kTileWords) s_bm[w] = 0u;
+        carry += tot;
+      }
+      if (threadIdx.x == 0 && carry != mt) atomicOr(err, 1);
+      __syncthreads();
+    }
   });
 }
 
