@@ -177,11 +177,12 @@ void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t
   const SlabB<uint8_t> b{r.prow, r.pcol, nullptr, r.rpt, r.b_nrows, G, r.T};
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, r.qctr, (int64_t)kCtrInts,
                      (int32_t)0);
-  auto k = k_sym_slab<512>;
-  static int occ = occupancy(k, 512);
+  constexpr int BS = 256;
+  auto k = k_sym_slab<BS>;
+  static int occ = occupancy(k, BS);
   const int grid = cus * occ > kQueues ? cus * occ : kQueues;
   marks.mark(kPhSymDenseBitmap, 1);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, r.drow, r.a_col, plan.bins, r.S, off2, r.qctr);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, b, r.drow, r.a_col, plan.bins, r.S, off2, r.qctr);
   marks.mark(kPhSymDenseBitmap, 0);
   hipLaunchKernelGGL(k_off2_finish<256>, dim3(grid_for(nd, 4, cus * 16)), dim3(256), 0, st, plan.bins, r.drow, off2,
                      r.T, cnt_out);
