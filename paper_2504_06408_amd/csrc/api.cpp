@@ -217,9 +217,14 @@ sg_status build_slabs(sg_handle* h, RowSource& r, const sg_csr* B, int vbytes, b
     SG_HIP(h, h->pcol_buf.ensure(sizeof(int32_t) * ne));
   }
   if (vals) SG_HIP(h, h->pval_buf.ensure((size_t)vbytes * ne));
-  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, ls, S, r.T, (int32_t*)h->bnd_buf.p,
+  // destinations of B's entries (int32 positions) for the value scatters of
+  // later numeric passes on the same structure
+  const bool use_perm = B->nnz <= INT32_MAX;
+  if (cols && use_perm) SG_HIP(h, h->perm_buf.ensure(sizeof(int32_t) * ne));
+  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, B->nnz, ls, S, r.T, (int32_t*)h->bnd_buf.p,
                         (int32_t*)h->rpt_buf.p, (int64_t*)h->prow_buf.p, partial, (int32_t*)h->pcol_buf.p,
-                        vals ? h->pval_buf.p : nullptr, cols, vals, h->d_flags, h->cus, st);
+                        vals ? h->pval_buf.p : nullptr, use_perm ? (int32_t*)h->perm_buf.p : nullptr, cols, vals,
+                        h->d_flags, h->cus, st);
   r.rpt = (const int32_t*)h->rpt_buf.p;
   r.prow = (const int64_t*)h->prow_buf.p;
   r.pcol = (const int32_t*)h->pcol_buf.p;
@@ -517,6 +522,7 @@ sg_status sg_handle_destroy(sg_handle* h) {
   h->bnd_buf.release();
   h->rpt_buf.release();
   h->dr_buf.release();
+  h->perm_buf.release();
   h->prow_buf.release();
   h->pcol_buf.release();
   h->pval_buf.release();

@@ -238,27 +238,30 @@ void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows
 }
 
 template <class V>
-void slab_scatter(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int64_t nb, int32_t ls,
-                  int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pcol, void* pval, bool cols, bool vals,
-                  int32_t* err, int cus, hipStream_t st) {
-  const dim3 g(grid_for(nb, 4, cus * 16)), b(256);
+void slab_scatter(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int64_t nb, int64_t nnz,
+                  int32_t ls, int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pcol, void* pval,
+                  int32_t* perm, bool cols, bool vals, int32_t* err, int cus, hipStream_t st) {
+  const dim3 g(grid_for(nb, 256, cus * 16)), b(256);
   const V* bv = (const V*)b_val;
   V* pv = (V*)pval;
   if (cols && vals)
     hipLaunchKernelGGL((k_slab_scatter<V, true, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow, pcol,
-                       pv, err);
+                       pv, perm, err);
   else if (cols)
     hipLaunchKernelGGL((k_slab_scatter<V, true, false>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
-                       pcol, pv, err);
+                       pcol, pv, perm, err);
+  else if (vals && perm)
+    hipLaunchKernelGGL((k_slab_perm_vals<V>), dim3(grid_for(nnz, 256, cus * 16)), b, 0, st, bv, (const int32_t*)perm,
+                       nnz, pv);
   else if (vals)
     hipLaunchKernelGGL((k_slab_scatter<V, false, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
-                       pcol, pv, err);
+                       pcol, pv, (int32_t*)nullptr, err);
 }
 
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
-                           int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
-                           int64_t* partial, int32_t* pcol, void* pval, bool cols, bool vals, int32_t* err, int cus,
-                           hipStream_t st) {
+                           int64_t nnz, int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
+                           int64_t* partial, int32_t* pcol, void* pval, int32_t* perm, bool cols, bool vals,
+                           int32_t* err, int cus, hipStream_t st) {
   if (nb <= 0) return;
   if (cols) {
     hipLaunchKernelGGL(k_slab_bounds<256>, dim3(grid_for(nb, 4, cus * 16)), dim3(256), 0, st, b_rowptr, b_col, nb, T,
@@ -268,9 +271,18 @@ void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const 
     launch_scan_inclusive(prow + 1, (int64_t)S * nb, partial, st);
   }
   switch (vbytes) {
-    case 1: slab_scatter<uint8_t>(b_rowptr, b_col, b_val, nb, ls, S, bnd, prow, pcol, pval, cols, vals, err, cus, st); break;
-    case 4: slab_scatter<uint32_t>(b_rowptr, b_col, b_val, nb, ls, S, bnd, prow, pcol, pval, cols, vals, err, cus, st); break;
-    default: slab_scatter<uint64_t>(b_rowptr, b_col, b_val, nb, ls, S, bnd, prow, pcol, pval, cols, vals, err, cus, st); break;
+    case 1:
+      slab_scatter<uint8_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pcol, pval, perm, cols, vals, err, cus,
+                            st);
+      break;
+    case 4:
+      slab_scatter<uint32_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pcol, pval, perm, cols, vals, err,
+                             cus, st);
+      break;
+    default:
+      slab_scatter<uint64_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pcol, pval, perm, cols, vals, err,
+                             cus, st);
+      break;
   }
 }
 

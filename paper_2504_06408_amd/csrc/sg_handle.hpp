@@ -79,7 +79,8 @@ struct sg_handle {
   SgBuf task_buf;            // dense-row task lists of the numeric pass
   SgBuf p_buf, nt_buf;       // per-row products and terms from symbolic, reused to re-bin numeric
   SgBuf bnd_buf, prow_buf;   // column-slab partition of B: per-row slab bounds, segment starts,
-  SgBuf rpt_buf, dr_buf;     //   tile offsets inside the segments; the dense rows' A rows
+  SgBuf rpt_buf, dr_buf;     //   tile offsets inside the segments; the dense rows' A rows;
+  SgBuf perm_buf;            //   each B entry's position in the partition
   SgBuf pcol_buf, pval_buf;  //   and the partitioned entries
   int slab = 1;              // dense rows of single products use the column-slab path
   int32_t tile_min = sg::kTileMinDefault;

@@ -303,14 +303,16 @@ int64_t analyze_blocks(int64_t nrows);
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,
                         hipStream_t st);
 // Column-slab partition of B (slabs of 2^ls columns, S of them): with cols
-// set, the bounds bnd (S+1 ints per B row), the segment starts prow
-// (S*nb + 1) and pcol; with vals set, pval (vbytes per entry).  partial:
-// scan_partials_len(S*nb) int64 of scratch; err: flag set on entries that
-// contradict the bounds (unsorted or out-of-range columns).
+// set, the bounds bnd (S+1 ints per B row), the tile offsets rpt, the
+// segment starts prow (S*nb + 1), pcol and, when perm is given, each
+// entry's destination; with vals set, pval (vbytes per entry), through perm
+// when it is given and cols is not set.  partial: scan_partials_len(S*nb)
+// int64 of scratch; err: flag set on entries that contradict the bounds
+// (unsorted or out-of-range columns).
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
-                           int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
-                           int64_t* partial, int32_t* pcol, void* pval, bool cols, bool vals, int32_t* err, int cus,
-                           hipStream_t st);
+                           int64_t nnz, int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
+                           int64_t* partial, int32_t* pcol, void* pval, int32_t* perm, bool cols, bool vals,
+                           int32_t* err, int cus, hipStream_t st);
 // Per dense row of the plan: its A row (the slab path's row table).
 void launch_dense_rows(const BinPlan& plan, const int64_t* a_rowptr, DenseRow* dr, int cus, hipStream_t st);
 void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,

@@ -96,35 +96,78 @@ __global__ __launch_bounds__(BS) void k_slab_counts(const int32_t* bnd, int64_t 
   if (blockIdx.x == 0 && threadIdx.x == 0) prow[0] = 0;
 }
 
-// One wavefront per B row scatters its entries into their slab segments.
-// Entries that do not fall where the bounds say (unsorted or out-of-range
-// columns) are dropped and flagged instead of written out of place.
+// Scatter of B's entries into their slab segments.  Each lane takes one B
+// row (wavefront w: rows 64w .. 64w+63); rows with more than kScatterLane
+// entries are then walked by the whole wavefront, one after another.  With
+// kCols the column ids go to pcol and, if perm is given, each entry's
+// destination to perm (so later value scatters need no bounds); with kVals
+// the values go to pval.  Entries that do not fall where the bounds say
+// (unsorted or out-of-range columns) are dropped and flagged instead of
+// written out of place.
+constexpr int kScatterLane = 32;
+
+template <class V, bool kCols, bool kVals>
+SG_DEV void slab_scatter_entry(const int32_t* col, const V* val, int64_t nb, int32_t ls, int32_t S,
+                               const int32_t* r, const int64_t* prow, int64_t k, int64_t s0, int64_t j,
+                               int32_t* pcol, V* pval, int32_t* perm, int32_t* err) {
+  const int32_t c = col[j];
+  const int32_t s = c >> ls;
+  bool ok = c >= 0 && s < S;
+  int64_t dst = 0;
+  if (ok) {
+    const int64_t o = (j - s0) - r[s];
+    ok = o >= 0 && o < (int64_t)(r[s + 1] - r[s]);
+    dst = prow[(int64_t)s * nb + k] + o;
+  }
+  if (!ok) {
+    atomicOr(err, 1);
+    if (perm) perm[j] = -1;
+    return;
+  }
+  if constexpr (kCols) {
+    pcol[dst] = c;
+    if (perm) perm[j] = (int32_t)dst;
+  }
+  if constexpr (kVals) pval[dst] = val[j];
+}
+
 template <class V, bool kCols, bool kVals>
 __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, const int32_t* col, const V* val,
                                                       int64_t nb, int32_t ls, int32_t S, const int32_t* bnd,
-                                                      const int64_t* prow, int32_t* pcol, V* pval, int32_t* err) {
-  const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int64_t nw = ((int64_t)gridDim.x * 256) >> 6;
-  for (int64_t k = w0; k < nb; k += nw) {
-    const int64_t s0 = rowptr[k], e = rowptr[k + 1];
-    const int32_t* r = bnd + k * (S + 1);
-    for (int64_t j = s0 + lane_id(); j < e; j += kWave) {
-      const int32_t c = col[j];
-      const int32_t s = c >> ls;
-      bool ok = c >= 0 && s < S;
-      int64_t dst = 0;
-      if (ok) {
-        const int64_t o = (j - s0) - r[s];
-        ok = o >= 0 && o < (int64_t)(r[s + 1] - r[s]);
-        dst = prow[(int64_t)s * nb + k] + o;
-      }
-      if (!ok) {
-        atomicOr(err, 1);
-        continue;
-      }
-      if constexpr (kCols) pcol[dst] = c;
-      if constexpr (kVals) pval[dst] = val[j];
+                                                      const int64_t* prow, int32_t* pcol, V* pval, int32_t* perm,
+                                                      int32_t* err) {
+  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t k0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * kWave; k0 < nb; k0 += nwaves * kWave) {
+    const int64_t k = k0 + lane_id();
+    int64_t s0 = 0, e = 0;
+    if (k < nb) {
+      s0 = rowptr[k];
+      e = rowptr[k + 1];
     }
+    const bool longrow = e - s0 > kScatterLane;
+    if (!longrow)
+      for (int64_t j = s0; j < e; ++j)
+        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, j, pcol, pval,
+                                            perm, err);
+    unsigned long long m = __ballot(longrow);
+    while (m) {
+      const int l = __ffsll((long long)m) - 1;
+      m &= m - 1ull;
+      const int64_t kk = k0 + l;
+      const int64_t ss = shfl_any(s0, l), ee = shfl_any(e, l);
+      for (int64_t j = ss + lane_id(); j < ee; j += kWave)
+        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + kk * (S + 1), prow, kk, ss, j, pcol, pval,
+                                            perm, err);
+    }
+  }
+}
+
+// Value scatter through the destinations recorded by the column scatter.
+template <class V>
+__global__ __launch_bounds__(256) void k_slab_perm_vals(const V* val, const int32_t* perm, int64_t n, V* pval) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const int32_t d = perm[j];
+    if (d >= 0) pval[d] = val[j];
   }
 }
 
