@@ -107,3 +107,14 @@ def test_dense_slab_option_errors(h):
     import paper_2504_06408_amd as sg
     with pytest.raises(sg.SgError):
         h.set_option("dense_slab", 2)
+
+
+@pytest.mark.parametrize("sr", ALL)
+def test_many_sources_per_row(h, sr):
+    """Rows of A with ~700 stored entries: more sources than one workgroup
+    chunk, so the symbolic, light and heavy slab kernels load sources chunk
+    by chunk (and the heavy kernel per tile)."""
+    _reset(h)
+    A = with_vals(synth.er(24, 2000, 700, 230), sr, 231)
+    B = _hstack([synth.er(2000, 16384, 40, 232), synth.er(2000, 300000, 6, 233)], sr, 234)
+    check_product(h, sr, A, B, what="many sources")
