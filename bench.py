@@ -14,8 +14,10 @@ with HIP events on the library's stream) and the CPU oracle's throughput on a
 bounded sample of the same rows.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -56,6 +58,35 @@ def make_inputs(name):
         A = synth.er(size, size, 8, 1).with_values(synth.values(vmap[vk], size * 8, lo, hi, 11))
         B = synth.er(size, size, 8, 2).with_values(synth.values(vmap[vk], size * 8, lo, hi, 12))
     return A, B, sr, desc
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COUNTERS = os.path.join(HERE, "profiles", "rmat20_minplus_hbm_counters.md")
+
+
+def kernel_sources_sha256() -> str:
+    """Digest of the HIP sources of the library (any edit changes it)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2504_06408_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy kernel) from the committed counter summary, when
+    that summary was taken on the current kernel sources; otherwise None."""
+    if workload != "rmat20_minplus" or not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    fields = dict(re.findall(r"^(dominant_kernel|traffic_bytes_per_launch|kernel_sources_sha256): (\S+)$", text, re.M))
+    if fields.get("dominant_kernel") != kernel or fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def products_per_row(A, B):
@@ -303,7 +334,8 @@ def main():
     kb = kernels[dom]
     achieved = kb / (phases[dom] * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_launch": int(kb),
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(args.workload, dom),
+            "bytes_per_launch": int(kb),
             "ms_per_launch": round(phases[dom], 4)}
 
     out = {

@@ -216,7 +216,8 @@ sg_status build_slabs(sg_handle* h, RowSource& r, const sg_csr* B, int vbytes, b
     SG_HIP(h, h->prow_buf.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
     SG_HIP(h, h->pcol_buf.ensure(sizeof(int32_t) * ne));
   }
-  if (vals) SG_HIP(h, h->pval_buf.ensure((size_t)vbytes * ne));
+  // numeric partition entries: (column, value) pairs, 8 bytes (16 for 8-byte values)
+  if (vals) SG_HIP(h, h->pval_buf.ensure((size_t)(vbytes >= 8 ? 16 : 8) * ne));
   // destinations of B's entries (int32 positions) for the value scatters of
   // later numeric passes on the same structure
   const bool use_perm = B->nnz <= INT32_MAX;

@@ -239,23 +239,23 @@ void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows
 
 template <class V>
 void slab_scatter(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int64_t nb, int64_t nnz,
-                  int32_t ls, int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pcol, void* pval,
+                  int32_t ls, int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pcol, void* pcv,
                   int32_t* perm, bool cols, bool vals, int32_t* err, int cus, hipStream_t st) {
   const dim3 g(grid_for(nb, 256, cus * 16)), b(256);
   const V* bv = (const V*)b_val;
-  V* pv = (V*)pval;
+  ColV<V>* cv = (ColV<V>*)pcv;
   if (cols && vals)
     hipLaunchKernelGGL((k_slab_scatter<V, true, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow, pcol,
-                       pv, perm, err);
+                       cv, perm, err);
   else if (cols)
     hipLaunchKernelGGL((k_slab_scatter<V, true, false>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
-                       pcol, pv, perm, err);
+                       pcol, cv, perm, err);
   else if (vals && perm)
-    hipLaunchKernelGGL((k_slab_perm_vals<V>), dim3(grid_for(nnz, 256, cus * 16)), b, 0, st, bv, (const int32_t*)perm,
-                       nnz, pv);
+    hipLaunchKernelGGL((k_slab_perm_cv<V>), dim3(grid_for(nnz, 256, cus * 16)), b, 0, st, b_col, bv,
+                       (const int32_t*)perm, nnz, cv);
   else if (vals)
     hipLaunchKernelGGL((k_slab_scatter<V, false, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
-                       pcol, pv, (int32_t*)nullptr, err);
+                       pcol, cv, (int32_t*)nullptr, err);
 }
 
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,

@@ -42,7 +42,7 @@ struct RowSource {
   // column-slab partition of B (single product; S = 0: not used)
   const int64_t* prow;
   const int32_t* pcol;
-  const void* pval;
+  const void* pval;       // numeric partition: (column, value) pairs (ColV)
   const int32_t* rpt;     // tile offsets inside each slab segment
   const DenseRow* drow;   // per dense row: its A row
   int32_t ls, S;
@@ -208,7 +208,7 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
                          c.src.drow, c.off2, T, G, c.src.S, (int32_t)kSlabCap, (const int64_t*)c.C.rowptr, light,
                          heavy, sbook, c.task_ctr);
       hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, sbook, T, c.task_ctr);
-      SlabB<V> b{c.src.prow, c.src.pcol, (const V*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
+      SlabB<V> b{c.src.prow, c.src.pcol, (const ColV<V>*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
       {
         auto k = k_num_slab<Sr, V, 512, kSlabCap>;
         static int occ = occupancy(k, 512);

@@ -2,7 +2,9 @@
 //
 // B's columns are cut into slabs of 2^ls columns (one to eight 16384-column
 // tiles).  A partition of B keeps, for slab s and B row k, the entries of
-// B_k inside the slab contiguous:  pcol/pval[prow[s*nb + k] .. prow[s*nb + k + 1]),
+// B_k inside the slab contiguous:  pcol/pcv[prow[s*nb + k] .. prow[s*nb + k + 1])
+// (pcol: column ids for the symbolic pass; pcv: column and value pairs for
+// the numeric pass),
 // and rpt[(s*nb + k)*(G+1) + t] holds where tile t of the slab starts inside
 // that segment.  A dense row's work is one task per (row, slab); every task
 // finds each source's segment with one read of prow, and the tasks run in
@@ -31,6 +33,14 @@ constexpr int kSlabLogMin = kTileLog;  // a slab is 1..8 column tiles
 constexpr int kSlabLogMax = 17;
 constexpr int kSlabWordsMax = 1 << (kSlabLogMax - 5);
 constexpr int kSlabTilesMax = 1 << (kSlabLogMax - kTileLog);
+
+// One entry of the numeric partition of B: column id and value side by side,
+// so a product is one load (8 bytes, or 16 for 8-byte values).
+template <class V>
+struct alignas(sizeof(V) >= 8 ? 16 : 8) ColV {
+  int32_t c;
+  V v;
+};
 
 // Per dense row (position h in the dense list): its A row.
 struct DenseRow {
@@ -109,7 +119,7 @@ constexpr int kScatterLane = 32;
 template <class V, bool kCols, bool kVals>
 SG_DEV void slab_scatter_entry(const int32_t* col, const V* val, int64_t nb, int32_t ls, int32_t S,
                                const int32_t* r, const int64_t* prow, int64_t k, int64_t s0, int64_t j,
-                               int32_t* pcol, V* pval, int32_t* perm, int32_t* err) {
+                               int32_t* pcol, ColV<V>* pcv, int32_t* perm, int32_t* err) {
   const int32_t c = col[j];
   const int32_t s = c >> ls;
   bool ok = c >= 0 && s < S;
@@ -128,13 +138,13 @@ SG_DEV void slab_scatter_entry(const int32_t* col, const V* val, int64_t nb, int
     pcol[dst] = c;
     if (perm) perm[j] = (int32_t)dst;
   }
-  if constexpr (kVals) pval[dst] = val[j];
+  if constexpr (kVals) pcv[dst] = ColV<V>{c, val[j]};
 }
 
 template <class V, bool kCols, bool kVals>
 __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, const int32_t* col, const V* val,
                                                       int64_t nb, int32_t ls, int32_t S, const int32_t* bnd,
-                                                      const int64_t* prow, int32_t* pcol, V* pval, int32_t* perm,
+                                                      const int64_t* prow, int32_t* pcol, ColV<V>* pcv, int32_t* perm,
                                                       int32_t* err) {
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
   for (int64_t k0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * kWave; k0 < nb; k0 += nwaves * kWave) {
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, con
     const bool longrow = e - s0 > kScatterLane;
     if (!longrow)
       for (int64_t j = s0; j < e; ++j)
-        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, j, pcol, pval,
+        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, j, pcol, pcv,
                                             perm, err);
     unsigned long long m = __ballot(longrow);
     while (m) {
@@ -156,18 +166,20 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, con
       const int64_t kk = k0 + l;
       const int64_t ss = shfl_any(s0, l), ee = shfl_any(e, l);
       for (int64_t j = ss + lane_id(); j < ee; j += kWave)
-        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + kk * (S + 1), prow, kk, ss, j, pcol, pval,
+        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + kk * (S + 1), prow, kk, ss, j, pcol, pcv,
                                             perm, err);
     }
   }
 }
 
-// Value scatter through the destinations recorded by the column scatter.
+// Numeric partition through the destinations recorded by the column
+// scatter (one thread per B entry).
 template <class V>
-__global__ __launch_bounds__(256) void k_slab_perm_vals(const V* val, const int32_t* perm, int64_t n, V* pval) {
+__global__ __launch_bounds__(256) void k_slab_perm_cv(const int32_t* col, const V* val, const int32_t* perm, int64_t n,
+                                                      ColV<V>* pcv) {
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
     const int32_t d = perm[j];
-    if (d >= 0) pval[d] = val[j];
+    if (d >= 0) pcv[d] = ColV<V>{col[j], val[j]};
   }
 }
 
@@ -287,7 +299,7 @@ template <class V>
 struct SlabB {
   const int64_t* prow;
   const int32_t* pcol;
-  const V* pval;
+  const ColV<V>* pcv;
   const int32_t* rpt;
   int64_t nb;
   int32_t G, T;
@@ -296,7 +308,7 @@ struct SlabB {
 constexpr int kBoffCache = 256;  // bucket offsets kept in LDS
 
 // LDS of one chunk of a task's sources: the A value, the start of the
-// source's window segment in pcol/pval, and the exclusive prefix of the
+// source's window segment in the partition, and the exclusive prefix of the
 // segment lengths.
 template <class V, int BS>
 struct SrcLds {
@@ -353,7 +365,7 @@ SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_va
 // One block of 64*U consecutive products [qb, qb + 64*U) of a chunk: lane
 // l takes q = qb + u*64 + l (u < U), so every load
 // instruction is coalesced; owners are found by a search narrowed to the
-// block's first and last owner.  fetch(owner, index into pcol/pval) returns
+// block's first and last owner.  fetch(owner, index into the partition) returns
 // a product; ok[u] tells which pp[u] hold one.
 template <int BS, int U, class V, class Fetch, class P>
 SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, Fetch& fetch, P* pp, bool* ok) {
@@ -510,12 +522,13 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     // With one round of products per wavefront the products stay in
     // registers for pass 2; otherwise pass 2 gathers them again.
     const bool held = one && total <= (int64_t)NW * kWave * kSlabU;
-    auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - cw0); };
+    auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcv[idx].c - cw0); };
     auto a1 = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
     };
     auto f2 = [&](int ow, int64_t idx) {
-      return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+      const ColV<V> e = b.pcv[idx];
+        return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)};
     };
     auto a2 = [&](const ColVal<Acc>& p) {
       if ((uint32_t)p.c >= cmax) return;
@@ -599,7 +612,7 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
 // reaches (kValueMarks) occupancy is read off the accumulator, otherwise an
 // occupancy bitmap is kept.
 template <class Sr, class V, int BS>
-__global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
+__global__ __launch_bounds__(BS, 4) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
                                                        const int32_t* off2, OutC C, const SlabTask* tasks,
                                                        const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
@@ -625,15 +638,22 @@ __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t
       const int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
       s_tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
     }
-    // the row's sources: one per thread when one chunk holds them all
+    // the row's sources: one per thread when one chunk holds them all, with
+    // the source's tile offsets kept in registers for every tile
     const bool one = tk.nsrc <= BS;
-    int32_t k = 0;
     int64_t sst = 0;
+    int32_t rec[kSlabTilesMax + 1];
+#pragma unroll
+    for (int q = 0; q <= kSlabTilesMax; ++q) rec[q] = 0;
     if (one && (int)threadIdx.x < tk.nsrc) {
       const int64_t e = tk.a0 + threadIdx.x;
-      k = a_col[e];
+      const int32_t k = a_col[e];
       L.a[threadIdx.x] = a_val[e];
       sst = b.prow[(int64_t)tk.s * b.nb + k];
+      const int32_t* r = b.rpt + ((int64_t)tk.s * b.nb + k) * (G + 1);
+#pragma unroll
+      for (int q = 0; q <= kSlabTilesMax; ++q)
+        if (q <= G) rec[q] = r[q];
     }
     __syncthreads();
     for (int t = ts0; t < ts1; ++t) {
@@ -641,7 +661,8 @@ __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t
       if (mt <= 0) continue;
       const int64_t cw0 = (int64_t)t << kTileLog;
       auto f = [&](int ow, int64_t idx) {
-        return ColVal<Acc>{(int32_t)(b.pcol[idx] - cw0), Sr::mul(L.a[ow], b.pval[idx])};
+        const ColV<V> e = b.pcv[idx];
+        return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)};
       };
       auto ap = [&](const ColVal<Acc>& p) {
         if ((uint32_t)p.c >= (uint32_t)kTile) return;
@@ -651,10 +672,15 @@ __global__ __launch_bounds__(BS) void k_num_slab_heavy(SlabB<V> b, const int32_t
       if (one) {
         int64_t len = 0, st = 0;
         if ((int)threadIdx.x < tk.nsrc) {
-          const int32_t* r = b.rpt + ((int64_t)tk.s * b.nb + k) * (G + 1) + (t - ts0);
-          const int32_t w0 = r[0];
+          int32_t w0 = 0, w1 = 0;
+#pragma unroll
+          for (int q = 0; q < kSlabTilesMax; ++q)
+            if (q == t - ts0) {
+              w0 = rec[q];
+              w1 = rec[q + 1];
+            }
           st = sst + w0;
-          len = r[1] - w0;
+          len = w1 - w0;
         }
         int64_t total;
         const int64_t off = block_excl_scan<NW, int64_t>(len, L.wave, &total);
