@@ -120,6 +120,52 @@ sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const i
   return SG_OK;
 }
 
+sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
+                      int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st) {
+  const int32_t ls = slab_log(r.ncols), S = slab_count(r.ncols, ls);
+  const int64_t nb = B->nrows;
+  const size_t ne = (size_t)(B->nnz > 0 ? B->nnz : 1);
+  const int32_t G = 1 << (ls - kTileLog);
+  if (cols) {
+    SG_HIP(h, sb.bnd.ensure(sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
+    SG_HIP(h, sb.rpt.ensure(sizeof(int32_t) * (size_t)S * (size_t)nb * (size_t)(G + 1)));
+    SG_HIP(h, sb.prow.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
+    SG_HIP(h, sb.pcol.ensure(sizeof(int32_t) * ne));
+  }
+  // numeric partition entries: (column, value) pairs, 8 bytes (16 for 8-byte values)
+  if (vals) SG_HIP(h, sb.pcv.ensure((size_t)(vbytes >= 8 ? 16 : 8) * ne));
+  // destinations of B's entries (int32 positions) for the value scatters of
+  // later numeric passes on the same structure
+  const bool use_perm = B->nnz <= INT32_MAX;
+  if (cols && use_perm) SG_HIP(h, sb.perm.ensure(sizeof(int32_t) * ne));
+  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, B->nnz, ls, S, r.T, (int32_t*)sb.bnd.p,
+                        (int32_t*)sb.rpt.p, (int64_t*)sb.prow.p, partial, (int32_t*)sb.pcol.p,
+                        vals ? sb.pcv.p : nullptr, use_perm ? (int32_t*)sb.perm.p : nullptr, cols, vals, err, h->cus,
+                        st);
+  r.rpt = (const int32_t*)sb.rpt.p;
+  r.prow = (const int64_t*)sb.prow.p;
+  r.pcol = (const int32_t*)sb.pcol.p;
+  r.pval = vals ? sb.pcv.p : nullptr;
+  r.ls = ls;
+  r.S = S;
+  r.qctr = qctr;
+  return SG_OK;
+}
+
+sg_status build_dense_rows(sg_handle* h, SlabBufs& sb, RowSource& r, const BinPlan& plan, hipStream_t st) {
+  const int32_t nd = plan.bins.nd_cap;
+  SG_HIP(h, sb.dr.ensure(sizeof(DenseRow) * (size_t)(nd > 0 ? nd : 1)));
+  launch_dense_rows(plan, r.a_rowptr, (DenseRow*)sb.dr.p, h->cus, st);
+  r.drow = (const DenseRow*)sb.dr.p;
+  return SG_OK;
+}
+
+size_t slab_partials(const sg_handle* h, const RowSource& r) {
+  if (r.mode != kModeProduct || !h->slab) return 0;
+  const int32_t ls = slab_log(r.ncols);
+  return (size_t)scan_partials_len((int64_t)slab_count(r.ncols, ls) * r.b_nrows);
+}
+
 }  // namespace sg
 
 namespace {
@@ -201,56 +247,6 @@ sg_status upload_parts(sg_handle* h, int nparts, const sg_csr* parts, hipStream_
   return SG_OK;
 }
 
-// Column-slab partition of B for the dense rows of a single product: with
-// cols, the bounds, segment starts and column ids (kept for the numeric pass
-// on the same structure); with vals, the partitioned values (vbytes each).
-sg_status build_slabs(sg_handle* h, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
-                      int64_t* partial, hipStream_t st) {
-  const int32_t ls = slab_log(r.ncols), S = slab_count(r.ncols, ls);
-  const int64_t nb = B->nrows;
-  const size_t ne = (size_t)(B->nnz > 0 ? B->nnz : 1);
-  const int32_t G = 1 << (ls - kTileLog);
-  if (cols) {
-    SG_HIP(h, h->bnd_buf.ensure(sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
-    SG_HIP(h, h->rpt_buf.ensure(sizeof(int32_t) * (size_t)S * (size_t)nb * (size_t)(G + 1)));
-    SG_HIP(h, h->prow_buf.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
-    SG_HIP(h, h->pcol_buf.ensure(sizeof(int32_t) * ne));
-  }
-  // numeric partition entries: (column, value) pairs, 8 bytes (16 for 8-byte values)
-  if (vals) SG_HIP(h, h->pval_buf.ensure((size_t)(vbytes >= 8 ? 16 : 8) * ne));
-  // destinations of B's entries (int32 positions) for the value scatters of
-  // later numeric passes on the same structure
-  const bool use_perm = B->nnz <= INT32_MAX;
-  if (cols && use_perm) SG_HIP(h, h->perm_buf.ensure(sizeof(int32_t) * ne));
-  launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, B->nnz, ls, S, r.T, (int32_t*)h->bnd_buf.p,
-                        (int32_t*)h->rpt_buf.p, (int64_t*)h->prow_buf.p, partial, (int32_t*)h->pcol_buf.p,
-                        vals ? h->pval_buf.p : nullptr, use_perm ? (int32_t*)h->perm_buf.p : nullptr, cols, vals,
-                        h->d_flags, h->cus, st);
-  r.rpt = (const int32_t*)h->rpt_buf.p;
-  r.prow = (const int64_t*)h->prow_buf.p;
-  r.pcol = (const int32_t*)h->pcol_buf.p;
-  r.pval = vals ? h->pval_buf.p : nullptr;
-  r.ls = ls;
-  r.S = S;
-  r.qctr = h->d_flags + kCtrBase;
-  return SG_OK;
-}
-
-// Per dense row of the plan: its A row (first entry, length, row id).
-sg_status build_dense_rows(sg_handle* h, RowSource& r, const BinPlan& plan, hipStream_t st) {
-  const int32_t nd = plan.ndense();
-  SG_HIP(h, h->dr_buf.ensure(sizeof(DenseRow) * (size_t)(nd > 0 ? nd : 1)));
-  launch_dense_rows(plan, r.a_rowptr, (DenseRow*)h->dr_buf.p, h->cus, st);
-  r.drow = (const DenseRow*)h->dr_buf.p;
-  return SG_OK;
-}
-
-size_t slab_partials(const sg_handle* h, const RowSource& r) {
-  if (r.mode != kModeProduct || !h->slab) return 0;
-  const int32_t ls = slab_log(r.ncols);
-  return (size_t)scan_partials_len((int64_t)slab_count(r.ncols, ls) * r.b_nrows);
-}
-
 // Shared body of the two symbolic entry points: counts into C_rowptr[1..n],
 // dense-row tile offsets into the handle's cache, scan, readback of nnz.
 sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_rowptr, int64_t* nnzC,
@@ -289,8 +285,8 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
       launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
     }
     if (slab) {
-      SG_TRY(build_slabs(h, r, B, 0, true, false, spartial, st));
-      SG_TRY(build_dense_rows(h, r, plan, st));
+      SG_TRY(build_slabs(h, h->sb, r, B, 0, true, false, spartial, h->d_flags, h->d_flags + kCtrBase, st));
+      SG_TRY(build_dense_rows(h, h->sb, r, plan, st));
     }
     mk.mark(kPhSymBounds, 0);
   }
@@ -342,8 +338,8 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
     if (slab) {
       // structure from the last symbolic pass when cached; values every call
       int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
-      SG_TRY(build_slabs(h, r, B, sr->value_bytes, !cached, true, spartial, st));
-      SG_TRY(build_dense_rows(h, r, plan, st));
+      SG_TRY(build_slabs(h, h->sb, r, B, sr->value_bytes, !cached, true, spartial, h->d_flags, h->d_flags + kCtrBase, st));
+      SG_TRY(build_dense_rows(h, h->sb, r, plan, st));
     } else if (r.mode == kModeProduct && r.T > 1) {
       if (!cached) {
         SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
@@ -520,13 +516,7 @@ sg_status sg_handle_destroy(sg_handle* h) {
   h->task_buf.release();
   h->p_buf.release();
   h->nt_buf.release();
-  h->bnd_buf.release();
-  h->rpt_buf.release();
-  h->dr_buf.release();
-  h->perm_buf.release();
-  h->prow_buf.release();
-  h->pcol_buf.release();
-  h->pval_buf.release();
+  h->sb.release();
   h->rp2_buf.release();
   h->off2_buf.release();
   h->parts_buf.release();

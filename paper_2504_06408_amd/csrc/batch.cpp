@@ -42,6 +42,12 @@ struct Stage {
   int32_t nd = 0;
   int64_t nnz = 0;
   SgBuf work, off_buf, off2_buf, col_buf, val_buf, task_buf;
+  // a single product recorded on the column-slab path: B's partition, its
+  // scan scratch and B's descriptor
+  bool slab = false;
+  SlabBufs sb;
+  SgBuf spart;
+  sg_csr b{};
   // views into work
   int64_t* p = nullptr;
   int32_t* nt = nullptr;
@@ -95,6 +101,15 @@ struct Stage {
     col_buf.release();
     val_buf.release();
     task_buf.release();
+    sb.release();
+    spart.release();
+  }
+  // dense-row task memory: the slab path's light and heavy lists, or the
+  // tile and range lists
+  size_t task_bytes() const {
+    const int64_t n = nd > 0 ? nd : 1;
+    if (slab) return 2 * sizeof(SlabTask) * (size_t)n * (size_t)src.S + sizeof(int32_t) * (6 * (size_t)src.T + 3);
+    return task_buffer_bytes(n * src.T, src.T);
   }
 };
 
@@ -140,7 +155,18 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
   S.nd = bp.ndense();
   bp.bins = Bins{S.list, S.bin_start, S.bin_count, S.nd};
   SG_HIP(h, S.off2_buf.ensure(sizeof(int32_t) * (size_t)(S.nd > 0 ? S.nd : 1) * (size_t)(S.src.T + 1)));
-  SG_HIP(h, S.task_buf.ensure(task_buffer_bytes((int64_t)(S.nd > 0 ? S.nd : 1) * S.src.T, S.src.T)));
+  if (S.slab && S.nd > 0) {
+    // structure once (patterns do not change after planning); values are
+    // re-scattered by every replay
+    SG_HIP(h, S.spart.ensure(sizeof(int64_t) * (slab_partials(h, S.src) + 1)));
+    SG_TRY(build_slabs(h, S.sb, S.src, &S.b, P->sr.value_bytes, true, true, (int64_t*)S.spart.p, P->d_flag + 1,
+                       P->d_flag + kCtrBase, st));
+    SG_TRY(build_dense_rows(h, S.sb, S.src, bp, st));
+  } else {
+    S.slab = false;
+    S.src.S = 0;
+  }
+  SG_HIP(h, S.task_buf.ensure(S.task_bytes()));
   if (S.nd > 0 && has_dense_inputs)
     for (auto& b : P->bounds)
       launch_tile_bounds(std::get<0>(b), std::get<1>(b), std::get<2>(b), std::get<3>(b), std::get<4>(b), h->cus, st);
@@ -187,6 +213,9 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   launch_scan_inclusive(S.off + 1, S.R, S.partial, st);
   launch_rebin(S.p, S.nt, S.off, S.R, pn, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, st);
   launch_pool_guard(S.off + S.R, pool_cap(S, (size_t)P->sr.value_bytes), S.bin_count, P->d_flag, st);
+  if (S.slab)  // the current values into the partition (buffers sized at plan time)
+    (void)build_slabs(h, S.sb, S.src, &S.b, P->sr.value_bytes, false, true, (int64_t*)S.spart.p, P->d_flag + 1,
+                      P->d_flag + kCtrBase, st);
   NumCtx c{};
   c.src = S.src;
   c.plan = bp;
@@ -196,6 +225,11 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   c.task_ctr = P->d_flag + kCtrBase;
   c.task_cap = (int64_t)(S.nd > 0 ? S.nd : 1) * S.src.T;
   c.tasks = (Task*)S.task_buf.p;
+  if (S.slab) {
+    const size_t tb = 2 * sizeof(SlabTask) * (size_t)S.nd * (size_t)S.src.S;
+    c.slab_tasks = (SlabTask*)S.task_buf.p;
+    c.slab_book = (int32_t*)((char*)S.task_buf.p + tb);
+  }
   c.tile_min = h->tile_min;
   c.cus = h->cus;
   c.comp_dense = pn.comp_mode != kCompNone;
@@ -269,6 +303,9 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   P->d_lrow_m = a.take<int64_t>((size_t)(P->ltot_m > 0 ? P->ltot_m : 1));
   P->d_flag = a.take<int32_t>(kFlagInts);
 
+  // one product and no merges: recorded as a single product on the
+  // column-slab path (no tile-bounds tables needed)
+  const bool single = np == 1 && ng == 0 && h->slab;
   // distinct B operands that need column-tile bounds
   std::map<std::tuple<const int64_t*, const int32_t*, int64_t>, int32_t*> seen;
   std::vector<ProbDesc> probs((size_t)np);
@@ -284,7 +321,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
     d.b_val = B.val;
     d.ncols = B.ncols;
     d.T = tiles_of(B.ncols);
-    if (d.T > 1) {
+    if (d.T > 1 && !single) {
       auto key = std::make_tuple((const int64_t*)B.rowptr, (const int32_t*)B.col, B.nrows);
       auto it = seen.find(key);
       if (it == seen.end()) {
@@ -312,12 +349,30 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
 
   // ---- product stage: size it with an eager pass ----
   Stage& S = P->prod;
-  S.src.mode = kModeBatchProducts;
-  S.src.probs = P->d_probs;
-  S.src.rbase = P->d_rbase_p;
-  S.src.ntable = np;
-  S.src.nrows = Rp;
-  S.src.T = Tmax_p;
+  if (single) {
+    const sg_csr& A = P->A[0];
+    const sg_csr& B = P->B[0];
+    S.src.mode = kModeProduct;
+    S.src.a_rowptr = A.rowptr;
+    S.src.a_col = A.col;
+    S.src.a_val = A.val;
+    S.src.b_rowptr = B.rowptr;
+    S.src.b_col = B.col;
+    S.src.b_val = B.val;
+    S.src.b_nrows = B.nrows;
+    S.src.nrows = A.nrows;
+    S.src.ncols = B.ncols;
+    S.src.T = tiles_of(B.ncols);
+    S.slab = true;
+    S.b = B;
+  } else {
+    S.src.mode = kModeBatchProducts;
+    S.src.probs = P->d_probs;
+    S.src.rbase = P->d_rbase_p;
+    S.src.ntable = np;
+    S.src.nrows = Rp;
+    S.src.T = Tmax_p;
+  }
   S.R = Rp;
   SG_TRY(S.alloc_work(h));
   SG_TRY(run_stage_eager(P, S, true));

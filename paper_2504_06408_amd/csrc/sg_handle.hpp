@@ -38,6 +38,22 @@ struct SgBuf {
   }
 };
 
+// Column-slab partition of one B (per-row slab bounds, tile offsets inside
+// the segments, segment starts, column ids, (column, value) pairs, each B
+// entry's position) and the dense-row table of the product using it.
+struct SlabBufs {
+  SgBuf bnd, rpt, prow, pcol, pcv, perm, dr;
+  void release() {
+    bnd.release();
+    rpt.release();
+    prow.release();
+    pcol.release();
+    pcv.release();
+    perm.release();
+    dr.release();
+  }
+};
+
 // Bump allocator over a buffer; with base == nullptr it only measures.
 struct SgArena {
   char* base = nullptr;
@@ -78,10 +94,7 @@ struct sg_handle {
   SgBuf parts_buf;           // device table of merge parts
   SgBuf task_buf;            // dense-row task lists of the numeric pass
   SgBuf p_buf, nt_buf;       // per-row products and terms from symbolic, reused to re-bin numeric
-  SgBuf bnd_buf, prow_buf;   // column-slab partition of B: per-row slab bounds, segment starts,
-  SgBuf rpt_buf, dr_buf;     //   tile offsets inside the segments; the dense rows' A rows;
-  SgBuf perm_buf;            //   each B entry's position in the partition
-  SgBuf pcol_buf, pval_buf;  //   and the partitioned entries
+  SlabBufs sb;               // column-slab partition of B and the dense-row table
   int slab = 1;              // dense rows of single products use the column-slab path
   int32_t tile_min = sg::kTileMinDefault;
   std::vector<sg::PartDesc> parts_host;
@@ -109,6 +122,16 @@ sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const i
                     SgArena& ar, BinPlan& plan, hipStream_t st, int64_t* p_keep = nullptr,
                     int32_t* nt_keep = nullptr, bool rebin = false);
 size_t plan_rows_bytes(int64_t nrows);
+// Column-slab partition of B for the dense rows of single product r: with
+// cols, the structure (bounds, tile offsets, segment starts, column ids and
+// each entry's position); with vals, the (column, value) pairs.  partial:
+// slab_partials() int64 of scratch.  Fills r's slab fields.
+sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
+                      int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st);
+// Per dense row of the plan: its A row (first entry, length, row id).
+sg_status build_dense_rows(sg_handle* h, SlabBufs& sb, RowSource& r, const BinPlan& plan, hipStream_t st);
+// int64 scratch the partition's scan needs (0 when r does not use slabs).
+size_t slab_partials(const sg_handle* h, const RowSource& r);
 // Timing hooks of the handle for a call on stream st (inactive unless the
 // "timing" option is on); clear_phases forgets phases [p0, p1).
 Marks handle_marks(sg_handle* h, hipStream_t st);

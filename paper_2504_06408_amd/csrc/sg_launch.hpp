@@ -196,7 +196,7 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
   if constexpr (kProduct) {
     if (slab) {
       const int32_t T = c.src.T;
-      const int32_t nd = c.plan.ndense();
+      const int32_t nd = c.plan.bins.nd_cap;  // bucket capacity (the count itself may only be on the device)
       int32_t* sbook = c.slab_book;
       SlabTask* light = c.slab_tasks;
       SlabTask* heavy = c.slab_tasks + (int64_t)nd * c.src.S;

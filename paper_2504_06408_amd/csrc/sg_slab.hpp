@@ -231,8 +231,8 @@ constexpr int kTaskSlabsLds = 512;  // slabs whose bucket counters a block keeps
 // One thread per dense row: every non-empty slab of the row becomes a light
 // task (at most `cap` entries: bitmap + rank in LDS) or a heavy one (a dense
 // LDS accumulator per tile).  Both lists hold per-slab buckets of nd slots
-// (book[l*T + s] counts bucket s of list l), so walking them in order is
-// slab-major.  A block counts its tasks per (list, slab) in LDS, reserves
+// (book[l*T + s] counts bucket s of list l; nd = bins.nd_cap), so walking
+// them in order is slab-major.  A block counts its tasks per (list, slab) in LDS, reserves
 // each range with one global atomic, then writes the tasks.  Entries per
 // list are summed for the statistics.
 template <int BS>
@@ -246,6 +246,7 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
   if (threadIdx.x < 2) s_ent[threadIdx.x] = 0ull;
   __syncthreads();
   const int64_t nd = dense_rows(bins);
+  const int64_t stride = bins.nd_cap;  // slots per bucket
   int32_t* cnt_g[2] = {book + kListSlab * T, book + kListTile * T};
   unsigned long long ent[2] = {0ull, 0ull};
   for (int64_t h0 = (int64_t)blockIdx.x * BS; h0 < nd; h0 += (int64_t)gridDim.x * BS) {
@@ -279,7 +280,8 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
         if (m <= 0) continue;
         const int l = m <= cap ? 0 : 1;
         const int32_t slot = lds ? s_base[l][sl] + atomicAdd(&s_cnt[l][sl], 1) : atomicAdd(&cnt_g[l][sl], 1);
-        (l == 0 ? light : heavy)[(int64_t)sl * nd + slot] = SlabTask{(int32_t)h, sl, ta, tb, base + lo, d.a0, d.nsrc, m};
+        (l == 0 ? light : heavy)[(int64_t)sl * stride + slot] =
+            SlabTask{(int32_t)h, sl, ta, tb, base + lo, d.a0, d.nsrc, m};
         ent[l] += (unsigned long long)m;
       }
     }

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import BOOL, EXACT, F64, I64, MINPLUS, assert_close_gated, with_vals
+from helpers import ALL, BOOL, EXACT, F64, I64, MINPLUS, assert_close_gated, with_vals
 from gpu_helpers import compare, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -130,3 +130,36 @@ def test_batch_shape_errors(h):
     with pytest.raises(sg.SgError) as e:
         h.batch_plan(sg.semiring(F64), [dA], [dA])
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("sr", ALL)
+@pytest.mark.parametrize("path", ["auto", "dense"])
+def test_batch_single_product(h, sr, path):
+    """A plan of one product and no merges is recorded on the column-slab
+    path: results match the oracle, replays pick up new values, and repeated
+    replays agree bit for bit on exact semirings."""
+    import torch
+    import paper_2504_06408_amd as sg
+    import oracle
+    from gpu_helpers import compare
+    h.set_option("force_path", path)
+    try:
+        A = with_vals(synth.rmat(11, 16, seed=80), sr, 81)
+        dA = to_dev(A)
+        plan = h.batch_plan(sg.semiring(sr), [dA], [dA])
+        plan.execute()
+        rp, cl, vl = plan.results_numpy()[0]
+        compare(sr, rp, cl, vl, oracle.get().spgemm(sr, A, A), "single product")
+        A2 = with_vals(A, sr, 82)
+        dA.val.copy_(torch.from_numpy(np.ascontiguousarray(A2.val)).to(dA.val.device))
+        plan.execute()
+        rp2, cl2, vl2 = plan.results_numpy()[0]
+        compare(sr, rp2, cl2, vl2, oracle.get().spgemm(sr, A2, A2), "single product, new values")
+        plan.execute()
+        rp3, cl3, vl3 = plan.results_numpy()[0]
+        assert np.array_equal(rp2, rp3) and np.array_equal(cl2, cl3)
+        if sr in EXACT:
+            assert np.array_equal(vl2.view(np.uint8), vl3.view(np.uint8))
+        plan.destroy()
+    finally:
+        h.set_option("force_path", "auto")
