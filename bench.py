@@ -119,19 +119,20 @@ def cpu_baseline(A, B, sr, p, target_s):
             "sample": f"{k} rows drawn uniformly (seed 3) of the same product, {prods} products, {dt:.2f} s"}
 
 
-def parity_sample(A, B, sr, p, C, per_bin=12):
+def parity_sample(A, B, sr, p, C, per_bin=12, rows=None):
     """Rows of the timed result against the oracle: a stratified sample over
-    product-count decades (exact semirings bit for bit; float sums: the gated
-    tolerance and plain max / median relative error)."""
+    product-count decades, or the given rows (exact semirings bit for bit;
+    float sums: the gated tolerance and plain max / median relative error)."""
     import torch
     import oracle
     import synth
-    rows = []
-    edges = [1, 64, 4096, 65536, 1 << 20, 1 << 62]
-    for lo, hi in zip(edges[:-1], edges[1:]):
-        cand = np.nonzero((p >= lo) & (p < hi))[0]
-        if len(cand):
-            rows.extend(cand[synth.select(len(cand), min(per_bin, len(cand)), lo)].tolist())
+    if rows is None:
+        rows = []
+        edges = [1, 64, 4096, 65536, 1 << 20, 1 << 62]
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            cand = np.nonzero((p >= lo) & (p < hi))[0]
+            if len(cand):
+                rows.extend(cand[synth.select(len(cand), min(per_bin, len(cand)), lo)].tolist())
     rows = np.sort(np.array(rows, dtype=np.int64))
     rp = C.rowptr.cpu().numpy()
     idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
@@ -239,6 +240,128 @@ def summa_leg(sg, torch, h, scale, steps):
             "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3)}
 
 
+def three_hop_leg(sg, torch, h, A, dA, steps):
+    """(min,+) 3-hop on a seeded panel S of 4096 non-empty rows of the s20
+    graph: X1 = A[S,:].A, X2 = X1.A (rows S of (A.A).A).  Timed as the two
+    products back to back; X2 rows sampled against the oracle bit for bit."""
+    import oracle
+    import synth
+    nonempty = np.nonzero(np.diff(A.rowptr) > 0)[0]
+    S = nonempty[synth.select(len(nonempty), min(4096, len(nonempty)), 9)]
+    AS = synth.take_rows(A, S)
+    dAS = sg.DeviceCSR.from_host(AS)
+    sr = sg.semiring(sg.MIN_PLUS_F32)
+
+    def run():
+        X1 = h.spgemm(sr, dAS, dA)
+        X2 = h.spgemm(sr, X1, dA)
+        return X1, X2
+
+    X1, X2 = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        del X1, X2
+        X1, X2 = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    h.check()
+    deg = dA.rowptr[1:] - dA.rowptr[:-1]
+    p1 = int(np.diff(A.rowptr)[AS.col].sum())
+    p2 = int(deg[X1.col.long()].sum().item())
+    orc = oracle.get()
+    r1 = orc.spgemm(5, AS, A)
+    X1h = synth.CSR(AS.nrows, A.ncols, r1.rowptr, r1.col, r1.val)
+    x1n = X1.to_numpy()
+    rows = np.sort(synth.select(AS.nrows, 24, 10))
+    p_x1 = np.zeros(X1h.nrows, np.int64)
+    par = parity_sample(X1h, A, 5, p_x1 + 1, X2, per_bin=0, rows=rows)
+    out = {"workload": "R-MAT s20 (min,+) 3-hop panel: X1 = A[S,:].A, X2 = X1.A, |S| = 4096 seeded non-empty rows",
+           "products": p1 + p2, "nnz_X1": int(X1.nnz), "nnz_X2": int(X2.nnz), "ms": round(ms, 3),
+           "value": (p1 + p2) / (ms * 1e-3), "unit": "semiring products/s",
+           "X1_equal_oracle": bool(np.array_equal(x1n[0], r1.rowptr) and np.array_equal(x1n[1], r1.col)
+                                   and np.array_equal(x1n[2].view(np.uint32), r1.val.view(np.uint32))),
+           "X2_parity_sample": par}
+    del X1, X2, dAS
+    return out
+
+
+def precision_leg(sg, torch, h, scale):
+    """(+,x) with N(0,1) values on the s20 pattern: fp32 storage with the
+    default (compensated by rule) and plain fp32 accumulation, and a plain
+    fp64 run on the same values, each against the fp64 oracle on stratified
+    rows (max / median relative error, gated tolerance)."""
+    import synth
+    A = synth.rmat(scale, 16, seed=1)
+    v32 = synth.values(synth.VAL_F32_NORMAL, A.nnz, 0, 1, 2)
+    A32 = A.with_values(v32)
+    A64 = A.with_values(v32.astype(np.float64))
+    p = products_per_row(A, A)
+    out = {"workload": f"R-MAT s{scale}, values N(0,1) stored in fp32, (+,x) C = A.A", "products": int(p.sum())}
+    for name, M, sid, acc in (("fp32_compensated", A32, 2, sg.ACC_DEFAULT), ("fp32_plain", A32, 2, sg.ACC_PLAIN),
+                              ("fp64_plain", A64, 3, 0)):
+        dM = sg.DeviceCSR.from_host(M)
+        sr = sg.semiring(sid, acc)
+        C = h.spgemm(sr, dM, dM)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        del C
+        C = h.spgemm(sr, dM, dM)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        h.check()
+        res = parity_sample(M, M, sid, p, C)
+        res["ms"] = round(ms, 3)
+        res["value"] = int(p.sum()) / (ms * 1e-3)
+        out[name] = res
+        del C, dM
+        torch.cuda.empty_cache()
+    return out
+
+
+def er_batch_leg(sg, torch, h, count, steps):
+    """A batch of ER products (fp64 (+,x)): per instance n log-uniform in
+    [1k, 64k], d uniform in {4..32} for A and B; one batched plan (graph
+    replays) against a per-call loop."""
+    import synth
+    n, d = synth.batch_params(count, 1024, 65536, 4, 32, 5)
+    As, Bs, prods = [], [], 0
+    for i in range(count):
+        a = synth.er(int(n[i]), int(n[i]), int(d[i]), 1000 + 2 * i)
+        b = synth.er(int(n[i]), int(n[i]), int(d[i]), 1001 + 2 * i)
+        a = a.with_values(synth.values(synth.VAL_F64_UNIFORM, a.nnz, 0, 1, 3000 + 2 * i))
+        b = b.with_values(synth.values(synth.VAL_F64_UNIFORM, b.nnz, 0, 1, 3001 + 2 * i))
+        prods += int(np.diff(b.rowptr)[a.col].sum())
+        As.append(sg.DeviceCSR.from_host(a))
+        Bs.append(sg.DeviceCSR.from_host(b))
+    sr = sg.semiring(sg.PLUS_TIMES_F64)
+
+    def per_call():
+        return [h.spgemm(sr, a, b) for a, b in zip(As, Bs)]
+
+    per_call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per_call()
+    torch.cuda.synchronize()
+    ms_pc = (time.perf_counter() - t0) * 1e3 / steps
+    torch.cuda.empty_cache()
+    plan = h.batch_plan(sr, As, Bs)
+    plan.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute()
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3 / steps
+    plan.results()
+    plan.destroy()
+    return {"workload": f"{count} ER fp64 (+,x) products, n log-uniform in [1k, 64k], d in {{4..32}}",
+            "products": prods, "ms_per_call_path": round(ms_pc, 3), "ms_batched": round(ms_b, 3),
+            "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +373,9 @@ def main():
     ap.add_argument("--hash-max", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched legs")
     ap.add_argument("--summa-scale", type=int, default=18, help="R-MAT scale of the 8x8 SUMMA leg (0: skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3-hop, precision and ER-batch legs")
+    ap.add_argument("--er-batch", type=int, default=256, help="ER products in the batch leg (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB copy kernel (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -369,6 +495,16 @@ def main():
         out["batched"] = batched_leg(sg, torch, h, sr, dA, dB, P, args.steps, ms)
         if args.summa_scale > 0:
             out["summa"] = summa_leg(sg, torch, h, args.summa_scale, args.steps)
+    if not args.no_extra and args.workload == "rmat20_minplus":
+        t_x = time.perf_counter()
+        out["three_hop"] = three_hop_leg(sg, torch, h, A, dA, args.steps)
+        torch.cuda.empty_cache()
+        out["precision"] = precision_leg(sg, torch, h, 20)
+        torch.cuda.empty_cache()
+        if args.er_batch > 0:
+            out["er_batch"] = er_batch_leg(sg, torch, h, args.er_batch, args.steps)
+            torch.cuda.empty_cache()
+        print(f"# extra legs in {time.perf_counter() - t_x:.1f}s", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         n = 1 << 27
         src = torch.ones(n, dtype=torch.int32, device=dev)
