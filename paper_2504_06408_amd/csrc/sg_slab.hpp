@@ -364,14 +364,36 @@ SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_va
   return total;
 }
 
+// Partition elements are loaded as one integer of their size; pin_loaded
+// makes the whole integer live at that point, so that the compiler cannot
+// split the load and defer its value half behind a branch on the column.
+template <int N> struct RawBits;
+template <> struct RawBits<4> { using T = unsigned int; };
+template <> struct RawBits<8> { using T = unsigned long long; };
+template <> struct RawBits<16> { typedef unsigned int T __attribute__((ext_vector_type(4))); };
+
+template <class T>
+SG_DEV void pin_loaded(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
 // One block of 64*U consecutive products [qb, qb + 64*U) of a chunk: lane
-// l takes q = qb + u*64 + l (u < U), so every load
-// instruction is coalesced; owners are found by a search narrowed to the
-// block's first and last owner.  fetch(owner, index into the partition) returns
-// a product; ok[u] tells which pp[u] hold one.
-template <int BS, int U, class V, class Fetch, class P>
-SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, Fetch& fetch, P* pp, bool* ok) {
+// l takes q = qb + u*64 + l (u < U), so every load instruction is
+// coalesced; owners are found by a search narrowed to the block's first and
+// last owner.  The round runs in three sweeps so that its U loads are in
+// flight together: all owner searches (LDS only), then the U loads of src
+// (lanes past the chunk's end re-load the block's first product, which always
+// exists), then fetch(owner, loaded element) makes each product.  ok[u]
+// tells which pp[u] hold one.
+template <int BS, int U, class V, class R, class Fetch, class P>
+SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch,
+                       P* pp, bool* ok) {
   constexpr int64_t kBlock = (int64_t)kWave * U;
+  if (qb >= total) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) ok[u] = false;
+    return;
+  }
   const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
   int a = 0, bb = nc - 1;
   while (a < bb) {
@@ -385,11 +407,16 @@ SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb
     if (L.off[mid] <= qe) e = mid;
     else f = mid - 1;
   }
+  const int64_t idx0 = L.st[a] + (qb - L.off[a]);
+  int own[U];
+  int64_t idx[U];
   int ow = a;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int64_t q = qb + u * kWave + lane_id();
     ok[u] = q < total;
+    own[u] = a;
+    idx[u] = idx0;
     if (ok[u]) {
       int h2 = e;
       while (ow < h2) {
@@ -397,22 +424,32 @@ SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb
         if (L.off[mid] <= q) ow = mid;
         else h2 = mid - 1;
       }
-      pp[u] = fetch(ow, L.st[ow] + (q - L.off[ow]));
+      own[u] = ow;
+      idx[u] = L.st[ow] + (q - L.off[ow]);
     }
   }
+  using Bits = typename RawBits<sizeof(R)>::T;
+  const Bits* bsrc = reinterpret_cast<const Bits*>(src);
+  Bits raw[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) raw[u] = bsrc[idx[u]];
+#pragma unroll
+  for (int u = 0; u < U; ++u) pin_loaded(raw[u]);
+#pragma unroll
+  for (int u = 0; u < U; ++u) pp[u] = fetch(own[u], __builtin_bit_cast(R, raw[u]));
 }
 
 // Flattened walk over the chunk's `total` products: wavefront w takes the
 // blocks w, w + NW, ... and folds each product with apply(product).
-template <int BS, int U, class V, class Fetch, class Apply>
-SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, Fetch& fetch, Apply& apply) {
+template <int BS, int U, class V, class R, class Fetch, class Apply>
+SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, const R* src, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
   constexpr int64_t kBlock = (int64_t)kWave * U;
-  using P = decltype(fetch(0, (int64_t)0));
+  using P = decltype(fetch(0, src[0]));
   for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
     P pp[U];
     bool ok[U];
-    slab_round<BS, U, V>(L, nc, total, qb, fetch, pp, ok);
+    slab_round<BS, U, V>(L, nc, total, qb, src, fetch, pp, ok);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) apply(pp[u]);
@@ -421,19 +458,19 @@ SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, Fetch& f
 
 // All products of a window of task (a0, nsrc, s, tr0, tr1): chunk by chunk
 // unless the caller already loaded the single chunk (`loaded`, total).
-template <int BS, int U, class V, bool kVals, class Fetch, class Apply>
+template <int BS, int U, class V, bool kVals, class R, class Fetch, class Apply>
 SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
                           int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int64_t total,
-                          SrcLds<V, BS>& L, Fetch& fetch, Apply& apply) {
+                          SrcLds<V, BS>& L, const R* src, Fetch& fetch, Apply& apply) {
   if (loaded) {
-    slab_iterate<BS, U, V>(L, nsrc, total, fetch, apply);
+    slab_iterate<BS, U, V>(L, nsrc, total, src, fetch, apply);
     return;
   }
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
     const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
     __syncthreads();
     const int64_t tc = slab_chunk<V, kVals, BS>(b, a_col, a_val, a0, s, tr0, tr1, whole, c0, nc, L);
-    slab_iterate<BS, U, V>(L, nc, tc, fetch, apply);
+    slab_iterate<BS, U, V>(L, nc, tc, src, fetch, apply);
   }
 }
 
@@ -462,11 +499,12 @@ __global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRo
     const DenseRow d = dr[h];
     const int ts0 = s * G;
     const int64_t c0 = (int64_t)ts0 << kTileLog;
-    auto fetch = [&](int, int64_t idx) { return (int32_t)(b.pcol[idx] - c0); };
+    auto fetch = [&](int, int32_t c) { return (int32_t)(c - c0); };
     auto apply = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bm[c >> 5], 1u << (c & 31));
     };
-    slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, L, fetch, apply);
+    slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, L, b.pcol, fetch,
+                                              apply);
     __syncthreads();
     int32_t* o2 = off2 + h * (T + 1);
     for (int tl = wave_id(); tl < G; tl += NW) {
@@ -524,14 +562,11 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     // With one round of products per wavefront the products stay in
     // registers for pass 2; otherwise pass 2 gathers them again.
     const bool held = one && total <= (int64_t)NW * kWave * kSlabU;
-    auto f1 = [&](int, int64_t idx) { return (int32_t)(b.pcv[idx].c - cw0); };
+    auto f1 = [&](int, const ColV<V>& e) { return (int32_t)(e.c - cw0); };
     auto a1 = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
     };
-    auto f2 = [&](int ow, int64_t idx) {
-      const ColV<V> e = b.pcv[idx];
-        return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)};
-    };
+    auto f2 = [&](int ow, const ColV<V>& e) { return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)}; };
     auto a2 = [&](const ColVal<Acc>& p) {
       if ((uint32_t)p.c >= cmax) return;
       const int w = p.c >> 5;
@@ -542,12 +577,13 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     bool ok[kSlabU];
     // pass 1: the window's column set
     if (held) {
-      slab_round<BS, kSlabU, V>(L, tk.nsrc, total, (int64_t)wv * kWave * kSlabU, f2, pp, ok);
+      slab_round<BS, kSlabU, V>(L, tk.nsrc, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
 #pragma unroll
       for (int u = 0; u < kSlabU; ++u)
         if (ok[u]) a1(pp[u].c);
     } else {
-      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f1, a1);
+      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, b.pcv, f1,
+                                         a1);
     }
     __syncthreads();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
@@ -582,7 +618,8 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       for (int u = 0; u < kSlabU; ++u)
         if (ok[u]) a2(pp[u]);
     } else {
-      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, f2, a2);
+      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, b.pcv, f2,
+                                         a2);
     }
     __syncthreads();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
@@ -609,15 +646,18 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
 // array): the row's sources are loaded once (A value, column, slab segment
 // start), then each non-empty tile of the slab is folded in one pass into a
 // dense 16384-slot LDS accumulator and compacted in column order; per tile a
-// source only re-reads its two tile offsets.  Touched slots are reset to the
-// identity as they are written out; for semirings whose identity no product
+// source only re-reads its two tile offsets.  Slots are reset to the
+// identity as they are compacted; for semirings whose identity no product
 // reaches (kValueMarks) occupancy is read off the accumulator, otherwise an
-// occupancy bitmap is kept.
+// occupancy bitmap is kept.  8-byte accumulators fill 128 KB of LDS: one
+// workgroup per CU.
 template <class Sr, class V, int BS>
-__global__ __launch_bounds__(BS, 4) void k_num_slab_heavy(SlabB<V> b, const int32_t* a_col, const V* a_val,
-                                                       const int32_t* off2, OutC C, const SlabTask* tasks,
-                                                       const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
+__global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_num_slab_heavy(
+    SlabB<V> b, const int32_t* a_col, const V* a_val, const int32_t* off2, OutC C, const SlabTask* tasks,
+    const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
+  constexpr int kSpan = kTile / NW;  // accumulator slots compacted per wavefront
+  static_assert(kSpan % kWave == 0, "whole steps of 64 slots per wavefront");
   using Acc = typename Sr::Acc;
   __shared__ Acc s_acc[kTile];
   __shared__ uint32_t s_bm[Sr::kValueMarks ? 1 : kTileWords];
@@ -625,6 +665,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab_heavy(SlabB<V> b, const int3
   __shared__ int32_t s_wave32[NW];
   __shared__ int32_t s_tc[kSlabTilesMax + 1];
   const int T = b.T, G = b.G;
+  const int wv = wave_id();
   for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
   if constexpr (!Sr::kValueMarks)
     for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
@@ -662,10 +703,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab_heavy(SlabB<V> b, const int3
       const int32_t rel = s_tc[t - ts0], mt = s_tc[t + 1 - ts0] - rel;
       if (mt <= 0) continue;
       const int64_t cw0 = (int64_t)t << kTileLog;
-      auto f = [&](int ow, int64_t idx) {
-        const ColV<V> e = b.pcv[idx];
-        return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)};
-      };
+      auto f = [&](int ow, const ColV<V>& e) { return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)}; };
       auto ap = [&](const ColVal<Acc>& p) {
         if ((uint32_t)p.c >= (uint32_t)kTile) return;
         Sr::lds_acc(&s_acc[p.c], p.v);
@@ -689,58 +727,56 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab_heavy(SlabB<V> b, const int3
         L.st[threadIdx.x] = st;
         L.off[threadIdx.x] = off;
         __syncthreads();
-        slab_iterate<BS, kSlabU, V>(L, tk.nsrc, total, f, ap);
+        slab_iterate<BS, kSlabU, V>(L, tk.nsrc, total, b.pcv, f, ap);
       } else {
         slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false, false,
-                                           0, L, f, ap);
+                                           0, L, b.pcv, f, ap);
       }
       __syncthreads();
-      // compaction: consecutive threads on consecutive words; up to four
-      // accumulators are read per wait
-      int32_t carry = 0;
-      for (int w0 = 0; w0 < kTileWords; w0 += BS) {
-        const int w = w0 + threadIdx.x;
-        uint32_t bits = 0u;
-        if (w < kTileWords) {
-          if constexpr (Sr::kValueMarks) {
-#pragma unroll
-            for (int j = 0; j < 32; ++j) bits |= (s_acc[w * 32 + j] != Sr::ident() ? 1u : 0u) << j;
-          } else {
-            bits = s_bm[w];
-          }
-        }
-        int32_t tot;
-        int32_t r = carry + block_excl_scan<NW, int32_t>(__popc(bits), s_wave32, &tot);
-        const int64_t out = tk.out + rel;
-        while (bits) {
-          int c[4];
-          Acc v[4];
-          int n = 0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (bits) {
-              const int bt = __ffs((int)bits) - 1;
-              bits &= bits - 1u;
-              c[j] = w * 32 + bt;
-              v[j] = s_acc[c[j]];
-              n = j + 1;
-            }
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (j < n) {
-              if (r < mt) {
-                C.col[out + r] = (int32_t)(cw0 + c[j]);
-                ((V*)C.val)[out + r] = Sr::out(v[j]);
-              }
-              s_acc[c[j]] = Sr::ident();
-              ++r;
-            }
-        }
-        if constexpr (!Sr::kValueMarks)
-          if (w < kTileWords) s_bm[w] = 0u;
-        carry += tot;
+      // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and
+      // reads 64 consecutive slots per step (no bank conflicts); a ballot of
+      // the occupied slots gives each lane its output rank, so the stores of
+      // a step are contiguous.  Slots are reset as they are read.
+      const int sb = wv * kSpan;
+      int32_t cnt;
+      if constexpr (Sr::kValueMarks) {
+        cnt = 0;
+#pragma unroll 8
+        for (int j = 0; j < kSpan; j += kWave)
+          cnt += __popcll(__ballot(s_acc[sb + j + lane_id()] != Sr::ident()));
+      } else {
+        static_assert(kSpan == 32 * kWave, "one bitmap word per lane");
+        cnt = wave_sum((int32_t)__popc(s_bm[(sb >> 5) + lane_id()]));
       }
-      if (threadIdx.x == 0 && carry != mt) atomicOr(err, 1);
+      if (lane_id() == 0) s_wave32[wv] = cnt;
+      __syncthreads();
+      int32_t base = 0, tot = 0;
+#pragma unroll
+      for (int u = 0; u < NW; ++u) {
+        const int32_t v = s_wave32[u];
+        base += u < wv ? v : 0;
+        tot += v;
+      }
+      const int64_t out = tk.out + rel;
+      const unsigned long long below = lanes_below();
+#pragma unroll 4
+      for (int j = 0; j < kSpan; j += kWave) {
+        const int x = sb + j + lane_id();
+        const Acc v = s_acc[x];
+        bool occ;
+        if constexpr (Sr::kValueMarks) occ = v != Sr::ident();
+        else occ = (s_bm[x >> 5] >> (x & 31)) & 1u;
+        const unsigned long long mk = __ballot(occ);
+        const int32_t r = base + (int32_t)__popcll(mk & below);
+        if (occ && r < mt) {
+          C.col[out + r] = (int32_t)(cw0 + x);
+          ((V*)C.val)[out + r] = Sr::out(v);
+        }
+        s_acc[x] = Sr::ident();
+        base += (int32_t)__popcll(mk);
+      }
+      if constexpr (!Sr::kValueMarks) s_bm[(sb >> 5) + lane_id()] = 0u;
+      if (threadIdx.x == 0 && tot != mt) atomicOr(err, 1);
       __syncthreads();
     }
   });
