@@ -28,23 +28,57 @@ SG_DEV T shfl(T v, int src) {
   return __shfl(v, src, kWave);
 }
 
-// Inclusive prefix sum over the 64 lanes of a wavefront.
+// x of the lane that the DPP control kCtrl selects (within the rows enabled
+// by kRowMask); lanes with no source lane, or in a disabled row, get 0.
+// 8-byte values move as two 32-bit halves from the same source lane.
+template <int kCtrl, int kRowMask, bool kBoundZero, class T>
+SG_DEV T dpp_from(T x) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte lane values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, kRowMask, 0xf, kBoundZero));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, kCtrl, kRowMask, 0xf, kBoundZero);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), kCtrl, kRowMask, 0xf, kBoundZero);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront, in registers: shifts
+// by 1, 2, 4, 8 lanes inside each row of 16 (row_shr), then the last lane of
+// row 0 and 2 is added to rows 1 and 3 (row_bcast:15) and the last lane of
+// row 1 to rows 2 and 3 (row_bcast:31).  Every lane must be active.
 template <class T>
 SG_DEV T wave_incl_scan(T v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T u = __shfl_up(v, (unsigned)d, kWave);
-    if (l >= d) v += u;
-  }
+  v += dpp_from<0x111, 0xf, true>(v);
+  v += dpp_from<0x112, 0xf, true>(v);
+  v += dpp_from<0x114, 0xf, true>(v);
+  v += dpp_from<0x118, 0xf, true>(v);
+  v += dpp_from<0x142, 0xa, false>(v);
+  v += dpp_from<0x143, 0xc, false>(v);
   return v;
 }
 
+// The value that lane l holds, in every lane.
+template <class T>
+SG_DEV T lane_value(T x, int l) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte lane values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+// Sum over the 64 lanes, in every lane.  Every lane must be active.
 template <class T>
 SG_DEV T wave_sum(T v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+  return lane_value(wave_incl_scan(v), kWave - 1);
 }
 
 template <class T>
@@ -86,25 +120,6 @@ SG_DEV T block_sum(T v, T* s_wave) {
 }
 
 SG_DEV int ceil_log2_u64(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll((long long)(x - 1)); }
-
-// Sets bit (c & 31) of bm[c >> 5] for every lane with `valid`.  Lanes of a
-// wavefront that hold the same word are combined first by a segmented OR scan
-// (lanes walking one sorted segment mostly share words), so one lane per run
-// of equal words issues the LDS atomic instead of up to 32 colliding ones.
-// Every lane of the wavefront must call it.
-SG_DEV void wave_or_bits(uint32_t* bm, int32_t c, bool valid) {
-  const int l = lane_id();
-  const int32_t w = valid ? (c >> 5) : -1 - l;
-  uint32_t m = valid ? (1u << (c & 31)) : 0u;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t wo = __shfl_up(w, (unsigned)d, kWave);
-    const uint32_t mo = __shfl_up(m, (unsigned)d, kWave);
-    if (l >= d && wo == w) m |= mo;
-  }
-  const int32_t wn = __shfl_down(w, 1u, kWave);
-  if (valid && (l == kWave - 1 || wn != w)) atomicOr(&bm[w], m);
-}
 
 // ---------------------------------------------------------------------------
 // LDS hash of int32 column ids, linear probing, power-of-two size 2^lgS.

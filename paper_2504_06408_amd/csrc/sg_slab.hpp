@@ -759,21 +759,28 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
       }
       const int64_t out = tk.out + rel;
       const unsigned long long below = lanes_below();
-#pragma unroll 4
-      for (int j = 0; j < kSpan; j += kWave) {
-        const int x = sb + j + lane_id();
-        const Acc v = s_acc[x];
-        bool occ;
-        if constexpr (Sr::kValueMarks) occ = v != Sr::ident();
-        else occ = (s_bm[x >> 5] >> (x & 31)) & 1u;
-        const unsigned long long mk = __ballot(occ);
-        const int32_t r = base + (int32_t)__popcll(mk & below);
-        if (occ && r < mt) {
-          C.col[out + r] = (int32_t)(cw0 + x);
-          ((V*)C.val)[out + r] = Sr::out(v);
+      // kBatch steps per group: their slots are read before any is reset
+      constexpr int kBatch = 8;
+      static_assert(kSpan % (kBatch * kWave) == 0, "whole groups of steps");
+      for (int j0 = 0; j0 < kSpan; j0 += kBatch * kWave) {
+        Acc v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = s_acc[sb + j0 + k * kWave + lane_id()];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+          const int x = sb + j0 + k * kWave + lane_id();
+          bool occ;
+          if constexpr (Sr::kValueMarks) occ = v[k] != Sr::ident();
+          else occ = (s_bm[x >> 5] >> (x & 31)) & 1u;
+          const unsigned long long mk = __ballot(occ);
+          const int32_t r = base + (int32_t)__popcll(mk & below);
+          if (occ && r < mt) {
+            C.col[out + r] = (int32_t)(cw0 + x);
+            ((V*)C.val)[out + r] = Sr::out(v[k]);
+          }
+          s_acc[x] = Sr::ident();
+          base += (int32_t)__popcll(mk);
         }
-        s_acc[x] = Sr::ident();
-        base += (int32_t)__popcll(mk);
       }
       if constexpr (!Sr::kValueMarks) s_bm[(sb >> 5) + lane_id()] = 0u;
       if (threadIdx.x == 0 && tot != mt) atomicOr(err, 1);
