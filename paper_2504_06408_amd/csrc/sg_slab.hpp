@@ -311,12 +311,15 @@ constexpr int kBoffCache = 256;  // bucket offsets kept in LDS
 
 // LDS of one chunk of a task's sources: the A value, the start of the
 // source's window segment in the partition, and the exclusive prefix of the
-// segment lengths.
+// segment lengths, for the sources whose segment is not empty (slots).
+constexpr int kRoundRowsMax = 8;  // rows of 64 products in one gather round
+
 template <class V, int BS>
 struct SrcLds {
   V a[BS];
   int64_t st[BS], off[BS], wave[BS / kWave];
   int32_t boff[kBoffCache + 1];
+  uint32_t rb[BS / kWave][2 * kRoundRowsMax];  // per wavefront: slot starts inside its round
   int64_t slot;
 };
 
@@ -333,18 +336,43 @@ SG_DEV SlabTask bucket_slab_task(const SlabTask* tasks, const int32_t* boff, con
   return tasks[(int64_t)lo * nd + (g - (bcache ? L.boff[lo] : boff[lo]))];
 }
 
+// Block scan of the sources' segment lengths (one source per thread) that
+// keeps only the sources with a non-empty segment: such a source goes to
+// slot pos = number of non-empty sources before it, with its segment start,
+// its first product's index and (kVals) its A value.  Slot offsets strictly
+// increase, so the owner of product q is the last slot whose offset is at
+// most q.  Lengths and flags share one 64-bit scan (flags in the low 16
+// bits).  Returns the product count; *n receives the slot count.
+template <class V, bool kVals, int BS>
+SG_DEV int64_t src_compact(SrcLds<V, BS>& L, int64_t st, int64_t len, V av, int* n) {
+  static_assert(BS < (1 << 16), "slot counts fit the low 16 bits");
+  const int64_t pk = (len << 16) | (len > 0 ? 1 : 0);
+  int64_t tot;
+  const int64_t ex = block_excl_scan<BS / kWave, int64_t>(pk, L.wave, &tot);
+  if (len > 0) {
+    const int pos = (int)(ex & 0xffff);
+    L.st[pos] = st;
+    L.off[pos] = ex >> 16;
+    if constexpr (kVals) L.a[pos] = av;
+  }
+  __syncthreads();
+  *n = (int)(tot & 0xffff);
+  return tot >> 16;
+}
+
 // Sources [c0, c0 + nc) of the row starting at A entry a0, restricted to
 // tiles [s*G + tr0, s*G + tr1) of slab s (whole: the full slab segment, from
-// prow alone; otherwise prow + the tile offsets rpt), one per thread, then a
-// block scan of the segment lengths.  Returns the chunk's product count.
+// prow alone; otherwise prow + the tile offsets rpt), one per thread,
+// compacted into slots.  Returns the chunk's product count; *n the slots.
 template <class V, bool kVals, int BS>
 SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t s,
-                          int32_t tr0, int32_t tr1, bool whole, int64_t c0, int nc, SrcLds<V, BS>& L) {
+                          int32_t tr0, int32_t tr1, bool whole, int64_t c0, int nc, SrcLds<V, BS>& L, int* n) {
   int64_t st = 0, len = 0;
+  V av{};
   if ((int)threadIdx.x < nc) {
     const int64_t e = a0 + c0 + threadIdx.x;
     const int32_t k = a_col[e];
-    if constexpr (kVals) L.a[threadIdx.x] = a_val[e];
+    if constexpr (kVals) av = a_val[e];
     const int64_t* pr = b.prow + (int64_t)s * b.nb + k;
     st = pr[0];
     if (whole) {
@@ -356,12 +384,7 @@ SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_va
       len = r[tr1] - w0;
     }
   }
-  int64_t total;
-  const int64_t off = block_excl_scan<BS / kWave, int64_t>(len, L.wave, &total);
-  L.st[threadIdx.x] = st;
-  L.off[threadIdx.x] = off;
-  __syncthreads();
-  return total;
+  return src_compact<V, kVals, BS>(L, st, len, av, n);
 }
 
 // Partition elements are loaded as one integer of their size; pin_loaded
@@ -377,57 +400,68 @@ SG_DEV void pin_loaded(T& v) {
   asm volatile("" : "+v"(v));
 }
 
-// One block of 64*U consecutive products [qb, qb + 64*U) of a chunk: lane
-// l takes q = qb + u*64 + l (u < U), so every load instruction is
-// coalesced; owners are found by a search narrowed to the block's first and
-// last owner.  The round runs in three sweeps so that its U loads are in
-// flight together: all owner searches (LDS only), then the U loads of src
-// (lanes past the chunk's end re-load the block's first product, which always
-// exists), then fetch(owner, loaded element) makes each product.  ok[u]
-// tells which pp[u] hold one.
+// One block of 64*U consecutive products [qb, qb + 64*U) of a chunk's nc
+// slots: lane l takes q = qb + u*64 + l (u < U), so every load instruction
+// is coalesced.  Owners come without per-lane searches: the owner a of qb by
+// a 64-ary search (one LDS read per lane and level), then every later slot
+// that starts inside the block sets the bit of its start in the wavefront's
+// 64*U-bit mask, and q's owner is a plus the set bits at or below q - qb.
+// The round then issues its U loads of src together (lanes past the chunk's
+// end re-load the block's first product, which always exists) and
+// fetch(slot, loaded element) makes each product.  ok[u] tells which pp[u]
+// hold one.
 template <int BS, int U, class V, class R, class Fetch, class P>
-SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch,
-                       P* pp, bool* ok) {
+SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch, P* pp,
+                       bool* ok) {
+  static_assert(U <= kRoundRowsMax, "round mask rows");
+  static_assert(BS <= kWave * kWave, "two search levels cover the slots");
   constexpr int64_t kBlock = (int64_t)kWave * U;
   if (qb >= total) {
 #pragma unroll
     for (int u = 0; u < U; ++u) ok[u] = false;
     return;
   }
+  const int lane = lane_id();
   const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
-  int a = 0, bb = nc - 1;
-  while (a < bb) {
-    const int mid = (a + bb + 1) >> 1;
-    if (L.off[mid] <= qb) a = mid;
-    else bb = mid - 1;
+  int a;
+  {
+    const int stride = (nc + kWave - 1) / kWave;
+    const int i1 = lane * stride;
+    const int c1 = __popcll(__ballot(i1 < nc && L.off[i1] <= qb));
+    const int b2 = (c1 - 1) * stride, i2 = b2 + lane;
+    a = b2 + __popcll(__ballot(lane < stride && i2 < nc && L.off[i2] <= qb)) - 1;
   }
-  int e = a, f = nc - 1;
-  while (e < f) {
-    const int mid = (e + f + 1) >> 1;
-    if (L.off[mid] <= qe) e = mid;
-    else f = mid - 1;
+  uint32_t* rb = L.rb[wave_id()];
+  if (lane < 2 * U) rb[lane] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  for (int j0 = a + 1; j0 < nc; j0 += kWave) {
+    const int j = j0 + lane;
+    const int64_t o = j < nc ? L.off[j] : qe + 1;
+    const bool in = o <= qe;
+    if (in) {
+      const int p = (int)(o - qb);
+      atomicOr(&rb[p >> 5], 1u << (p & 31));
+    }
+    if (__ballot(in) != ~0ull) break;
   }
+  __builtin_amdgcn_wave_barrier();
+  unsigned long long w[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) w[u] = (unsigned long long)rb[2 * u] | ((unsigned long long)rb[2 * u + 1] << 32);
+  const unsigned long long incl = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
   const int64_t idx0 = L.st[a] + (qb - L.off[a]);
   int own[U];
   int64_t idx[U];
-  int ow = a;
+  int cnt = a;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int64_t q = qb + u * kWave + lane_id();
+    const int64_t q = qb + u * kWave + lane;
     ok[u] = q < total;
-    own[u] = a;
-    idx[u] = idx0;
-    if (ok[u]) {
-      int h2 = e;
-      while (ow < h2) {
-        const int mid = (ow + h2 + 1) >> 1;
-        if (L.off[mid] <= q) ow = mid;
-        else h2 = mid - 1;
-      }
-      own[u] = ow;
-      idx[u] = L.st[ow] + (q - L.off[ow]);
-    }
+    own[u] = cnt + __popcll(w[u] & incl);
+    cnt += __popcll(w[u]);
   }
+#pragma unroll
+  for (int u = 0; u < U; ++u) idx[u] = ok[u] ? L.st[own[u]] + (qb + u * kWave + lane - L.off[own[u]]) : idx0;
   using Bits = typename RawBits<sizeof(R)>::T;
   const Bits* bsrc = reinterpret_cast<const Bits*>(src);
   Bits raw[U];
@@ -442,7 +476,7 @@ SG_DEV void slab_round(const SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb
 // Flattened walk over the chunk's `total` products: wavefront w takes the
 // blocks w, w + NW, ... and folds each product with apply(product).
 template <int BS, int U, class V, class R, class Fetch, class Apply>
-SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, const R* src, Fetch& fetch, Apply& apply) {
+SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
   constexpr int64_t kBlock = (int64_t)kWave * U;
   using P = decltype(fetch(0, src[0]));
@@ -457,20 +491,22 @@ SG_DEV void slab_iterate(const SrcLds<V, BS>& L, int nc, int64_t total, const R*
 }
 
 // All products of a window of task (a0, nsrc, s, tr0, tr1): chunk by chunk
-// unless the caller already loaded the single chunk (`loaded`, total).
+// unless the caller already loaded the single chunk (`loaded`: nl slots,
+// total products).
 template <int BS, int U, class V, bool kVals, class R, class Fetch, class Apply>
 SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
-                          int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int64_t total,
+                          int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int nl, int64_t total,
                           SrcLds<V, BS>& L, const R* src, Fetch& fetch, Apply& apply) {
   if (loaded) {
-    slab_iterate<BS, U, V>(L, nsrc, total, src, fetch, apply);
+    slab_iterate<BS, U, V>(L, nl, total, src, fetch, apply);
     return;
   }
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
     const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
     __syncthreads();
-    const int64_t tc = slab_chunk<V, kVals, BS>(b, a_col, a_val, a0, s, tr0, tr1, whole, c0, nc, L);
-    slab_iterate<BS, U, V>(L, nc, tc, src, fetch, apply);
+    int ns;
+    const int64_t tc = slab_chunk<V, kVals, BS>(b, a_col, a_val, a0, s, tr0, tr1, whole, c0, nc, L, &ns);
+    slab_iterate<BS, U, V>(L, ns, tc, src, fetch, apply);
   }
 }
 
@@ -483,7 +519,7 @@ constexpr int kSlabU = 8;
 // interleaved queues.  The per-tile popcounts of the slab's bitmap are written
 // raw to off2[h*(T+1) + t]; k_off2_finish turns them into per-row offsets.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
+__global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
                                                  Bins bins, int32_t S, int32_t* off2, int32_t* ctr) {
   constexpr int NW = BS / kWave;
   __shared__ uint32_t s_bm[kSlabWordsMax];
@@ -503,8 +539,8 @@ __global__ __launch_bounds__(BS) void k_sym_slab(SlabB<uint8_t> b, const DenseRo
     auto apply = [&](int32_t c) {
       if ((uint32_t)c < cmax) atomicOr(&s_bm[c >> 5], 1u << (c & 31));
     };
-    slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, L, b.pcol, fetch,
-                                              apply);
+    slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pcol,
+                                              fetch, apply);
     __syncthreads();
     int32_t* o2 = off2 + h * (T + 1);
     for (int tl = wave_id(); tl < G; tl += NW) {
@@ -557,8 +593,9 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     const uint32_t cmax = (uint32_t)nwords * 32u;
     const bool one = tk.nsrc <= BS;
     int64_t total = 0;
+    int nl = 0;
     __syncthreads();
-    if (one) total = slab_chunk<V, true, BS>(b, a_col, a_val, tk.a0, tk.s, tr0, tr1, whole, 0, tk.nsrc, L);
+    if (one) total = slab_chunk<V, true, BS>(b, a_col, a_val, tk.a0, tk.s, tr0, tr1, whole, 0, tk.nsrc, L, &nl);
     // With one round of products per wavefront the products stay in
     // registers for pass 2; otherwise pass 2 gathers them again.
     const bool held = one && total <= (int64_t)NW * kWave * kSlabU;
@@ -577,13 +614,13 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
     bool ok[kSlabU];
     // pass 1: the window's column set
     if (held) {
-      slab_round<BS, kSlabU, V>(L, tk.nsrc, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
+      slab_round<BS, kSlabU, V>(L, nl, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
 #pragma unroll
       for (int u = 0; u < kSlabU; ++u)
         if (ok[u]) a1(pp[u].c);
     } else {
-      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, b.pcv, f1,
-                                         a1);
+      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L, b.pcv,
+                                         f1, a1);
     }
     __syncthreads();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
@@ -618,8 +655,8 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       for (int u = 0; u < kSlabU; ++u)
         if (ok[u]) a2(pp[u]);
     } else {
-      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, total, L, b.pcv, f2,
-                                         a2);
+      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L, b.pcv,
+                                         f2, a2);
     }
     __syncthreads();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
@@ -682,16 +719,18 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
       s_tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
     }
     // the row's sources: one per thread when one chunk holds them all, with
-    // the source's tile offsets kept in registers for every tile
+    // the A value and the source's tile offsets kept in registers for every
+    // tile; each tile compacts its non-empty segments into slots
     const bool one = tk.nsrc <= BS;
     int64_t sst = 0;
+    V av{};
     int32_t rec[kSlabTilesMax + 1];
 #pragma unroll
     for (int q = 0; q <= kSlabTilesMax; ++q) rec[q] = 0;
     if (one && (int)threadIdx.x < tk.nsrc) {
       const int64_t e = tk.a0 + threadIdx.x;
       const int32_t k = a_col[e];
-      L.a[threadIdx.x] = a_val[e];
+      av = a_val[e];
       sst = b.prow[(int64_t)tk.s * b.nb + k];
       const int32_t* r = b.rpt + ((int64_t)tk.s * b.nb + k) * (G + 1);
 #pragma unroll
@@ -722,15 +761,12 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
           st = sst + w0;
           len = w1 - w0;
         }
-        int64_t total;
-        const int64_t off = block_excl_scan<NW, int64_t>(len, L.wave, &total);
-        L.st[threadIdx.x] = st;
-        L.off[threadIdx.x] = off;
-        __syncthreads();
-        slab_iterate<BS, kSlabU, V>(L, tk.nsrc, total, b.pcv, f, ap);
+        int nl;
+        const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
+        slab_iterate<BS, kSlabU, V>(L, nl, total, b.pcv, f, ap);
       } else {
         slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false, false,
-                                           0, L, b.pcv, f, ap);
+                                           0, 0, L, b.pcv, f, ap);
       }
       __syncthreads();
       // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and
