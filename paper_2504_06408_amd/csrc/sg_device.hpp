@@ -61,6 +61,14 @@ SG_DEV T wave_incl_scan(T v) {
   return v;
 }
 
+// A block- or wavefront-uniform value read from the first active lane, so
+// the compiler can keep it (and addresses built on it) in scalar registers.
+SG_DEV int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // The value that lane l holds, in every lane.
 template <class T>
 SG_DEV T lane_value(T x, int l) {

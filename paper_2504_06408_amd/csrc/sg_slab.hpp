@@ -309,9 +309,10 @@ struct SlabB {
 
 constexpr int kBoffCache = 256;  // bucket offsets kept in LDS
 
-// LDS of one chunk of a task's sources: the A value, the start of the
-// source's window segment in the partition, and the exclusive prefix of the
-// segment lengths, for the sources whose segment is not empty (slots).
+// LDS of one chunk of a task's sources whose window segment is not empty
+// (slots): the A value, the exclusive prefix of the segment lengths (off,
+// the chunk index of the slot's first product) and the segment's start in
+// the partition minus off (st), so product q of slot j sits at st[j] + q.
 constexpr int kRoundRowsMax = 8;  // rows of 64 products in one gather round
 
 template <class V, int BS>
@@ -338,8 +339,9 @@ SG_DEV SlabTask bucket_slab_task(const SlabTask* tasks, const int32_t* boff, con
 
 // Block scan of the sources' segment lengths (one source per thread) that
 // keeps only the sources with a non-empty segment: such a source goes to
-// slot pos = number of non-empty sources before it, with its segment start,
-// its first product's index and (kVals) its A value.  Slot offsets strictly
+// slot pos = number of non-empty sources before it, with its first
+// product's index off and the partition index of product q of the slot,
+// minus q (st - off), and (kVals) its A value.  Slot offsets strictly
 // increase, so the owner of product q is the last slot whose offset is at
 // most q.  Lengths and flags share one 64-bit scan (flags in the low 16
 // bits).  Returns the product count; *n receives the slot count.
@@ -351,8 +353,8 @@ SG_DEV int64_t src_compact(SrcLds<V, BS>& L, int64_t st, int64_t len, V av, int*
   const int64_t ex = block_excl_scan<BS / kWave, int64_t>(pk, L.wave, &tot);
   if (len > 0) {
     const int pos = (int)(ex & 0xffff);
-    L.st[pos] = st;
     L.off[pos] = ex >> 16;
+    L.st[pos] = st - (ex >> 16);
     if constexpr (kVals) L.a[pos] = av;
   }
   __syncthreads();
@@ -449,7 +451,7 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
 #pragma unroll
   for (int u = 0; u < U; ++u) w[u] = (unsigned long long)rb[2 * u] | ((unsigned long long)rb[2 * u + 1] << 32);
   const unsigned long long incl = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
-  const int64_t idx0 = L.st[a] + (qb - L.off[a]);
+  const int64_t idx0 = L.st[a] + qb;
   int own[U];
   int64_t idx[U];
   int cnt = a;
@@ -461,7 +463,7 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
     cnt += __popcll(w[u]);
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) idx[u] = ok[u] ? L.st[own[u]] + (qb + u * kWave + lane - L.off[own[u]]) : idx0;
+  for (int u = 0; u < U; ++u) idx[u] = ok[u] ? L.st[own[u]] + (qb + u * kWave + lane) : idx0;
   using Bits = typename RawBits<sizeof(R)>::T;
   const Bits* bsrc = reinterpret_cast<const Bits*>(src);
   Bits raw[U];
@@ -793,8 +795,13 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         base += u < wv ? v : 0;
         tot += v;
       }
-      const int64_t out = tk.out + rel;
-      const unsigned long long below = lanes_below();
+      // output pointers of the wavefront's first entry: lanes store at 32-bit
+      // offsets from a uniform base
+      const int64_t o0 = uniform64(tk.out + rel + base);
+      char* colb = reinterpret_cast<char*>(C.col + o0);
+      char* valb = reinterpret_cast<char*>((V*)C.val + o0);
+      const uint32_t lim = (uint32_t)(mt - base);
+      uint32_t run = 0;
       // kBatch steps per group: their slots are read before any is reset
       constexpr int kBatch = 8;
       static_assert(kSpan % (kBatch * kWave) == 0, "whole groups of steps");
@@ -809,13 +816,14 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
           if constexpr (Sr::kValueMarks) occ = v[k] != Sr::ident();
           else occ = (s_bm[x >> 5] >> (x & 31)) & 1u;
           const unsigned long long mk = __ballot(occ);
-          const int32_t r = base + (int32_t)__popcll(mk & below);
-          if (occ && r < mt) {
-            C.col[out + r] = (int32_t)(cw0 + x);
-            ((V*)C.val)[out + r] = Sr::out(v[k]);
+          const uint32_t r =
+              run + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+          if (occ && r < lim) {
+            *reinterpret_cast<int32_t*>(colb + r * (uint32_t)sizeof(int32_t)) = (int32_t)(cw0 + x);
+            *reinterpret_cast<V*>(valb + r * (uint32_t)sizeof(V)) = Sr::out(v[k]);
           }
           s_acc[x] = Sr::ident();
-          base += (int32_t)__popcll(mk);
+          run += (uint32_t)__popcll(mk);
         }
       }
       if constexpr (!Sr::kValueMarks) s_bm[(sb >> 5) + lane_id()] = 0u;
