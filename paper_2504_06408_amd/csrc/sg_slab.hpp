@@ -452,18 +452,22 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
   for (int u = 0; u < U; ++u) w[u] = (unsigned long long)rb[2 * u] | ((unsigned long long)rb[2 * u + 1] << 32);
   const unsigned long long incl = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
   const int64_t idx0 = L.st[a] + qb;
+  // products of the block: lane's row u holds product qb + u*64 + lane
+  const int lim = (total - qb) < kBlock ? (int)(total - qb) : (int)kBlock;
   int own[U];
-  int64_t idx[U];
   int cnt = a;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int64_t q = qb + u * kWave + lane;
-    ok[u] = q < total;
+    ok[u] = u * kWave + lane < lim;
     own[u] = cnt + __popcll(w[u] & incl);
     cnt += __popcll(w[u]);
   }
+  // every row's owner is a valid slot, so the LDS reads need no branch
+  int64_t idx[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) idx[u] = ok[u] ? L.st[own[u]] + (qb + u * kWave + lane) : idx0;
+  for (int u = 0; u < U; ++u) idx[u] = L.st[own[u]];
+#pragma unroll
+  for (int u = 0; u < U; ++u) idx[u] = ok[u] ? idx[u] + qb + (u * kWave + lane) : idx0;
   using Bits = typename RawBits<sizeof(R)>::T;
   const Bits* bsrc = reinterpret_cast<const Bits*>(src);
   Bits raw[U];
