@@ -571,7 +571,8 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
                                                  const SlabTask* tasks, const int32_t* boff, int32_t nd,
                                                  int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
-  static_assert(NW * kWave <= kTileWords, "each wavefront owns a multiple of 64 words of a window");
+  static_assert(kTileWords % (NW * kWave) == 0, "each wavefront owns a multiple of 64 words of a window");
+  static_assert(kSlabWordsMax <= kSlabTilesMax * kWave * NW, "a lane owns at most kSlabTilesMax words");
   static_assert(CAP <= 65535, "ranks are 16-bit");
   using Acc = typename Sr::Acc;
   __shared__ uint32_t s_bits[kSlabWordsMax];
@@ -629,16 +630,20 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
                                          f1, a1);
     }
     __syncthreads();
-    // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lanes consecutive
-    int32_t run = 0;
-    for (int it = 0; it < wpw; it += kWave) {
-      const int w = wv * wpw + it + lane_id();
-      const int32_t pc = __popc(s_bits[w]);
-      const int32_t inc = wave_incl_scan(pc);
-      s_rank[w] = (uint16_t)(run + inc - pc);
-      run += shfl(inc, kWave - 1);
+    // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lane l the kpl
+    // consecutive words from wv*wpw + l*kpl; word popcounts stay in
+    // registers between the count and the rank pass
+    const int kpl = wpw / kWave;
+    const int w0 = wv * wpw + lane_id() * kpl;
+    int32_t pcw[kSlabTilesMax];
+    int32_t lt = 0;
+#pragma unroll
+    for (int i = 0; i < kSlabTilesMax; ++i) {
+      pcw[i] = i < kpl ? __popc(s_bits[w0 + i]) : 0;
+      lt += pcw[i];
     }
-    if (lane_id() == 0) s_wt[wv] = run;
+    const int32_t linc = wave_incl_scan(lt);
+    if (lane_id() == kWave - 1) s_wt[wv] = linc;
     for (int x = threadIdx.x; x < m; x += BS) s_val[x] = Sr::ident();
     __syncthreads();
     int32_t wbase = 0, tot = 0;
@@ -649,10 +654,12 @@ __global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_co
       tot += v;
     }
     if (threadIdx.x == 0 && tot != tk.m) atomicOr(err, 1);
-    if (wbase)
-      for (int it = 0; it < wpw; it += kWave) {
-        const int w = wv * wpw + it + lane_id();
-        s_rank[w] = (uint16_t)(s_rank[w] + wbase);
+    int32_t rk = wbase + linc - lt;
+#pragma unroll
+    for (int i = 0; i < kSlabTilesMax; ++i)
+      if (i < kpl) {
+        s_rank[w0 + i] = (uint16_t)rk;
+        rk += pcw[i];
       }
     __syncthreads();
     // pass 2: fold every product into its compacted slot
