@@ -308,45 +308,60 @@ template <int BS, int U, class Src, class Fetch, class Apply>
 SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s_item, int64_t* s_start,
                              int64_t* s_off, int64_t* s_wave, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
+  static_assert(BS < (1 << 16) && BS <= kWave * kWave, "slot counts in 16 bits; two search levels");
   using P = decltype(fetch(s_item[0], (int64_t)0));
+  const int lane = lane_id();
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
     const int64_t j = c0 + threadIdx.x;
     int64_t start = 0, len = 0;
     typename Src::Item it{};
     if (j < nsrc) src.load(j, it, start, len);
-    int64_t total;
-    const int64_t off = block_excl_scan<NW, int64_t>(len, s_wave, &total);
-    s_item[threadIdx.x] = it;
-    s_start[threadIdx.x] = start;
-    s_off[threadIdx.x] = off;
-    const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
+    // sources with an empty segment are dropped: one scan of (length, flag)
+    // pairs gives each non-empty source its slot and first product; a slot
+    // keeps its segment start minus that offset, so product q of slot k is
+    // element s_start[k] + q of its source
+    const int64_t pk = (len << 16) | (len > 0 ? 1 : 0);
+    int64_t tot;
+    const int64_t ex = block_excl_scan<NW, int64_t>(pk, s_wave, &tot);
+    if (len > 0) {
+      const int pos = (int)(ex & 0xffff);
+      s_item[pos] = it;
+      s_off[pos] = ex >> 16;
+      s_start[pos] = start - (ex >> 16);
+    }
+    const int nc = (int)(tot & 0xffff);
+    const int64_t total = tot >> 16;
     __syncthreads();
     // Wave w takes blocks of 64*U consecutive products; its lanes take
     // q = qb + u*64 + lane (u < U), so every load instruction is coalesced.
-    // The owners of the block's first and last product are found with
-    // searches at wave-uniform addresses (LDS broadcasts); each lane then
-    // searches only the sources in between, starting from its previous hit.
+    // The owners of the block's first and last product come from a 64-ary
+    // search (one LDS read per lane and level); each lane then searches
+    // only the slots in between, starting from its previous hit.  All
+    // searches come first, then all U fetches (their loads in flight
+    // together), then the applies.
     constexpr int64_t kBlock = (int64_t)kWave * U;
+    const int stride = (nc + kWave - 1) / kWave;
     for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
       const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
-      int a = 0, b = nc - 1;
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (s_off[mid] <= qb) a = mid;
-        else b = mid - 1;
+      int a, e;
+      {
+        const int i1 = lane * stride;
+        const int64_t o1 = i1 < nc ? s_off[i1] : INT64_MAX;
+        const int ca = __popcll(__ballot(o1 <= qb)), ce = __popcll(__ballot(o1 <= qe));
+        const int ba = (ca - 1) * stride, be = (ce - 1) * stride;
+        const int l2 = lane & 31;
+        const int i2 = (lane < 32 ? ba : be) + l2;
+        const int64_t o2 = (l2 < stride && i2 < nc) ? s_off[i2] : INT64_MAX;
+        const unsigned long long m2 = __ballot(o2 <= (lane < 32 ? qb : qe));
+        a = ba + __popc((uint32_t)m2) - 1;
+        e = be + __popc((uint32_t)(m2 >> 32)) - 1;
       }
-      int e = a, f = nc - 1;
-      while (e < f) {
-        const int mid = (e + f + 1) >> 1;
-        if (s_off[mid] <= qe) e = mid;
-        else f = mid - 1;
-      }
-      P p[U];
+      int own[U];
       bool ok[U];
       int lo = a;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t q = qb + u * kWave + lane_id();
+        const int64_t q = qb + u * kWave + lane;
         ok[u] = q < total;
         if (ok[u]) {
           int hi = e;
@@ -355,8 +370,17 @@ SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s
             if (s_off[mid] <= q) lo = mid;
             else hi = mid - 1;
           }
-          p[u] = fetch(s_item[lo], s_start[lo] + (q - s_off[lo]));
         }
+        own[u] = lo;
+      }
+      // lanes past the chunk's end fetch the block's first product, which
+      // always exists
+      P p[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = ok[u] ? own[u] : a;
+        const int64_t q = ok[u] ? qb + u * kWave + lane : qb;
+        p[u] = fetch(s_item[k], s_start[k] + q);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
