@@ -365,11 +365,18 @@ __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy
   int64_t p = 0;
   const bool heavy = nsrc > 32;
   if (!heavy) {
-    for (int64_t j = 0; j < nsrc; ++j) {
-      typename Src::Item it;
-      int64_t st, len;
-      s.load(j, it, st, len);
-      p += len;
+    // eight source loads in flight at a time (indices past the row's end
+    // re-load its last source and are not counted)
+    for (int64_t j0 = 0; j0 < nsrc; j0 += 8) {
+      int64_t lens[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        typename Src::Item it;
+        int64_t st;
+        s.load(j0 + u < nsrc ? j0 + u : nsrc - 1, it, st, lens[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p += j0 + u < nsrc ? lens[u] : 0;
     }
   }
   unsigned long long hmask = __ballot(heavy);

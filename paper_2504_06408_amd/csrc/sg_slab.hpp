@@ -108,37 +108,59 @@ __global__ __launch_bounds__(BS) void k_slab_counts(const int32_t* bnd, int64_t 
 
 // Scatter of B's entries into their slab segments.  Each lane takes one B
 // row (wavefront w: rows 64w .. 64w+63); rows with more than kScatterLane
-// entries are then walked by the whole wavefront, one after another.  With
-// kCols the column ids go to pcol and, if perm is given, each entry's
-// destination to perm (so later value scatters need no bounds); with kVals
-// the values go to pval.  Entries that do not fall where the bounds say
-// (unsorted or out-of-range columns) are dropped and flagged instead of
-// written out of place.
+// entries are then walked by the whole wavefront, one after another.  Entries
+// go kScatterU at a time per lane: their columns, then their slab bounds and
+// segment starts, are loaded together before any is stored.  With kCols the
+// column ids go to pcol and, if perm is given, each entry's destination to
+// perm (so later value scatters need no bounds); with kVals the values go to
+// pval.  Entries that do not fall where the bounds say (unsorted or
+// out-of-range columns) are dropped and flagged instead of written out of
+// place.
 constexpr int kScatterLane = 32;
+constexpr int kScatterU = 8;
 
+// Entries jb + u*step (u < kScatterU, those below e) of row k starting at s0,
+// whose row-local slab bounds are r[0..S].
 template <class V, bool kCols, bool kVals>
-SG_DEV void slab_scatter_entry(const int32_t* col, const V* val, int64_t nb, int32_t ls, int32_t S,
-                               const int32_t* r, const int64_t* prow, int64_t k, int64_t s0, int64_t j,
-                               int32_t* pcol, ColV<V>* pcv, int32_t* perm, int32_t* err) {
-  const int32_t c = col[j];
-  const int32_t s = c >> ls;
-  bool ok = c >= 0 && s < S;
-  int64_t dst = 0;
-  if (ok) {
-    const int64_t o = (j - s0) - r[s];
-    ok = o >= 0 && o < (int64_t)(r[s + 1] - r[s]);
-    dst = prow[(int64_t)s * nb + k] + o;
+SG_DEV void slab_scatter_entries(const int32_t* col, const V* val, int64_t nb, int32_t ls, int32_t S,
+                                 const int32_t* r, const int64_t* prow, int64_t k, int64_t s0, int64_t e, int64_t jb,
+                                 int step, int32_t* pcol, ColV<V>* pcv, int32_t* perm, int32_t* err) {
+  int32_t c[kScatterU];
+  V v[kScatterU];
+#pragma unroll
+  for (int u = 0; u < kScatterU; ++u) {
+    const int64_t j = jb + (int64_t)u * step < e ? jb + (int64_t)u * step : e - 1;
+    c[u] = col[j];
+    if constexpr (kVals) v[u] = val[j];
   }
-  if (!ok) {
-    atomicOr(err, 1);
-    if (perm) perm[j] = -1;
-    return;
+  int32_t lo[kScatterU], hi[kScatterU];
+  int64_t pb[kScatterU];
+#pragma unroll
+  for (int u = 0; u < kScatterU; ++u) {
+    int32_t sl = c[u] >> ls;
+    sl = sl < 0 ? 0 : (sl >= S ? S - 1 : sl);
+    lo[u] = r[sl];
+    hi[u] = r[sl + 1];
+    pb[u] = prow[(int64_t)sl * nb + k];
   }
-  if constexpr (kCols) {
-    pcol[dst] = c;
-    if (perm) perm[j] = (int32_t)dst;
+#pragma unroll
+  for (int u = 0; u < kScatterU; ++u) {
+    const int64_t j = jb + (int64_t)u * step;
+    if (j >= e) break;
+    const int64_t o = (j - s0) - lo[u];
+    const bool ok = c[u] >= 0 && (c[u] >> ls) < S && o >= 0 && o < (int64_t)(hi[u] - lo[u]);
+    if (!ok) {
+      atomicOr(err, 1);
+      if (perm) perm[j] = -1;
+      continue;
+    }
+    const int64_t dst = pb[u] + o;
+    if constexpr (kCols) {
+      pcol[dst] = c[u];
+      if (perm) perm[j] = (int32_t)dst;
+    }
+    if constexpr (kVals) pcv[dst] = ColV<V>{c[u], v[u]};
   }
-  if constexpr (kVals) pcv[dst] = ColV<V>{c, val[j]};
 }
 
 template <class V, bool kCols, bool kVals>
@@ -156,18 +178,18 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, con
     }
     const bool longrow = e - s0 > kScatterLane;
     if (!longrow)
-      for (int64_t j = s0; j < e; ++j)
-        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, j, pcol, pcv,
-                                            perm, err);
+      for (int64_t jb = s0; jb < e; jb += kScatterU)
+        slab_scatter_entries<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, e, jb, 1, pcol,
+                                              pcv, perm, err);
     unsigned long long m = __ballot(longrow);
     while (m) {
       const int l = __ffsll((long long)m) - 1;
       m &= m - 1ull;
       const int64_t kk = k0 + l;
       const int64_t ss = shfl_any(s0, l), ee = shfl_any(e, l);
-      for (int64_t j = ss + lane_id(); j < ee; j += kWave)
-        slab_scatter_entry<V, kCols, kVals>(col, val, nb, ls, S, bnd + kk * (S + 1), prow, kk, ss, j, pcol, pcv,
-                                            perm, err);
+      for (int64_t jb = ss + lane_id(); jb < ee; jb += (int64_t)kWave * kScatterU)
+        slab_scatter_entries<V, kCols, kVals>(col, val, nb, ls, S, bnd + kk * (S + 1), prow, kk, ss, ee, jb, kWave,
+                                              pcol, pcv, perm, err);
     }
   }
 }
