@@ -428,11 +428,10 @@ SG_DEV void pin_loaded(T& v) {
 // slots: lane l takes q = qb + u*64 + l (u < U), so every load instruction
 // is coalesced.  Owners come without per-lane searches: the owner a of qb by
 // a 64-ary search (one LDS read per lane and level), then every later slot
-// that starts inside the block sets the bit of its start in the wavefront's
-// 64*U-bit mask, and q's owner is a plus the set bits at or below q - qb.
-// The round then issues its U loads of src together (lanes past the chunk's
-// end re-load the block's first product, which always exists) and
-// fetch(slot, loaded element) makes each product.  ok[u] tells which pp[u]
+// that starts inside the block marks its start in the wavefront's 64*U-bit
+// mask, and q's owner is a plus the starts at or below q - qb.  The round
+// then issues its U loads of src together and fetch(slot, loaded element)
+// makes each product.  ok[u] tells which pp[u]
 // hold one.
 template <int BS, int U, class V, class R, class Fetch, class P>
 SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch, P* pp,
@@ -463,7 +462,8 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
     const int64_t o = j < nc ? L.off[j] : qe + 1;
     const bool in = o <= qe;
     if (in) {
-      const int p = (int)(o - qb);
+      // a slot starting at position p (1 <= p < 64*U) marks bit p - 1
+      const int p = (int)(o - qb) - 1;
       atomicOr(&rb[p >> 5], 1u << (p & 31));
     }
     if (__ballot(in) != ~0ull) break;
@@ -472,24 +472,24 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
   unsigned long long w[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) w[u] = (unsigned long long)rb[2 * u] | ((unsigned long long)rb[2 * u + 1] << 32);
-  const unsigned long long incl = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
-  const int64_t idx0 = L.st[a] + qb;
-  // products of the block: lane's row u holds product qb + u*64 + lane
+  // products of the block: lane's row u holds product qb + u*64 + lane,
+  // owned by slot a plus the starts marked at bits below its position (the
+  // bits below the lane in its row: mbcnt); lanes past the chunk's end take
+  // its last product, so every index is valid and needs no branch
   const int lim = (total - qb) < kBlock ? (int)(total - qb) : (int)kBlock;
   int own[U];
   int cnt = a;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     ok[u] = u * kWave + lane < lim;
-    own[u] = cnt + __popcll(w[u] & incl);
+    own[u] = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(w[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)w[u], 0u));
     cnt += __popcll(w[u]);
   }
-  // every row's owner is a valid slot, so the LDS reads need no branch
   int64_t idx[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) idx[u] = L.st[own[u]];
 #pragma unroll
-  for (int u = 0; u < U; ++u) idx[u] = ok[u] ? idx[u] + qb + (u * kWave + lane) : idx0;
+  for (int u = 0; u < U; ++u) idx[u] += qb + (ok[u] ? u * kWave + lane : lim - 1);
   using Bits = typename RawBits<sizeof(R)>::T;
   const Bits* bsrc = reinterpret_cast<const Bits*>(src);
   Bits raw[U];
