@@ -384,10 +384,27 @@ SG_DEV int64_t src_compact(SrcLds<V, BS>& L, int64_t st, int64_t len, V av, int*
   return tot >> 16;
 }
 
+// The segment of B row k inside tiles [s*G + tr0, s*G + tr1) of slab s
+// (whole: the full slab segment, from prow alone; otherwise prow + the tile
+// offsets rpt): its start in the partition and its length.
+template <class V>
+SG_DEV void src_segment(const SlabB<V>& b, int32_t k, int32_t s, int32_t tr0, int32_t tr1, bool whole, int64_t* st,
+                        int64_t* len) {
+  const int64_t* pr = b.prow + (int64_t)s * b.nb + k;
+  *st = pr[0];
+  if (whole) {
+    *len = pr[1] - *st;
+  } else {
+    const int32_t* r = b.rpt + ((int64_t)s * b.nb + k) * (b.G + 1);
+    const int32_t w0 = r[tr0];
+    *st += w0;
+    *len = r[tr1] - w0;
+  }
+}
+
 // Sources [c0, c0 + nc) of the row starting at A entry a0, restricted to
-// tiles [s*G + tr0, s*G + tr1) of slab s (whole: the full slab segment, from
-// prow alone; otherwise prow + the tile offsets rpt), one per thread,
-// compacted into slots.  Returns the chunk's product count; *n the slots.
+// tiles [s*G + tr0, s*G + tr1) of slab s, one per thread, compacted into
+// slots.  Returns the chunk's product count; *n the slots.
 template <class V, bool kVals, int BS>
 SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t s,
                           int32_t tr0, int32_t tr1, bool whole, int64_t c0, int nc, SrcLds<V, BS>& L, int* n) {
@@ -397,16 +414,7 @@ SG_DEV int64_t slab_chunk(const SlabB<V>& b, const int32_t* a_col, const V* a_va
     const int64_t e = a0 + c0 + threadIdx.x;
     const int32_t k = a_col[e];
     if constexpr (kVals) av = a_val[e];
-    const int64_t* pr = b.prow + (int64_t)s * b.nb + k;
-    st = pr[0];
-    if (whole) {
-      len = pr[1] - st;
-    } else {
-      const int32_t* r = b.rpt + ((int64_t)s * b.nb + k) * (b.G + 1);
-      const int32_t w0 = r[tr0];
-      st += w0;
-      len = r[tr1] - w0;
-    }
+    src_segment(b, k, s, tr0, tr1, whole, &st, &len);
   }
   return src_compact<V, kVals, BS>(L, st, len, av, n);
 }
@@ -520,7 +528,8 @@ SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, 
 
 // All products of a window of task (a0, nsrc, s, tr0, tr1): chunk by chunk
 // unless the caller already loaded the single chunk (`loaded`: nl slots,
-// total products).
+// total products).  The columns and A values of chunk c+1 are loaded while
+// chunk c is gathered, so a chunk waits for its segment bounds only.
 template <int BS, int U, class V, bool kVals, class R, class Fetch, class Apply>
 SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
                           int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int nl, int64_t total,
@@ -529,11 +538,24 @@ SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_va
     slab_iterate<BS, U, V>(L, nl, total, src, fetch, apply);
     return;
   }
+  const int64_t tid = threadIdx.x;
+  int32_t kn = 0;
+  V avn{};
+  if (tid < nsrc) {
+    kn = a_col[a0 + tid];
+    if constexpr (kVals) avn = a_val[a0 + tid];
+  }
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
-    const int nc = (int)((nsrc - c0) < BS ? (nsrc - c0) : BS);
+    int64_t st = 0, len = 0;
+    const V av = avn;
+    if (c0 + tid < nsrc) src_segment(b, kn, s, tr0, tr1, whole, &st, &len);
+    if (c0 + BS + tid < nsrc) {
+      kn = a_col[a0 + c0 + BS + tid];
+      if constexpr (kVals) avn = a_val[a0 + c0 + BS + tid];
+    }
     __syncthreads();
     int ns;
-    const int64_t tc = slab_chunk<V, kVals, BS>(b, a_col, a_val, a0, s, tr0, tr1, whole, c0, nc, L, &ns);
+    const int64_t tc = src_compact<V, kVals, BS>(L, st, len, av, &ns);
     slab_iterate<BS, U, V>(L, ns, tc, src, fetch, apply);
   }
 }
@@ -589,7 +611,7 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
 // Light windows (at most CAP entries): bitmap + rank, two passes over the
 // products (sources loaded once when one chunk holds them).
 template <class Sr, class V, int BS, int CAP>
-__global__ __launch_bounds__(BS) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
+__global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
                                                  const SlabTask* tasks, const int32_t* boff, int32_t nd,
                                                  int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
