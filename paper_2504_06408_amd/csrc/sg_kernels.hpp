@@ -392,19 +392,18 @@ __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy
     // eight independent source loads per lane in flight (hub rows of power-law
     // graphs hold tens of thousands of entries)
     for (int64_t j0 = 0; j0 < n2; j0 += 8 * kWave) {
+      // indices past the row's end re-load its last source, uncounted, so
+      // the eight loads carry no branch
       int64_t lens[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t j = j0 + u * kWave + lane_id();
-        lens[u] = 0;
-        if (j < n2) {
-          typename Src::Item it;
-          int64_t st;
-          t.load(j, it, st, lens[u]);
-        }
+        typename Src::Item it;
+        int64_t st;
+        t.load(j < n2 ? j : n2 - 1, it, st, lens[u]);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) part += lens[u];
+      for (int u = 0; u < 8; ++u) part += j0 + u * kWave + lane_id() < n2 ? lens[u] : 0;
     }
     part = wave_sum(part);
     if (lane_id() == leader) p = part;
