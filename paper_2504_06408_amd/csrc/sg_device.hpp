@@ -16,6 +16,16 @@ constexpr int kWave = 64;
 constexpr int32_t kEmptyKey = -1;
 
 SG_DEV int lane_id() { return (int)__lane_id(); }
+
+// Workgroup barrier for kernels whose wavefronts exchange data through LDS
+// only: the fences cover LDS alone, so a wavefront waits for its own LDS
+// operations (lgkmcnt) but not for its outstanding global loads and stores,
+// which __syncthreads() would also drain.
+SG_DEV void block_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 SG_DEV int wave_id() { return (int)(threadIdx.x >> 6); }
 
 SG_DEV unsigned long long lanes_below() {
@@ -106,7 +116,7 @@ template <int NW, class T>
 SG_DEV T block_excl_scan(T v, T* s_wave, T* total) {
   const T incl = wave_incl_scan(v);
   if (lane_id() == kWave - 1) s_wave[wave_id()] = incl;
-  __syncthreads();
+  block_sync();
   T pre = 0, tot = 0;
   const int w = wave_id();
 #pragma unroll
@@ -116,7 +126,7 @@ SG_DEV T block_excl_scan(T v, T* s_wave, T* total) {
     tot += s;
   }
   *total = tot;
-  __syncthreads();
+  block_sync();
   return pre + incl - v;
 }
 
@@ -182,7 +192,7 @@ SG_DEV void block_bitonic_sort(uint64_t* buf, int n) {
           buf[l] = a;
         }
       }
-      __syncthreads();
+      block_sync();
     }
   }
 }
@@ -207,7 +217,7 @@ SG_DEV uint64_t* block_radix_sort_hi(uint64_t* buf, uint64_t* tmp, int n, int kb
   const int c1 = (c0 + per_wave) < n ? (c0 + per_wave) : n;
   for (int shift = 32; shift < 32 + kbits; shift += 8) {
     for (int x = threadIdx.x; x < NW * 256; x += BS) s_hist[x] = 0;
-    __syncthreads();
+    block_sync();
     uint64_t item[RPL];
     int rank[RPL], dig[RPL];
 #pragma unroll
@@ -231,7 +241,7 @@ SG_DEV uint64_t* block_radix_sort_hi(uint64_t* buf, uint64_t* tmp, int n, int kb
       rank[r] = old + __popcll(below);
       dig[r] = valid ? d : -1;
     }
-    __syncthreads();
+    block_sync();
     // waves 0..3 (threads 0..255) own one digit each
     int tot = 0, inc = 0;
     if (threadIdx.x < 256) {
@@ -239,7 +249,7 @@ SG_DEV uint64_t* block_radix_sort_hi(uint64_t* buf, uint64_t* tmp, int n, int kb
       inc = wave_incl_scan(tot);
       if (l == kWave - 1) s_wt[w] = inc;
     }
-    __syncthreads();
+    block_sync();
     if (threadIdx.x < 256) {
       const int d = threadIdx.x;
       int run = inc - tot;
@@ -250,11 +260,11 @@ SG_DEV uint64_t* block_radix_sort_hi(uint64_t* buf, uint64_t* tmp, int n, int kb
         run += t;
       }
     }
-    __syncthreads();
+    block_sync();
 #pragma unroll
     for (int r = 0; r < RPL; ++r)
       if (dig[r] >= 0) tmp[s_hist[w * 256 + dig[r]] + rank[r]] = item[r];
-    __syncthreads();
+    block_sync();
     uint64_t* t = buf;
     buf = tmp;
     tmp = t;
@@ -331,7 +341,7 @@ SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s
     }
     const int nc = (int)(tot & 0xffff);
     const int64_t total = tot >> 16;
-    __syncthreads();
+    block_sync();
     // Wave w takes blocks of 64*U consecutive products; its lanes take
     // q = qb + u*64 + lane (u < U), so every load instruction is coalesced.
     // The owners of the block's first and last product come from a 64-ary
@@ -386,7 +396,7 @@ SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s
       for (int u = 0; u < U; ++u)
         if (ok[u]) apply(p[u]);
     }
-    __syncthreads();
+    block_sync();
   }
 }
 

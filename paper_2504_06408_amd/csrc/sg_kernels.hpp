@@ -355,7 +355,7 @@ __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy
   using Src = typename Rows::Src;
   __shared__ int32_t s_hist[kNB];
   for (int b = threadIdx.x; b < kNB; b += BS) s_hist[b] = 0;
-  __syncthreads();
+  block_sync();
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   const bool valid = i < nrows;
   Src s{};
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy
     atomicAdd(&s_hist[b], 1);
     if (!pol.numeric && b == kBinEmpty) cnt_out[i] = 0;
   }
-  __syncthreads();
+  block_sync();
   for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
 }
 
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(BS) void k_rebin(const int64_t* p_in, const int32_t
                                               int64_t nrows, Policy pol, uint8_t* bin_out, int32_t* hist) {
   __shared__ int32_t s_hist[kNB];
   for (int b = threadIdx.x; b < kNB; b += BS) s_hist[b] = 0;
-  __syncthreads();
+  block_sync();
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < nrows) {
     const int64_t p = p_in[i];
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(BS) void k_rebin(const int64_t* p_in, const int32_t
     bin_out[i] = (uint8_t)b;
     atomicAdd(&s_hist[b], 1);
   }
-  __syncthreads();
+  block_sync();
   for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
 }
 
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(BS) void k_bin_scatter(const uint8_t* bin_in, int64
   constexpr int NW = BS / kWave;
   __shared__ int32_t s_cnt[NW][kNB];
   for (int x = threadIdx.x; x < NW * kNB; x += BS) (&s_cnt[0][0])[x] = 0;
-  __syncthreads();
+  block_sync();
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   const bool valid = i < nrows;
   const int b = valid ? (int)bin_in[i] : 0;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(BS) void k_bin_scatter(const uint8_t* bin_in, int64
   const unsigned long long below = match & lanes_below();
   const int rank = __popcll(below);
   if (valid && below == 0) s_cnt[wave_id()][b] = __popcll(match);
-  __syncthreads();
+  block_sync();
   if (valid) {
     int32_t pre = 0;
     for (int w = 0; w < wave_id(); ++w) pre += s_cnt[w][b];
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(BS) void k_sym_hash(Rows rows, Bins bins, int bin, 
   for (int r = blockIdx.x; r < n; r += gridDim.x) {
     const int64_t i = L[r];
     for (int x = threadIdx.x; x < S; x += BS) s_keys[x] = kEmptyKey;
-    __syncthreads();
+    block_sync();
     Src s{};
     int64_t li;
     rows.get(i, s, li);
@@ -655,7 +655,7 @@ SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_
     sm.vals[x] = Sr::ident();
   }
   if (threadIdx.x == 0) sm.n = 0;
-  __syncthreads();
+  block_sync();
   const int64_t nsrc = s.bind(li, t0, t1);
   auto fetch = [&](const Item& it, int64_t idx) {
     return ColVal<typename Sr::Acc>{s.col(it, idx), s.template value<Sr>(it, idx)};
@@ -675,7 +675,7 @@ SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_
       if (pos < S / 2) sm.sort[pos] = ((uint64_t)(uint32_t)(k - key_base) << 32) | (uint32_t)x;
     }
   }
-  __syncthreads();
+  block_sync();
   int cnt = sm.n;
   if (threadIdx.x == 0 && cnt != m) atomicOr(err, 1);
   cnt = cnt < S / 2 ? cnt : S / 2;
@@ -692,7 +692,7 @@ SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_
     int M = 1;
     while (M < cnt) M <<= 1;
     for (int x = cnt + threadIdx.x; x < M; x += BS) sm.sort[x] = ~0ull;
-    __syncthreads();
+    block_sync();
     block_bitonic_sort<BS>(sm.sort, M);
   }
   const int64_t wr = cnt < m ? cnt : m;
@@ -701,7 +701,7 @@ SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_
     C.col[o + x] = (int32_t)((int64_t)(e >> 32) + key_base);
     ((V*)C.val)[o + x] = Sr::out(sm.vals[(uint32_t)e]);
   }
-  __syncthreads();
+  block_sync();
 }
 
 template <class Sr, class Rows, int LGS, int BS>
@@ -758,7 +758,7 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
       c1 = c1 < ncols ? c1 : ncols;
       const int nwords = (int)((c1 - c0 + 31) >> 5);
       for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
-      __syncthreads();
+      block_sync();
       const int64_t nsrc = s.bind(li, st, t1);
       auto fetch = [&](const Item& it, int64_t idx) { return (int32_t)(s.col(it, idx) - c0); };
       auto apply = [&](int32_t c) { atomicOr(&s_bm[c >> 5], 1u << (c & 31)); };
@@ -773,7 +773,7 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
         c = wave_sum(c);
         if (lane_id() == 0) s_tcnt[tl] = c;
       }
-      __syncthreads();
+      block_sync();
       if (wave_id() == 0) {
         const int ntl = t1 - st;
         const int32_t v = lane_id() < ntl ? s_tcnt[lane_id()] : 0;
@@ -781,12 +781,12 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
         if (lane_id() < ntl) o2[st + lane_id()] = run + inc - v;
         if (lane_id() == kWave - 1) s_run = run + inc;
       }
-      __syncthreads();
+      block_sync();
       run = s_run;
     }
     for (int t = T + threadIdx.x; t <= Tmax; t += BS) o2[t] = run;
     if (threadIdx.x == 0) cnt_out[i] = run;
-    __syncthreads();
+    block_sync();
   }
 }
 
@@ -821,9 +821,9 @@ SG_DEV void for_each_queued(int32_t* ctr, int list, int64_t ntask, int64_t* s_sl
   const int64_t nq = ntask > q ? (ntask - q + kQueues - 1) / kQueues : 0;
   while (true) {
     if (threadIdx.x == 0) *s_slot = atomicAdd(qc, kGrab);
-    __syncthreads();
+    block_sync();
     const int64_t j0 = *s_slot;
-    __syncthreads();
+    block_sync();
     if (j0 >= nq) break;
     const int64_t j1 = (j0 + kGrab) < nq ? (j0 + kGrab) : nq;
     for (int64_t j = j0; j < j1; ++j) task(q + j * kQueues);
@@ -863,7 +863,7 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
                                                     int32_t* ctr) {
   __shared__ unsigned long long s_ent[3];
   if (threadIdx.x < 3) s_ent[threadIdx.x] = 0ull;
-  __syncthreads();
+  block_sync();
   unsigned long long ent[3] = {0ull, 0ull, 0ull};
   const int32_t nd = dense_rows(bins);
   int32_t* cnt_t = book;
@@ -912,7 +912,7 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
     const unsigned long long v = wave_sum(ent[l]);
     if (lane_id() == 0 && v) atomicAdd(&s_ent[l], v);
   }
-  __syncthreads();
+  block_sync();
   if (threadIdx.x < 3 && s_ent[threadIdx.x])
     atomicAdd((unsigned long long*)(ctr + kCtrEntries) + threadIdx.x, s_ent[threadIdx.x]);
 }
@@ -1011,7 +1011,7 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
       }
       s_bm[threadIdx.x] = 0u;
     }
-    __syncthreads();
+    block_sync();
   });
 }
 

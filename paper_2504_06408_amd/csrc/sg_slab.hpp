@@ -266,7 +266,7 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
   __shared__ unsigned long long s_ent[2];
   const bool lds = S <= kTaskSlabsLds;
   if (threadIdx.x < 2) s_ent[threadIdx.x] = 0ull;
-  __syncthreads();
+  block_sync();
   const int64_t nd = dense_rows(bins);
   const int64_t stride = bins.nd_cap;  // slots per bucket
   int32_t* cnt_g[2] = {book + kListSlab * T, book + kListTile * T};
@@ -277,21 +277,21 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
     const int32_t* o2 = off2 + (mine ? h : 0) * (T + 1);
     if (lds) {
       for (int x = threadIdx.x; x < 2 * S; x += BS) s_cnt[x / S][x % S] = 0;
-      __syncthreads();
+      block_sync();
       if (mine)
         for (int32_t sl = 0, ta = 0; ta < T; ta += G, ++sl) {
           const int32_t tb = ta + G < T ? ta + G : T;
           const int32_t m = o2[tb] - o2[ta];
           if (m > 0) atomicAdd(&s_cnt[m <= cap ? 0 : 1][sl], 1);
         }
-      __syncthreads();
+      block_sync();
       for (int x = threadIdx.x; x < 2 * S; x += BS) {
         const int l = x / S, sl = x % S;
         const int32_t c = s_cnt[l][sl];
         s_base[l][sl] = c ? atomicAdd(&cnt_g[l][sl], c) : 0;
         s_cnt[l][sl] = 0;
       }
-      __syncthreads();
+      block_sync();
     }
     if (mine) {
       const DenseRow d = dr[h];
@@ -307,13 +307,13 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
         ent[l] += (unsigned long long)m;
       }
     }
-    if (lds) __syncthreads();
+    if (lds) block_sync();
   }
   for (int l = 0; l < 2; ++l) {
     const unsigned long long v = wave_sum(ent[l]);
     if (lane_id() == 0 && v) atomicAdd(&s_ent[l], v);
   }
-  __syncthreads();
+  block_sync();
   unsigned long long* eg = (unsigned long long*)(ctr + kCtrEntries);
   if (threadIdx.x == 0 && s_ent[0]) atomicAdd(eg + kListSlab, s_ent[0]);
   if (threadIdx.x == 1 && s_ent[1]) atomicAdd(eg + kListTile, s_ent[1]);
@@ -379,7 +379,7 @@ SG_DEV int64_t src_compact(SrcLds<V, BS>& L, int64_t st, int64_t len, V av, int*
     L.st[pos] = st - (ex >> 16);
     if constexpr (kVals) L.a[pos] = av;
   }
-  __syncthreads();
+  block_sync();
   *n = (int)(tot & 0xffff);
   return tot >> 16;
 }
@@ -553,7 +553,7 @@ SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_va
       kn = a_col[a0 + c0 + BS + tid];
       if constexpr (kVals) avn = a_val[a0 + c0 + BS + tid];
     }
-    __syncthreads();
+    block_sync();
     int ns;
     const int64_t tc = src_compact<V, kVals, BS>(L, st, len, av, &ns);
     slab_iterate<BS, U, V>(L, ns, tc, src, fetch, apply);
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
     };
     slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pcol,
                                               fetch, apply);
-    __syncthreads();
+    block_sync();
     int32_t* o2 = off2 + h * (T + 1);
     for (int tl = wave_id(); tl < G; tl += NW) {
       int32_t c = 0;
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
   const bool bcache = T < kBoffCache;
   if (bcache)
     for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
-  __syncthreads();
+  block_sync();
   const int wv = wave_id();
   for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &L.slot, [&](int64_t g) {
     const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     const bool one = tk.nsrc <= BS;
     int64_t total = 0;
     int nl = 0;
-    __syncthreads();
+    block_sync();
     if (one) total = slab_chunk<V, true, BS>(b, a_col, a_val, tk.a0, tk.s, tr0, tr1, whole, 0, tk.nsrc, L, &nl);
     // With one round of products per wavefront the products stay in
     // registers for pass 2; otherwise pass 2 gathers them again.
@@ -673,7 +673,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
       slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L, b.pcv,
                                          f1, a1);
     }
-    __syncthreads();
+    block_sync();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lane l the kpl
     // consecutive words from wv*wpw + l*kpl; word popcounts stay in
     // registers between the count and the rank pass
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     const int32_t linc = wave_incl_scan(lt);
     if (lane_id() == kWave - 1) s_wt[wv] = linc;
     for (int x = threadIdx.x; x < m; x += BS) s_val[x] = Sr::ident();
-    __syncthreads();
+    block_sync();
     int32_t wbase = 0, tot = 0;
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
         s_rank[w0 + i] = (uint16_t)rk;
         rk += pcw[i];
       }
-    __syncthreads();
+    block_sync();
     // pass 2: fold every product into its compacted slot
     if (held) {
 #pragma unroll
@@ -715,24 +715,29 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
       slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L, b.pcv,
                                          f2, a2);
     }
-    __syncthreads();
+    block_sync();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
     // loop), values in rank order (coalesced); the bitmap is cleared for the
     // next task
+    // (lanes store at 32-bit offsets from the task's uniform output base)
+    const int64_t o0 = uniform64(tk.out);
+    char* colb = reinterpret_cast<char*>(C.col + o0);
+    char* valb = reinterpret_cast<char*>((V*)C.val + o0);
     for (int it = 0; it < wpw; it += kWave) {
       const int w = wv * wpw + it + lane_id();
       uint32_t bits = s_bits[w];
-      int32_t r = s_rank[w];
-      const int64_t cbase = cw0 + w * 32;
+      uint32_t r = s_rank[w];
+      const int32_t cbase = (int32_t)(cw0 + w * 32);
       while (bits) {
         const int bt = __ffs((int)bits) - 1;
         bits &= bits - 1u;
-        if (r < m) C.col[tk.out + r] = (int32_t)(cbase + bt);
+        if (r < (uint32_t)m) *reinterpret_cast<int32_t*>(colb + r * (uint32_t)sizeof(int32_t)) = cbase + bt;
         ++r;
       }
       s_bits[w] = 0u;
     }
-    for (int x = threadIdx.x; x < m; x += BS) ((V*)C.val)[tk.out + x] = Sr::out(s_val[x]);
+    for (uint32_t x = threadIdx.x; x < (uint32_t)m; x += BS)
+      *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(s_val[x]);
   });
 }
 
@@ -766,11 +771,11 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
   const bool bcache = T < kBoffCache;
   if (bcache)
     for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
-  __syncthreads();
+  block_sync();
   for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, [&](int64_t g) {
     const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
     const int ts0 = tk.t0, ts1 = tk.t1;
-    __syncthreads();
+    block_sync();
     if ((int)threadIdx.x <= ts1 - ts0) {
       const int32_t* o2 = off2 + (int64_t)tk.h * (T + 1);
       s_tc[threadIdx.x] = o2[ts0 + threadIdx.x] - o2[ts0];
@@ -794,7 +799,7 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
       for (int q = 0; q <= kSlabTilesMax; ++q)
         if (q <= G) rec[q] = r[q];
     }
-    __syncthreads();
+    block_sync();
     for (int t = ts0; t < ts1; ++t) {
       const int32_t rel = s_tc[t - ts0], mt = s_tc[t + 1 - ts0] - rel;
       if (mt <= 0) continue;
@@ -825,7 +830,7 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false, false,
                                            0, 0, L, b.pcv, f, ap);
       }
-      __syncthreads();
+      block_sync();
       // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and
       // reads 64 consecutive slots per step (no bank conflicts); a ballot of
       // the occupied slots gives each lane its output rank, so the stores of
@@ -842,7 +847,7 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         cnt = wave_sum((int32_t)__popc(s_bm[(sb >> 5) + lane_id()]));
       }
       if (lane_id() == 0) s_wave32[wv] = cnt;
-      __syncthreads();
+      block_sync();
       int32_t base = 0, tot = 0;
 #pragma unroll
       for (int u = 0; u < NW; ++u) {
@@ -883,7 +888,7 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
       }
       if constexpr (!Sr::kValueMarks) s_bm[(sb >> 5) + lane_id()] = 0u;
       if (threadIdx.x == 0 && tot != mt) atomicOr(err, 1);
-      __syncthreads();
+      block_sync();
     }
   });
 }
