@@ -83,10 +83,11 @@ def measured_traffic(workload: str, kernel: str):
     if workload != "rmat20_minplus" or not os.path.exists(COUNTERS):
         return None
     text = open(COUNTERS).read()
-    fields = dict(re.findall(r"^(dominant_kernel|traffic_bytes_per_launch|kernel_sources_sha256): (\S+)$", text, re.M))
-    if fields.get("dominant_kernel") != kernel or fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+    sha = re.search(r"^kernel_sources_sha256: (\S+)$", text, re.M)
+    per = dict(re.findall(r"^traffic_bytes_per_launch\.(\w+): (\d+)$", text, re.M))
+    if not sha or sha.group(1) != kernel_sources_sha256() or kernel not in per:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(per[kernel])
 
 
 def products_per_row(A, B):
