@@ -586,8 +586,14 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
     const int ts0 = s * G;
     const int64_t c0 = (int64_t)ts0 << kTileLog;
     auto fetch = [&](int, int32_t c) { return (int32_t)(c - c0); };
+    // only each tile's count of distinct columns is needed, so columns are
+    // interleaved over the tile's words (column x of a tile: word x mod 512,
+    // bit x / 512): neighbouring columns, which the lanes of a round mostly
+    // hold, land in different words and LDS banks
     auto apply = [&](int32_t c) {
-      if ((uint32_t)c < cmax) atomicOr(&s_bm[c >> 5], 1u << (c & 31));
+      if ((uint32_t)c < cmax)
+        atomicOr(&s_bm[(c >> kTileLog) * kTileWords + (c & (kTileWords - 1))],
+                 1u << ((c & (kTile - 1)) >> (kTileLog - 5)));
     };
     slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pcol,
                                               fetch, apply);
