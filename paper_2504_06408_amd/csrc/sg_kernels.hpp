@@ -748,28 +748,28 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
     int64_t li;
     rows.get(i, s, li);
     const int32_t T = s.T;
-    const int64_t ncols = s.ncols;
     int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
     int32_t run = 0;
     for (int st = 0; st < T; st += kSymTiles) {
       const int t1 = (st + kSymTiles) < T ? (st + kSymTiles) : T;
       const int64_t c0 = (int64_t)st << kTileLog;
-      int64_t c1 = (int64_t)t1 << kTileLog;
-      c1 = c1 < ncols ? c1 : ncols;
-      const int nwords = (int)((c1 - c0 + 31) >> 5);
+      // whole tiles: columns are interleaved over a tile's words (column x
+      // of a tile: word x mod 512, bit x / 512), since only per-tile counts
+      // are needed; neighbouring columns then land in different words and
+      // LDS banks
+      const int nwords = (t1 - st) * kTileWords;
       for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
       block_sync();
       const int64_t nsrc = s.bind(li, st, t1);
       auto fetch = [&](const Item& it, int64_t idx) { return (int32_t)(s.col(it, idx) - c0); };
-      auto apply = [&](int32_t c) { atomicOr(&s_bm[c >> 5], 1u << (c & 31)); };
+      auto apply = [&](int32_t c) {
+        atomicOr(&s_bm[(c >> kTileLog) * kTileWords + (c & (kTileWords - 1))], 1u << ((c & (kTile - 1)) >> (kTileLog - 5)));
+      };
       for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, fetch, apply);
       // one wavefront per tile, lanes over its 512 words
       for (int tl = wave_id(); tl < t1 - st; tl += NW) {
         int32_t c = 0;
-        for (int x = lane_id(); x < kTileWords; x += kWave) {
-          const int wx = tl * kTileWords + x;
-          if (wx < nwords) c += __popc(s_bm[wx]);
-        }
+        for (int x = lane_id(); x < kTileWords; x += kWave) c += __popc(s_bm[tl * kTileWords + x]);
         c = wave_sum(c);
         if (lane_id() == 0) s_tcnt[tl] = c;
       }
