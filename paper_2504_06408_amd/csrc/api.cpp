@@ -130,7 +130,7 @@ sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B,
     SG_HIP(h, sb.bnd.ensure(sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
     SG_HIP(h, sb.rpt.ensure(sizeof(int32_t) * (size_t)S * (size_t)nb * (size_t)(G + 1)));
     SG_HIP(h, sb.prow.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
-    SG_HIP(h, sb.pcol.ensure(sizeof(int32_t) * ne));
+    SG_HIP(h, sb.pbit.ensure(sizeof(int32_t) * ne));
   }
   // numeric partition entries: (column, value) pairs, 8 bytes (16 for 8-byte values)
   if (vals) SG_HIP(h, sb.pcv.ensure((size_t)(vbytes >= 8 ? 16 : 8) * ne));
@@ -139,12 +139,12 @@ sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B,
   const bool use_perm = B->nnz <= INT32_MAX;
   if (cols && use_perm) SG_HIP(h, sb.perm.ensure(sizeof(int32_t) * ne));
   launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, B->nnz, ls, S, r.T, (int32_t*)sb.bnd.p,
-                        (int32_t*)sb.rpt.p, (int64_t*)sb.prow.p, partial, (int32_t*)sb.pcol.p,
+                        (int32_t*)sb.rpt.p, (int64_t*)sb.prow.p, partial, (int32_t*)sb.pbit.p,
                         vals ? sb.pcv.p : nullptr, use_perm ? (int32_t*)sb.perm.p : nullptr, cols, vals, err, h->cus,
                         st);
   r.rpt = (const int32_t*)sb.rpt.p;
   r.prow = (const int64_t*)sb.prow.p;
-  r.pcol = (const int32_t*)sb.pcol.p;
+  r.pbit = (const int32_t*)sb.pbit.p;
   r.pval = vals ? sb.pcv.p : nullptr;
   r.ls = ls;
   r.S = S;

@@ -174,7 +174,7 @@ void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t
   const int nd = plan.ndense();
   if (nd == 0) return;
   const int32_t G = 1 << (r.ls - kTileLog);
-  const SlabB<uint8_t> b{r.prow, r.pcol, nullptr, r.rpt, r.b_nrows, G, r.T};
+  const SlabB<uint8_t> b{r.prow, r.pbit, nullptr, r.rpt, r.b_nrows, G, r.T};
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, r.qctr, (int64_t)kCtrInts,
                      (int32_t)0);
   constexpr int BS = 256;
@@ -239,31 +239,34 @@ void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows
 
 template <class V>
 void slab_scatter(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int64_t nb, int64_t nnz,
-                  int32_t ls, int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pcol, void* pcv,
+                  int32_t ls, int32_t S, const int32_t* bnd, const int64_t* prow, int32_t* pbit, void* pcv,
                   int32_t* perm, bool cols, bool vals, int32_t* err, int cus, hipStream_t st) {
   const dim3 g(grid_for(nb, 256, cus * 16)), b(256);
   const V* bv = (const V*)b_val;
   ColV<V>* cv = (ColV<V>*)pcv;
   if (cols && vals)
-    hipLaunchKernelGGL((k_slab_scatter<V, true, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow, pcol,
+    hipLaunchKernelGGL((k_slab_scatter<V, true, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow, pbit,
                        cv, perm, err);
   else if (cols)
     hipLaunchKernelGGL((k_slab_scatter<V, true, false>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
-                       pcol, cv, perm, err);
+                       pbit, cv, perm, err);
   else if (vals && perm)
     hipLaunchKernelGGL((k_slab_perm_cv<V>), dim3(grid_for(nnz, 256, cus * 16)), b, 0, st, b_col, bv,
                        (const int32_t*)perm, nnz, cv);
   else if (vals)
     hipLaunchKernelGGL((k_slab_scatter<V, false, true>), g, b, 0, st, b_rowptr, b_col, bv, nb, ls, S, bnd, prow,
-                       pcol, cv, (int32_t*)nullptr, err);
+                       pbit, cv, (int32_t*)nullptr, err);
 }
 
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
                            int64_t nnz, int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
-                           int64_t* partial, int32_t* pcol, void* pval, int32_t* perm, bool cols, bool vals,
+                           int64_t* partial, int32_t* pbit, void* pval, int32_t* perm, bool cols, bool vals,
                            int32_t* err, int cus, hipStream_t st) {
   if (nb <= 0) return;
   if (cols) {
+    // entries that contradict the bounds leave their slot unwritten; code 0
+    // there keeps every bitmap code in range
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(nnz, 256, cus * 16)), dim3(256), 0, st, pbit, nnz, (int32_t)0);
     hipLaunchKernelGGL(k_slab_bounds<256>, dim3(grid_for(nb, 4, cus * 16)), dim3(256), 0, st, b_rowptr, b_col, nb, T,
                        (int32_t)(1 << (ls - kTileLog)), S, bnd, rpt);
     hipLaunchKernelGGL(k_slab_counts<256>, dim3(grid_for((int64_t)S * nb, 256, cus * 16)), dim3(256), 0, st,
@@ -272,15 +275,15 @@ void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const 
   }
   switch (vbytes) {
     case 1:
-      slab_scatter<uint8_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pcol, pval, perm, cols, vals, err, cus,
+      slab_scatter<uint8_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pbit, pval, perm, cols, vals, err, cus,
                             st);
       break;
     case 4:
-      slab_scatter<uint32_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pcol, pval, perm, cols, vals, err,
+      slab_scatter<uint32_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pbit, pval, perm, cols, vals, err,
                              cus, st);
       break;
     default:
-      slab_scatter<uint64_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pcol, pval, perm, cols, vals, err,
+      slab_scatter<uint64_t>(b_rowptr, b_col, b_val, nb, nnz, ls, S, bnd, prow, pbit, pval, perm, cols, vals, err,
                              cus, st);
       break;
   }

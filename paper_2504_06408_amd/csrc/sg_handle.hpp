@@ -42,12 +42,12 @@ struct SgBuf {
 // the segments, segment starts, column ids, (column, value) pairs, each B
 // entry's position) and the dense-row table of the product using it.
 struct SlabBufs {
-  SgBuf bnd, rpt, prow, pcol, pcv, perm, dr;
+  SgBuf bnd, rpt, prow, pbit, pcv, perm, dr;
   void release() {
     bnd.release();
     rpt.release();
     prow.release();
-    pcol.release();
+    pbit.release();
     pcv.release();
     perm.release();
     dr.release();

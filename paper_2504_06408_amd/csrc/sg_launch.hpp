@@ -41,7 +41,7 @@ struct RowSource {
   int32_t T;      // column tiles (single modes) or the largest over the batch
   // column-slab partition of B (single product; S = 0: not used)
   const int64_t* prow;
-  const int32_t* pcol;
+  const int32_t* pbit;
   const void* pval;       // numeric partition: (column, value) pairs (ColV)
   const int32_t* rpt;     // tile offsets inside each slab segment
   const DenseRow* drow;   // per dense row: its A row
@@ -208,7 +208,7 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
                          c.src.drow, c.off2, T, G, c.src.S, (int32_t)kSlabCap, (const int64_t*)c.C.rowptr, light,
                          heavy, sbook, c.task_ctr);
       hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, sbook, T, c.task_ctr);
-      SlabB<V> b{c.src.prow, c.src.pcol, (const ColV<V>*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
+      SlabB<V> b{c.src.prow, c.src.pbit, (const ColV<V>*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
       {
         auto k = k_num_slab<Sr, V, 512, kSlabCap>;
         static int occ = occupancy(k, 512);
@@ -304,14 +304,14 @@ void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows
                         hipStream_t st);
 // Column-slab partition of B (slabs of 2^ls columns, S of them): with cols
 // set, the bounds bnd (S+1 ints per B row), the tile offsets rpt, the
-// segment starts prow (S*nb + 1), pcol and, when perm is given, each
+// segment starts prow (S*nb + 1), pbit and, when perm is given, each
 // entry's destination; with vals set, pval (vbytes per entry), through perm
 // when it is given and cols is not set.  partial: scan_partials_len(S*nb)
 // int64 of scratch; err: flag set on entries that contradict the bounds
 // (unsorted or out-of-range columns).
 void launch_slab_partition(const int64_t* b_rowptr, const int32_t* b_col, const void* b_val, int vbytes, int64_t nb,
                            int64_t nnz, int32_t ls, int32_t S, int32_t T, int32_t* bnd, int32_t* rpt, int64_t* prow,
-                           int64_t* partial, int32_t* pcol, void* pval, int32_t* perm, bool cols, bool vals,
+                           int64_t* partial, int32_t* pbit, void* pval, int32_t* perm, bool cols, bool vals,
                            int32_t* err, int cus, hipStream_t st);
 // Per dense row of the plan: its A row (the slab path's row table).
 void launch_dense_rows(const BinPlan& plan, const int64_t* a_rowptr, DenseRow* dr, int cus, hipStream_t st);

@@ -1,7 +1,8 @@
 // Device-side semirings (paper, Section 2.2): value type V, the accumulator
 // type Acc kept in LDS, the identity of (+) used to initialise accumulator
 // slots, (x) producing an Acc, (+) on Acc both atomically in LDS and in
-// registers, and the final conversion back to V.
+// registers, and the final conversion back to V.  kIdempotent: x (+) x = x,
+// so folding a product twice equals folding it once.
 //
 // Slots start at the (+)-identity, so "0 (+) first product" stands in for
 // "first product initialises the slot"; the two agree exactly except for the
@@ -21,6 +22,7 @@ struct SrI64 {
   using Acc = unsigned long long;
   static constexpr int kId = 1;
   static constexpr bool kValueMarks = false;
+  static constexpr bool kIdempotent = false;
   SG_DEV static Acc ident() { return 0ull; }
   SG_DEV static Acc mul(V a, V b) { return (Acc)a * (Acc)b; }
   SG_DEV static Acc lift(V a) { return (Acc)a; }
@@ -35,6 +37,7 @@ struct SrF32 {
   using Acc = float;
   static constexpr int kId = 2;
   static constexpr bool kValueMarks = false;
+  static constexpr bool kIdempotent = false;
   SG_DEV static Acc ident() { return 0.0f; }
   SG_DEV static Acc mul(V a, V b) { return a * b; }
   SG_DEV static Acc lift(V a) { return a; }
@@ -54,6 +57,7 @@ struct SrF32Comp {
   using Acc = unsigned long long;  // low word: hi, high word: lo
   static constexpr int kId = 2;
   static constexpr bool kValueMarks = false;
+  static constexpr bool kIdempotent = false;
   SG_DEV static Acc pack(float hi, float lo) {
     return (Acc)__float_as_uint(hi) | ((Acc)__float_as_uint(lo) << 32);
   }
@@ -94,6 +98,7 @@ struct SrF64 {
   using Acc = double;
   static constexpr int kId = 3;
   static constexpr bool kValueMarks = false;
+  static constexpr bool kIdempotent = false;
   SG_DEV static Acc ident() { return 0.0; }
   SG_DEV static Acc mul(V a, V b) { return a * b; }
   SG_DEV static Acc lift(V a) { return a; }
@@ -109,6 +114,7 @@ struct SrBool {
   using Acc = uint8_t;
   static constexpr int kId = 4;
   static constexpr bool kValueMarks = false;
+  static constexpr bool kIdempotent = true;
   SG_DEV static Acc ident() { return 0; }
   SG_DEV static Acc mul(V a, V b) { return (a != 0 && b != 0) ? 1 : 0; }
   SG_DEV static Acc lift(V a) { return a != 0 ? 1 : 0; }
@@ -130,6 +136,7 @@ struct SrMinPlus {
   using Acc = uint32_t;
   static constexpr int kId = 5;
   static constexpr bool kValueMarks = true;
+  static constexpr bool kIdempotent = true;
   SG_DEV static uint32_t key(float f) {
     const uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);

@@ -2,8 +2,8 @@
 //
 // B's columns are cut into slabs of 2^ls columns (one to eight 16384-column
 // tiles).  A partition of B keeps, for slab s and B row k, the entries of
-// B_k inside the slab contiguous:  pcol/pcv[prow[s*nb + k] .. prow[s*nb + k + 1])
-// (pcol: column ids for the symbolic pass; pcv: column and value pairs for
+// B_k inside the slab contiguous:  pbit/pcv[prow[s*nb + k] .. prow[s*nb + k + 1])
+// (pbit: column ids for the symbolic pass; pcv: column and value pairs for
 // the numeric pass),
 // and rpt[(s*nb + k)*(G+1) + t] holds where tile t of the slab starts inside
 // that segment.  A dense row's work is one task per (row, slab); every task
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(BS) void k_slab_counts(const int32_t* bnd, int64_t 
 // entries are then walked by the whole wavefront, one after another.  Entries
 // go kScatterU at a time per lane: their columns, then their slab bounds and
 // segment starts, are loaded together before any is stored.  With kCols the
-// column ids go to pcol and, if perm is given, each entry's destination to
+// column ids go to pbit and, if perm is given, each entry's destination to
 // perm (so later value scatters need no bounds); with kVals the values go to
 // pval.  Entries that do not fall where the bounds say (unsorted or
 // out-of-range columns) are dropped and flagged instead of written out of
@@ -119,12 +119,23 @@ __global__ __launch_bounds__(BS) void k_slab_counts(const int32_t* bnd, int64_t 
 constexpr int kScatterLane = 32;
 constexpr int kScatterU = 8;
 
+// Position of column c in the symbolic bitmap of its slab (slabs of 2^ls
+// columns): a tile's columns are interleaved over its kTileWords words
+// (column x of the tile: word x mod kTileWords, bit x / kTileWords), and the
+// code is word*128 + bit, so that code >> 5 is the word's byte offset and the
+// code's low 5 bits are the bit.  Any c gives a word below kSlabWordsMax.
+SG_DEV int32_t slab_bit_code(int32_t c, int32_t ls) {
+  const int32_t r = c & ((1 << ls) - 1);
+  const int32_t word = ((r >> kTileLog) * kTileWords) | (r & (kTileWords - 1));
+  return (word << 7) | ((r & (kTile - 1)) / kTileWords);
+}
+
 // Entries jb + u*step (u < kScatterU, those below e) of row k starting at s0,
 // whose row-local slab bounds are r[0..S].
 template <class V, bool kCols, bool kVals>
 SG_DEV void slab_scatter_entries(const int32_t* col, const V* val, int64_t nb, int32_t ls, int32_t S,
                                  const int32_t* r, const int64_t* prow, int64_t k, int64_t s0, int64_t e, int64_t jb,
-                                 int step, int32_t* pcol, ColV<V>* pcv, int32_t* perm, int32_t* err) {
+                                 int step, int32_t* pbit, ColV<V>* pcv, int32_t* perm, int32_t* err) {
   int32_t c[kScatterU];
   V v[kScatterU];
 #pragma unroll
@@ -156,7 +167,7 @@ SG_DEV void slab_scatter_entries(const int32_t* col, const V* val, int64_t nb, i
     }
     const int64_t dst = pb[u] + o;
     if constexpr (kCols) {
-      pcol[dst] = c[u];
+      pbit[dst] = slab_bit_code(c[u], ls);
       if (perm) perm[j] = (int32_t)dst;
     }
     if constexpr (kVals) pcv[dst] = ColV<V>{c[u], v[u]};
@@ -166,7 +177,7 @@ SG_DEV void slab_scatter_entries(const int32_t* col, const V* val, int64_t nb, i
 template <class V, bool kCols, bool kVals>
 __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, const int32_t* col, const V* val,
                                                       int64_t nb, int32_t ls, int32_t S, const int32_t* bnd,
-                                                      const int64_t* prow, int32_t* pcol, ColV<V>* pcv, int32_t* perm,
+                                                      const int64_t* prow, int32_t* pbit, ColV<V>* pcv, int32_t* perm,
                                                       int32_t* err) {
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
   for (int64_t k0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * kWave; k0 < nb; k0 += nwaves * kWave) {
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, con
     const bool longrow = e - s0 > kScatterLane;
     if (!longrow)
       for (int64_t jb = s0; jb < e; jb += kScatterU)
-        slab_scatter_entries<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, e, jb, 1, pcol,
+        slab_scatter_entries<V, kCols, kVals>(col, val, nb, ls, S, bnd + k * (S + 1), prow, k, s0, e, jb, 1, pbit,
                                               pcv, perm, err);
     unsigned long long m = __ballot(longrow);
     while (m) {
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int64_t* rowptr, con
       const int64_t ss = shfl_any(s0, l), ee = shfl_any(e, l);
       for (int64_t jb = ss + lane_id(); jb < ee; jb += (int64_t)kWave * kScatterU)
         slab_scatter_entries<V, kCols, kVals>(col, val, nb, ls, S, bnd + kk * (S + 1), prow, kk, ss, ee, jb, kWave,
-                                              pcol, pcv, perm, err);
+                                              pbit, pcv, perm, err);
     }
   }
 }
@@ -322,7 +333,7 @@ __global__ __launch_bounds__(BS) void k_slab_tasks(Bins bins, const DenseRow* dr
 template <class V>
 struct SlabB {
   const int64_t* prow;
-  const int32_t* pcol;
+  const int32_t* pbit;  // symbolic bitmap codes (slab_bit_code) of the entries
   const ColV<V>* pcv;
   const int32_t* rpt;
   int64_t nb;
@@ -439,8 +450,7 @@ SG_DEV void pin_loaded(T& v) {
 // that starts inside the block marks its start in the wavefront's 64*U-bit
 // mask, and q's owner is a plus the starts at or below q - qb.  The round
 // then issues its U loads of src together and fetch(slot, loaded element)
-// makes each product.  ok[u] tells which pp[u]
-// hold one.
+// makes each product.  ok[u] tells which pp[u] hold one.
 template <int BS, int U, class V, class R, class Fetch, class P>
 SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch, P* pp,
                        bool* ok) {
@@ -510,8 +520,11 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
 }
 
 // Flattened walk over the chunk's `total` products: wavefront w takes the
-// blocks w, w + NW, ... and folds each product with apply(product).
-template <int BS, int U, class V, class R, class Fetch, class Apply>
+// blocks w, w + NW, ... and folds each product with apply(product).  With
+// kRepeat, applying a product twice equals applying it once (a bitmap or, a
+// minimum), so lanes past the chunk's end apply the last product again
+// instead of branching.
+template <int BS, int U, class V, bool kRepeat, class R, class Fetch, class Apply>
 SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
   constexpr int64_t kBlock = (int64_t)kWave * U;
@@ -522,7 +535,7 @@ SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, 
     slab_round<BS, U, V>(L, nc, total, qb, src, fetch, pp, ok);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) apply(pp[u]);
+      if (kRepeat || ok[u]) apply(pp[u]);
   }
 }
 
@@ -530,12 +543,12 @@ SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, 
 // unless the caller already loaded the single chunk (`loaded`: nl slots,
 // total products).  The columns and A values of chunk c+1 are loaded while
 // chunk c is gathered, so a chunk waits for its segment bounds only.
-template <int BS, int U, class V, bool kVals, class R, class Fetch, class Apply>
+template <int BS, int U, class V, bool kVals, bool kRepeat, class R, class Fetch, class Apply>
 SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
                           int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int nl, int64_t total,
                           SrcLds<V, BS>& L, const R* src, Fetch& fetch, Apply& apply) {
   if (loaded) {
-    slab_iterate<BS, U, V>(L, nl, total, src, fetch, apply);
+    slab_iterate<BS, U, V, kRepeat>(L, nl, total, src, fetch, apply);
     return;
   }
   const int64_t tid = threadIdx.x;
@@ -556,7 +569,7 @@ SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_va
     block_sync();
     int ns;
     const int64_t tc = src_compact<V, kVals, BS>(L, st, len, av, &ns);
-    slab_iterate<BS, U, V>(L, ns, tc, src, fetch, apply);
+    slab_iterate<BS, U, V, kRepeat>(L, ns, tc, src, fetch, apply);
   }
 }
 
@@ -572,43 +585,57 @@ template <int BS>
 __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
                                                  Bins bins, int32_t S, int32_t* off2, int32_t* ctr) {
   constexpr int NW = BS / kWave;
-  __shared__ uint32_t s_bm[kSlabWordsMax];
+  constexpr int kTilesPerWave = (kSlabTilesMax + NW - 1) / NW;
+  static_assert(kTileWords == kWave * 8, "a lane counts 8 words of a tile");
+  __shared__ __align__(16) uint32_t s_bm[kSlabWordsMax];
   __shared__ SrcLds<uint8_t, BS> L;
   const int T = b.T, G = b.G;
   const int nwords = G * kTileWords;
   for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
   const int64_t nd = dense_rows(bins);
-  const uint32_t cmax = (uint32_t)nwords * 32u;
   for_each_queued(ctr, kListSymSlab, nd * S, &L.slot, [&](int64_t g) {
     const int32_t s = (int32_t)(g / nd);
     const int64_t h = g - (int64_t)s * nd;
     const DenseRow d = dr[h];
     const int ts0 = s * G;
-    const int64_t c0 = (int64_t)ts0 << kTileLog;
-    auto fetch = [&](int, int32_t c) { return (int32_t)(c - c0); };
-    // only each tile's count of distinct columns is needed, so columns are
-    // interleaved over the tile's words (column x of a tile: word x mod 512,
-    // bit x / 512): neighbouring columns, which the lanes of a round mostly
-    // hold, land in different words and LDS banks
-    auto apply = [&](int32_t c) {
-      if ((uint32_t)c < cmax)
-        atomicOr(&s_bm[(c >> kTileLog) * kTileWords + (c & (kTileWords - 1))],
-                 1u << ((c & (kTile - 1)) >> (kTileLog - 5)));
+    // the partition holds each entry's bitmap code (slab_bit_code): only
+    // each tile's count of distinct columns is needed, and with a tile's
+    // columns interleaved over its words, neighbouring columns, which the
+    // lanes of a round mostly hold, land in different words and LDS banks
+    auto fetch = [&](int, int32_t code) { return code; };
+    auto apply = [&](int32_t code) {
+      atomicOr(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s_bm) + (code >> 5)), 1u << (code & 31));
     };
-    slab_products<BS, kSlabU, uint8_t, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pcol,
+    slab_products<BS, kSlabU, uint8_t, false, true>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pbit,
                                               fetch, apply);
     block_sync();
+    // per-tile counts: wavefront w takes tiles w, w + NW, ..., lane l the 8
+    // words [8l, 8l + 8) of each (two 16-byte reads); all reads are issued
+    // before the first count, and the words are cleared for the next task
     int32_t* o2 = off2 + h * (T + 1);
-    for (int tl = wave_id(); tl < G; tl += NW) {
-      int32_t c = 0;
-      for (int x = lane_id(); x < kTileWords; x += kWave) {
-        const int wx = tl * kTileWords + x;
-        c += __popc(s_bm[wx]);
-        s_bm[wx] = 0u;
+    uint4* bm4 = reinterpret_cast<uint4*>(s_bm);
+    uint4 q[kTilesPerWave][2];
+#pragma unroll
+    for (int i = 0; i < kTilesPerWave; ++i) {
+      const int tl = wave_id() + i * NW;
+      if (tl < G) {
+        q[i][0] = bm4[(tl * kTileWords + lane_id() * 8) / 4];
+        q[i][1] = bm4[(tl * kTileWords + lane_id() * 8) / 4 + 1];
       }
-      c = wave_sum(c);
-      const int t = ts0 + tl;
-      if (lane_id() == 0 && t < T) o2[t] = c;
+    }
+#pragma unroll
+    for (int i = 0; i < kTilesPerWave; ++i) {
+      const int tl = wave_id() + i * NW;
+      if (tl < G) {
+        const int32_t c = wave_sum((int32_t)(__popc(q[i][0].x) + __popc(q[i][0].y) + __popc(q[i][0].z) +
+                                             __popc(q[i][0].w) + __popc(q[i][1].x) + __popc(q[i][1].y) +
+                                             __popc(q[i][1].z) + __popc(q[i][1].w)));
+        const uint4 z{0u, 0u, 0u, 0u};
+        bm4[(tl * kTileWords + lane_id() * 8) / 4] = z;
+        bm4[(tl * kTileWords + lane_id() * 8) / 4 + 1] = z;
+        const int t = ts0 + tl;
+        if (lane_id() == 0 && t < T) o2[t] = c;
+      }
     }
   });
 }
@@ -647,7 +674,6 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     const int64_t cw0 = (int64_t)tk.t0 << kTileLog;
     const int nwords = (tk.t1 - tk.t0) * kTileWords;
     const int wpw = nwords / NW;
-    const uint32_t cmax = (uint32_t)nwords * 32u;
     const bool one = tk.nsrc <= BS;
     int64_t total = 0;
     int nl = 0;
@@ -656,28 +682,31 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     // With one round of products per wavefront the products stay in
     // registers for pass 2; otherwise pass 2 gathers them again.
     const bool held = one && total <= (int64_t)NW * kWave * kSlabU;
+    // a window column c lies below nwords*32; the word index is masked to
+    // the bitmap all the same, so that no partition content can reach
+    // beyond it
     auto f1 = [&](int, const ColV<V>& e) { return (int32_t)(e.c - cw0); };
-    auto a1 = [&](int32_t c) {
-      if ((uint32_t)c < cmax) atomicOr(&s_bits[c >> 5], 1u << (c & 31));
-    };
+    auto a1 = [&](int32_t c) { atomicOr(&s_bits[(c >> 5) & (kSlabWordsMax - 1)], 1u << (c & 31)); };
     auto f2 = [&](int ow, const ColV<V>& e) { return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)}; };
     auto a2 = [&](const ColVal<Acc>& p) {
-      if ((uint32_t)p.c >= cmax) return;
-      const int w = p.c >> 5;
+      const int w = (p.c >> 5) & (kSlabWordsMax - 1);
       const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
       if (r < m) Sr::lds_acc(&s_val[r], p.v);
     };
     ColVal<Acc> pp[kSlabU];
     bool ok[kSlabU];
+    // a held round that is not empty repeats its last product in the lanes
+    // past the end, which idempotent folds may apply again
+    const bool hround = (int64_t)wv * kWave * kSlabU < total;
     // pass 1: the window's column set
     if (held) {
       slab_round<BS, kSlabU, V>(L, nl, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
+      if (hround)
 #pragma unroll
-      for (int u = 0; u < kSlabU; ++u)
-        if (ok[u]) a1(pp[u].c);
+        for (int u = 0; u < kSlabU; ++u) a1(pp[u].c);
     } else {
-      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L, b.pcv,
-                                         f1, a1);
+      slab_products<BS, kSlabU, V, true, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L,
+                                               b.pcv, f1, a1);
     }
     block_sync();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lane l the kpl
@@ -716,10 +745,10 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     if (held) {
 #pragma unroll
       for (int u = 0; u < kSlabU; ++u)
-        if (ok[u]) a2(pp[u]);
+        if (Sr::kIdempotent ? hround : ok[u]) a2(pp[u]);
     } else {
-      slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L, b.pcv,
-                                         f2, a2);
+      slab_products<BS, kSlabU, V, true, Sr::kIdempotent>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one,
+                                                          nl, total, L, b.pcv, f2, a2);
     }
     block_sync();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
@@ -809,10 +838,11 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
     for (int t = ts0; t < ts1; ++t) {
       const int32_t rel = s_tc[t - ts0], mt = s_tc[t + 1 - ts0] - rel;
       if (mt <= 0) continue;
-      const int64_t cw0 = (int64_t)t << kTileLog;
-      auto f = [&](int ow, const ColV<V>& e) { return ColVal<Acc>{(int32_t)(e.c - cw0), Sr::mul(L.a[ow], e.v)}; };
+      const int32_t cw0 = t << kTileLog;
+      // the tile's products: column within the tile (tiles are aligned, so
+      // the low bits; masking also bounds any partition content)
+      auto f = [&](int ow, const ColV<V>& e) { return ColVal<Acc>{e.c & (kTile - 1), Sr::mul(L.a[ow], e.v)}; };
       auto ap = [&](const ColVal<Acc>& p) {
-        if ((uint32_t)p.c >= (uint32_t)kTile) return;
         Sr::lds_acc(&s_acc[p.c], p.v);
         if constexpr (!Sr::kValueMarks) atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
       };
@@ -831,10 +861,10 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
         int nl;
         const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
-        slab_iterate<BS, kSlabU, V>(L, nl, total, b.pcv, f, ap);
+        slab_iterate<BS, kSlabU, V, Sr::kIdempotent>(L, nl, total, b.pcv, f, ap);
       } else {
-        slab_products<BS, kSlabU, V, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false, false,
-                                           0, 0, L, b.pcv, f, ap);
+        slab_products<BS, kSlabU, V, true, Sr::kIdempotent>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
+                                                            false, false, 0, 0, L, b.pcv, f, ap);
       }
       block_sync();
       // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and
