@@ -318,7 +318,8 @@ template <int BS, int U, class Src, class Fetch, class Apply>
 SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s_item, int64_t* s_start,
                              int64_t* s_off, int64_t* s_wave, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
-  static_assert(BS < (1 << 16) && BS <= kWave * kWave, "slot counts in 16 bits; two search levels");
+  static_assert(BS < (1 << 16) && (((BS + kWave - 1) / kWave) | 1) <= kWave / 2,
+                "slot counts in 16 bits; two search levels of half a wavefront");
   using P = decltype(fetch(s_item[0], (int64_t)0));
   const int lane = lane_id();
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
@@ -350,7 +351,8 @@ SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s
     // searches come first, then all U fetches (their loads in flight
     // together), then the applies.
     constexpr int64_t kBlock = (int64_t)kWave * U;
-    const int stride = (nc + kWave - 1) / kWave;
+    // odd, so that the lanes' 8-byte offset reads spread over all LDS banks
+    const int stride = ((nc + kWave - 1) / kWave) | 1;
     for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
       const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
       int a, e;

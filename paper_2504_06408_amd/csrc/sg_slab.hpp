@@ -455,7 +455,7 @@ template <int BS, int U, class V, class R, class Fetch, class P>
 SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch, P* pp,
                        bool* ok) {
   static_assert(U <= kRoundRowsMax, "round mask rows");
-  static_assert(BS <= kWave * kWave, "two search levels cover the slots");
+  static_assert(BS <= kWave * (kWave - 1), "two search levels cover the slots");
   constexpr int64_t kBlock = (int64_t)kWave * U;
   if (qb >= total) {
 #pragma unroll
@@ -466,7 +466,9 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
   const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
   int a;
   {
-    const int stride = (nc + kWave - 1) / kWave;
+    // an odd stride spreads the 8-byte offsets the lanes read over all LDS
+    // banks (an even one puts 32 lanes on 32 / gcd banks)
+    const int stride = ((nc + kWave - 1) / kWave) | 1;
     const int i1 = lane * stride;
     const int c1 = __popcll(__ballot(i1 < nc && L.off[i1] <= qb));
     const int b2 = (c1 - 1) * stride, i2 = b2 + lane;
@@ -609,9 +611,10 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
     slab_products<BS, kSlabU, uint8_t, false, true>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pbit,
                                               fetch, apply);
     block_sync();
-    // per-tile counts: wavefront w takes tiles w, w + NW, ..., lane l the 8
-    // words [8l, 8l + 8) of each (two 16-byte reads); all reads are issued
-    // before the first count, and the words are cleared for the next task
+    // per-tile counts: wavefront w takes tiles w, w + NW, ..., lane l the
+    // words [4l, 4l + 4) and [256 + 4l, 256 + 4l + 4) of each (two 16-byte
+    // reads, consecutive over the lanes); all reads are issued before the
+    // first count, and the words are cleared for the next task
     int32_t* o2 = off2 + h * (T + 1);
     uint4* bm4 = reinterpret_cast<uint4*>(s_bm);
     uint4 q[kTilesPerWave][2];
@@ -619,8 +622,8 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
     for (int i = 0; i < kTilesPerWave; ++i) {
       const int tl = wave_id() + i * NW;
       if (tl < G) {
-        q[i][0] = bm4[(tl * kTileWords + lane_id() * 8) / 4];
-        q[i][1] = bm4[(tl * kTileWords + lane_id() * 8) / 4 + 1];
+        q[i][0] = bm4[tl * (kTileWords / 4) + lane_id()];
+        q[i][1] = bm4[tl * (kTileWords / 4) + kWave + lane_id()];
       }
     }
 #pragma unroll
@@ -631,8 +634,8 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
                                              __popc(q[i][0].w) + __popc(q[i][1].x) + __popc(q[i][1].y) +
                                              __popc(q[i][1].z) + __popc(q[i][1].w)));
         const uint4 z{0u, 0u, 0u, 0u};
-        bm4[(tl * kTileWords + lane_id() * 8) / 4] = z;
-        bm4[(tl * kTileWords + lane_id() * 8) / 4 + 1] = z;
+        bm4[tl * (kTileWords / 4) + lane_id()] = z;
+        bm4[tl * (kTileWords / 4) + kWave + lane_id()] = z;
         const int t = ts0 + tl;
         if (lane_id() == 0 && t < T) o2[t] = c;
       }
