@@ -277,8 +277,10 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
     const bool slab = r.mode == kModeProduct && h->slab;
     const bool tiles = !slab && r.mode == kModeProduct && r.T > 1;
     if (tiles) SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
-    SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
+    // the slab path keeps span counts after the tile offsets
+    SG_HIP(h, h->off2_buf.ensure(slab ? off2_span_bytes(nd, r.T) : sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
     off2 = (int32_t*)h->off2_buf.p;
+    if (slab) r.spn = (uint4*)((char*)h->off2_buf.p + span_offset(nd, r.T));
     mk.mark(kPhSymBounds, 1);
     if (tiles) {
       r.rp2 = (const int32_t*)h->rp2_buf.p;
@@ -347,8 +349,13 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
       }
       r.rp2 = (const int32_t*)h->rp2_buf.p;
     }
+    if (slab) {
+      SG_HIP(h, h->off2_buf.ensure(off2_span_bytes(nd, r.T)));
+      r.spn = (uint4*)((char*)h->off2_buf.p + span_offset(nd, r.T));
+    }
     if (!cached) {
-      SG_HIP(h, h->off2_buf.ensure(sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
+      SG_HIP(h, h->off2_buf.ensure(slab ? off2_span_bytes(nd, r.T)
+                                        : sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
       int64_t* scratch = ar.take<int64_t>(n);
       launch_symbolic_dense(r, plan, scratch, (int32_t*)h->off2_buf.p, h->cus, st);
       h->cache_valid = false;  // off2 now belongs to this call's inputs only
@@ -361,6 +368,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.plan = plan;
   c.C = OutC{C->rowptr, C->col, C->val};
   c.off2 = (const int32_t*)h->off2_buf.p;
+  c.spn = r.spn;
   c.err = h->d_flags;
   c.task_ctr = h->d_flags + kCtrBase;
   c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;

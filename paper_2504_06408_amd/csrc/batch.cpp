@@ -154,8 +154,10 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
   std::memcpy(bp.count, hp, sizeof(bp.count));
   S.nd = bp.ndense();
   bp.bins = Bins{S.list, S.bin_start, S.bin_count, S.nd};
-  SG_HIP(h, S.off2_buf.ensure(sizeof(int32_t) * (size_t)(S.nd > 0 ? S.nd : 1) * (size_t)(S.src.T + 1)));
   if (S.slab && S.nd > 0) {
+    // the slab path keeps span counts after the tile offsets
+    SG_HIP(h, S.off2_buf.ensure(off2_span_bytes(S.nd, S.src.T)));
+    S.src.spn = (uint4*)((char*)S.off2_buf.p + span_offset(S.nd, S.src.T));
     // structure once (patterns do not change after planning); values are
     // re-scattered by every replay
     SG_HIP(h, S.spart.ensure(sizeof(int64_t) * (slab_partials(h, S.src) + 1)));
@@ -165,6 +167,8 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
   } else {
     S.slab = false;
     S.src.S = 0;
+    S.src.spn = nullptr;
+    SG_HIP(h, S.off2_buf.ensure(sizeof(int32_t) * (size_t)(S.nd > 0 ? S.nd : 1) * (size_t)(S.src.T + 1)));
   }
   SG_HIP(h, S.task_buf.ensure(S.task_bytes()));
   if (S.nd > 0 && has_dense_inputs)
@@ -221,6 +225,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   c.plan = bp;
   c.C = OutC{S.off, (int32_t*)S.col_buf.p, S.val_buf.p};
   c.off2 = (const int32_t*)S.off2_buf.p;
+  c.spn = S.src.spn;
   c.err = P->d_flag + 1;
   c.task_ctr = P->d_flag + kCtrBase;
   c.task_cap = (int64_t)(S.nd > 0 ? S.nd : 1) * S.src.T;

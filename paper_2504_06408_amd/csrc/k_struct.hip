@@ -182,7 +182,7 @@ void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t
   static int occ = occupancy(k, BS);
   const int grid = cus * occ > kQueues ? cus * occ : kQueues;
   marks.mark(kPhSymDenseBitmap, 1);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, b, r.drow, r.a_col, plan.bins, r.S, off2, r.qctr);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, b, r.drow, r.a_col, plan.bins, r.S, off2, r.spn, r.qctr);
   marks.mark(kPhSymDenseBitmap, 0);
   hipLaunchKernelGGL(k_off2_finish<256>, dim3(grid_for(nd, 4, cus * 16)), dim3(256), 0, st, plan.bins, r.drow, off2,
                      r.T, cnt_out);

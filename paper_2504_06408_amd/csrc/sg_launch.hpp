@@ -45,6 +45,7 @@ struct RowSource {
   const void* pval;       // numeric partition: (column, value) pairs (ColV)
   const int32_t* rpt;     // tile offsets inside each slab segment
   const DenseRow* drow;   // per dense row: its A row
+  uint4* spn;             // span counts of the dense rows' tiles (after off2 in its buffer)
   int32_t ls, S;
   int32_t* qctr;  // counter block (kCtrInts ints) of the slab symbolic pass
 };
@@ -80,6 +81,7 @@ struct NumCtx {
   BinPlan plan;
   OutC C;
   const int32_t* off2;
+  const uint4* spn;  // span counts of the slab path's tiles (after off2)
   int32_t* err;
   int32_t* task_ctr;  // counter block of kCtrInts ints (list totals, queue cursors)
   Task* tasks;        // tile, range and slab task lists of task_cap entries each
@@ -224,8 +226,8 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
         static int occ = occupancy(k, 512);
         const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
         c.marks.mark(kPhNumDenseTiles, 1);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.off2, c.C,
-                           (const SlabTask*)heavy, (const int32_t*)book_off(sbook, T, kListTile), nd, c.task_ctr,
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.off2, c.spn,
+                           c.C, (const SlabTask*)heavy, (const int32_t*)book_off(sbook, T, kListTile), nd, c.task_ctr,
                            c.err);
         c.marks.mark(kPhNumDenseTiles, 0);
       }

@@ -34,6 +34,20 @@ constexpr int kSlabLogMax = 17;
 constexpr int kSlabWordsMax = 1 << (kSlabLogMax - 5);
 constexpr int kSlabTilesMax = 1 << (kSlabLogMax - kTileLog);
 
+// Span counts: for every (dense row, tile) whose entry count reaches
+// kSpanMin, the symbolic slab pass also records the entries in each of the
+// tile's kSpans spans of kTile / kSpans columns (uint16 each, 16 bytes per
+// tile), so that the heavy numeric kernel, whose wavefronts each compact one
+// span, knows every wavefront's output offset without counting first.  They
+// follow the per-row tile offsets (nd * (T + 1) int32) in the same buffer.
+constexpr int kSpans = 8;
+constexpr int kSpanLog = kTileLog - 3;  // 2048 columns
+constexpr int32_t kSpanMin = 1024;
+inline size_t span_offset(int64_t nd, int32_t T) { return ((size_t)nd * (size_t)(T + 1) * 4 + 15) & ~(size_t)15; }
+inline size_t off2_span_bytes(int64_t nd, int32_t T) {
+  return span_offset(nd, T) + (size_t)nd * (size_t)T * kSpans * sizeof(uint16_t);
+}
+
 // One entry of the numeric partition of B: column id and value side by side,
 // so a product is one load (8 bytes, or 16 for 8-byte values).
 template <class V>
@@ -585,7 +599,7 @@ constexpr int kSlabU = 8;
 // raw to off2[h*(T+1) + t]; k_off2_finish turns them into per-row offsets.
 template <int BS>
 __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
-                                                 Bins bins, int32_t S, int32_t* off2, int32_t* ctr) {
+                                                 Bins bins, int32_t S, int32_t* off2, uint4* spn, int32_t* ctr) {
   constexpr int NW = BS / kWave;
   constexpr int kTilesPerWave = (kSlabTilesMax + NW - 1) / NW;
   static_assert(kTileWords == kWave * 8, "a lane counts 8 words of a tile");
@@ -633,10 +647,32 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
         const int32_t c = wave_sum((int32_t)(__popc(q[i][0].x) + __popc(q[i][0].y) + __popc(q[i][0].z) +
                                              __popc(q[i][0].w) + __popc(q[i][1].x) + __popc(q[i][1].y) +
                                              __popc(q[i][1].z) + __popc(q[i][1].w)));
+        const int t = ts0 + tl;
+        if (spn != nullptr && c >= kSpanMin && t < T) {
+          // span k holds bits [4k, 4k + 4) of every word: nibble popcounts
+          // (SWAR), summed per lane in bytes (at most 32), widened to 16-bit
+          // fields for the wavefront sums (at most 2048)
+          uint32_t ev = 0u, od = 0u;
+          const uint32_t wds[8] = {q[i][0].x, q[i][0].y, q[i][0].z, q[i][0].w,
+                                   q[i][1].x, q[i][1].y, q[i][1].z, q[i][1].w};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            uint32_t x = wds[k] - ((wds[k] >> 1) & 0x55555555u);
+            x = (x & 0x33333333u) + ((x >> 2) & 0x33333333u);
+            ev += x & 0x0F0F0F0Fu;
+            od += (x >> 4) & 0x0F0F0F0Fu;
+          }
+          const uint32_t s04 = (uint32_t)wave_sum((int32_t)(ev & 0x00FF00FFu));         // spans 0 | 4
+          const uint32_t s26 = (uint32_t)wave_sum((int32_t)((ev >> 8) & 0x00FF00FFu));  // spans 2 | 6
+          const uint32_t s15 = (uint32_t)wave_sum((int32_t)(od & 0x00FF00FFu));         // spans 1 | 5
+          const uint32_t s37 = (uint32_t)wave_sum((int32_t)((od >> 8) & 0x00FF00FFu));  // spans 3 | 7
+          if (lane_id() == 0)
+            spn[h * T + t] = uint4{(s04 & 0xFFFFu) | (s15 << 16), (s26 & 0xFFFFu) | (s37 << 16),
+                                   (s04 >> 16) | (s15 & 0xFFFF0000u), (s26 >> 16) | (s37 & 0xFFFF0000u)};
+        }
         const uint4 z{0u, 0u, 0u, 0u};
         bm4[tl * (kTileWords / 4) + lane_id()] = z;
         bm4[tl * (kTileWords / 4) + kWave + lane_id()] = z;
-        const int t = ts0 + tl;
         if (lane_id() == 0 && t < T) o2[t] = c;
       }
     }
@@ -787,14 +823,17 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
 // identity as they are compacted; for semirings whose identity no product
 // reaches (kValueMarks) occupancy is read off the accumulator, otherwise an
 // occupancy bitmap is kept.  8-byte accumulators fill 128 KB of LDS: one
-// workgroup per CU.
+// workgroup per CU.  Wavefront w compacts span w of the tile; where the
+// symbolic pass recorded the tile's span counts they give each wavefront its
+// output offset, otherwise the wavefronts count their spans first.
 template <class Sr, class V, int BS>
 __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_num_slab_heavy(
-    SlabB<V> b, const int32_t* a_col, const V* a_val, const int32_t* off2, OutC C, const SlabTask* tasks,
-    const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
+    SlabB<V> b, const int32_t* a_col, const V* a_val, const int32_t* off2, const uint4* spn, OutC C,
+    const SlabTask* tasks, const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
   constexpr int NW = BS / kWave;
   constexpr int kSpan = kTile / NW;  // accumulator slots compacted per wavefront
   static_assert(kSpan % kWave == 0, "whole steps of 64 slots per wavefront");
+  static_assert(NW == kSpans, "one symbolic span per wavefront");
   using Acc = typename Sr::Acc;
   __shared__ Acc s_acc[kTile];
   __shared__ uint32_t s_bm[Sr::kValueMarks ? 1 : kTileWords];
@@ -841,6 +880,9 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
     for (int t = ts0; t < ts1; ++t) {
       const int32_t rel = s_tc[t - ts0], mt = s_tc[t + 1 - ts0] - rel;
       if (mt <= 0) continue;
+      const bool spans = spn != nullptr && mt >= kSpanMin;
+      uint4 sp{0u, 0u, 0u, 0u};
+      if (spans) sp = spn[(int64_t)tk.h * T + t];
       const int32_t cw0 = t << kTileLog;
       // the tile's products: column within the tile (tiles are aligned, so
       // the low bits; masking also bounds any partition content)
@@ -875,24 +917,33 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
       // the occupied slots gives each lane its output rank, so the stores of
       // a step are contiguous.  Slots are reset as they are read.
       const int sb = wv * kSpan;
-      int32_t cnt;
-      if constexpr (Sr::kValueMarks) {
-        cnt = 0;
-#pragma unroll 8
-        for (int j = 0; j < kSpan; j += kWave)
-          cnt += __popcll(__ballot(s_acc[sb + j + lane_id()] != Sr::ident()));
-      } else {
-        static_assert(kSpan == 32 * kWave, "one bitmap word per lane");
-        cnt = wave_sum((int32_t)__popc(s_bm[(sb >> 5) + lane_id()]));
-      }
-      if (lane_id() == 0) s_wave32[wv] = cnt;
-      block_sync();
-      int32_t base = 0, tot = 0;
+      int32_t cnt = 0, base = 0, tot = 0;
+      if (spans) {
+        const uint32_t pk[4] = {sp.x, sp.y, sp.z, sp.w};  // span 2i | span 2i+1 << 16
 #pragma unroll
-      for (int u = 0; u < NW; ++u) {
-        const int32_t v = s_wave32[u];
-        base += u < wv ? v : 0;
-        tot += v;
+        for (int u = 0; u < NW; ++u) {
+          const int32_t v = (int32_t)((pk[u >> 1] >> (16 * (u & 1))) & 0xFFFFu);
+          base += u < wv ? v : 0;
+          cnt = u == wv ? v : cnt;
+          tot += v;
+        }
+      } else {
+        if constexpr (Sr::kValueMarks) {
+#pragma unroll 8
+          for (int j = 0; j < kSpan; j += kWave)
+            cnt += __popcll(__ballot(s_acc[sb + j + lane_id()] != Sr::ident()));
+        } else {
+          static_assert(kSpan == 32 * kWave, "one bitmap word per lane");
+          cnt = wave_sum((int32_t)__popc(s_bm[(sb >> 5) + lane_id()]));
+        }
+        if (lane_id() == 0) s_wave32[wv] = cnt;
+        block_sync();
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+          const int32_t v = s_wave32[u];
+          base += u < wv ? v : 0;
+          tot += v;
+        }
       }
       // output pointers of the wavefront's first entry: lanes store at 32-bit
       // offsets from a uniform base
@@ -926,6 +977,8 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
       }
       if constexpr (!Sr::kValueMarks) s_bm[(sb >> 5) + lane_id()] = 0u;
+      // the symbolic and numeric passes must agree on every span
+      if (lane_id() == 0 && run != (uint32_t)cnt) atomicOr(err, 1);
       if (threadIdx.x == 0 && tot != mt) atomicOr(err, 1);
       block_sync();
     }
