@@ -178,7 +178,8 @@ inline void launch_num_hash_all(const Rows& rows, const NumCtx& c, int bin0, hip
   launch_num_hash_one<Sr, Rows, 10, 256>(rows, c, bin0 + 3, st);
   launch_num_hash_one<Sr, Rows, 11, 512>(rows, c, bin0 + 4, st);
   launch_num_hash_one<Sr, Rows, 12, 512>(rows, c, bin0 + 5, st);
-  launch_num_hash_one<Sr, Rows, 13, 512>(rows, c, bin0 + 6, st);
+  // the largest table with 4-byte accumulators leaves LDS for 1024 threads
+  launch_num_hash_one<Sr, Rows, 13, sizeof(typename Sr::Acc) <= 4 ? 1024 : 512>(rows, c, bin0 + 6, st);
 }
 
 // Dense rows: build the tile and range task lists from the per-tile counts,
