@@ -41,8 +41,8 @@ constexpr int kSlabTilesMax = 1 << (kSlabLogMax - kTileLog);
 // span, knows every wavefront's output offset without counting first.  They
 // follow the per-row tile offsets (nd * (T + 1) int32) in the same buffer.
 constexpr int kSpans = 8;
-constexpr int kSpanLog = kTileLog - 3;  // 2048 columns
 constexpr int32_t kSpanMin = 1024;
+static_assert(kTile / kSpans == 4 * kTileWords, "a span is four bits of every word of the interleaved bitmap");
 inline size_t span_offset(int64_t nd, int32_t T) { return ((size_t)nd * (size_t)(T + 1) * 4 + 15) & ~(size_t)15; }
 inline size_t off2_span_bytes(int64_t nd, int32_t T) {
   return span_offset(nd, T) + (size_t)nd * (size_t)T * kSpans * sizeof(uint16_t);
