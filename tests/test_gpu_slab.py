@@ -118,3 +118,25 @@ def test_many_sources_per_row(h, sr):
     A = with_vals(synth.er(24, 2000, 700, 230), sr, 231)
     B = _hstack([synth.er(2000, 16384, 40, 232), synth.er(2000, 300000, 6, 233)], sr, 234)
     check_product(h, sr, A, B, what="many sources")
+
+
+@pytest.mark.parametrize("sr", ALL)
+def test_heavy_tile_span_counts(h, sr):
+    """One dense row over 2^20 columns whose first slab is heavy for every
+    semiring (34,815 entries).  Tile 0 is full (2048 entries in each of its
+    eight 2048-column spans, the largest span count), tile 1 holds exactly
+    1024 entries, all in its last span (the least count for which the
+    symbolic pass records span counts), tile 2 holds 1023 (heavy tasks count
+    such a tile themselves), tile 3 is full.  A second source repeats every
+    third column, so entries also fold two products."""
+    _reset(h)
+    c0 = np.concatenate([np.arange(16384), 16384 + 14336 + np.arange(1024), 32768 + 2 * np.arange(1023),
+                         49152 + np.arange(16384)]).astype(np.int32)
+    c1 = c0[::3]
+    B = synth.CSR(2, 1 << 20, np.array([0, c0.size, c0.size + c1.size], np.int64), np.concatenate([c0, c1]),
+                  np.zeros(c0.size + c1.size, np.float64))
+    B = with_vals(B, sr, 240)
+    A = with_vals(synth.CSR(1, 2, np.array([0, 2], np.int64), np.array([0, 1], np.int32), np.zeros(2)), sr, 241)
+    check_product(h, sr, A, B, what="heavy span counts")
+    st = h.stats()
+    assert st["tile_tasks"] == 1 and st["tile_entries"] == c0.size, st
