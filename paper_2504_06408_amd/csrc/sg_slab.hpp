@@ -367,7 +367,7 @@ struct SrcLds {
   V a[BS];
   int64_t st[BS], off[BS], wave[BS / kWave];
   int32_t boff[kBoffCache + 1];
-  uint32_t rb[BS / kWave][2 * kRoundRowsMax];  // per wavefront: slot starts inside its round
+  alignas(16) uint32_t rb[BS / kWave][2 * kRoundRowsMax];  // per wavefront: slot starts inside its round
   int64_t slot;
 };
 
@@ -503,9 +503,16 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
     if (__ballot(in) != ~0ull) break;
   }
   __builtin_amdgcn_wave_barrier();
+  // the mask rows, two per 16-byte read
+  static_assert(U % 2 == 0, "mask rows read in pairs");
   unsigned long long w[U];
+  const uint4* rb4 = reinterpret_cast<const uint4*>(rb);
 #pragma unroll
-  for (int u = 0; u < U; ++u) w[u] = (unsigned long long)rb[2 * u] | ((unsigned long long)rb[2 * u + 1] << 32);
+  for (int u = 0; u < U; u += 2) {
+    const uint4 q = rb4[u / 2];
+    w[u] = (unsigned long long)q.x | ((unsigned long long)q.y << 32);
+    w[u + 1] = (unsigned long long)q.z | ((unsigned long long)q.w << 32);
+  }
   // products of the block: lane's row u holds product qb + u*64 + lane,
   // owned by slot a plus the starts marked at bits below its position (the
   // bits below the lane in its row: mbcnt); lanes past the chunk's end take
