@@ -546,7 +546,8 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
 // blocks w, w + NW, ... and folds each product with apply(product).  With
 // kRepeat, applying a product twice equals applying it once (a bitmap or, a
 // minimum), so lanes past the chunk's end apply the last product again
-// instead of branching.
+// instead of branching.  Those repeats all hit one LDS word, and atomics on
+// one address serialize: worth it only where LDS is not the limit.
 template <int BS, int U, class V, bool kRepeat, class R, class Fetch, class Apply>
 SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
@@ -629,8 +630,8 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
     auto apply = [&](int32_t code) {
       atomicOr(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s_bm) + (code >> 5)), 1u << (code & 31));
     };
-    slab_products<BS, kSlabU, uint8_t, false, true>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L, b.pbit,
-                                              fetch, apply);
+    slab_products<BS, kSlabU, uint8_t, false, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L,
+                                                     b.pbit, fetch, apply);
     block_sync();
     // per-tile counts: wavefront w takes tiles w, w + NW, ..., lane l the
     // words [4l, 4l + 4) and [256 + 4l, 256 + 4l + 4) of each (two 16-byte
@@ -913,10 +914,10 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
         int nl;
         const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
-        slab_iterate<BS, kSlabU, V, Sr::kIdempotent>(L, nl, total, b.pcv, f, ap);
+        slab_iterate<BS, kSlabU, V, false>(L, nl, total, b.pcv, f, ap);
       } else {
-        slab_products<BS, kSlabU, V, true, Sr::kIdempotent>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
-                                                            false, false, 0, 0, L, b.pcv, f, ap);
+        slab_products<BS, kSlabU, V, true, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false,
+                                                  false, 0, 0, L, b.pcv, f, ap);
       }
       block_sync();
       // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and
