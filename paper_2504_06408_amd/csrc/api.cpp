@@ -145,6 +145,8 @@ sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B,
   r.rpt = (const int32_t*)sb.rpt.p;
   r.prow = (const int64_t*)sb.prow.p;
   r.pbit = (const int32_t*)sb.pbit.p;
+  // 32-bit gathers need the bitmap-code array (4 bytes per entry) below 4 GiB
+  r.gather32 = h->gather32 && B->nnz < ((int64_t)1 << 30);
   r.pval = vals ? sb.pcv.p : nullptr;
   r.ls = ls;
   r.S = S;
@@ -437,6 +439,9 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
   } else if (n == "dense_slab") {
     if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "dense_slab must be 0 or 1");
     h->slab = v == "1";
+  } else if (n == "gather32") {
+    if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "gather32 must be 0 or 1");
+    h->gather32 = v == "1";
   } else if (n == "force_path") {
     if (v == "auto") h->force = kForceAuto;
     else if (v == "small") h->force = kForceSmall;

@@ -178,8 +178,8 @@ void sym_slab(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, int32_t
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, r.qctr, (int64_t)kCtrInts,
                      (int32_t)0);
   constexpr int BS = 256;
-  auto k = k_sym_slab<BS>;
-  static int occ = occupancy(k, BS);
+  auto k = r.gather32 ? k_sym_slab<BS, true> : k_sym_slab<BS, false>;
+  static int occ = occupancy(k_sym_slab<BS, true>, BS);
   const int grid = cus * occ > kQueues ? cus * occ : kQueues;
   marks.mark(kPhSymDenseBitmap, 1);
   hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, b, r.drow, r.a_col, plan.bins, r.S, off2, r.spn, r.qctr);

@@ -96,6 +96,7 @@ struct sg_handle {
   SgBuf p_buf, nt_buf;       // per-row products and terms from symbolic, reused to re-bin numeric
   SlabBufs sb;               // column-slab partition of B and the dense-row table
   int slab = 1;              // dense rows of single products use the column-slab path
+  int gather32 = 1;          // slab symbolic gathers at 32-bit offsets where B allows
   int32_t tile_min = sg::kTileMinDefault;
   std::vector<sg::PartDesc> parts_host;
   bool cache_valid = false;

@@ -46,6 +46,7 @@ struct RowSource {
   const int32_t* rpt;     // tile offsets inside each slab segment
   const DenseRow* drow;   // per dense row: its A row
   uint4* spn;             // span counts of the dense rows' tiles (after off2 in its buffer)
+  bool gather32;          // the symbolic slab pass may gather at 32-bit offsets
   int32_t ls, S;
   int32_t* qctr;  // counter block (kCtrInts ints) of the slab symbolic pass
 };

@@ -465,7 +465,7 @@ SG_DEV void pin_loaded(T& v) {
 // mask, and q's owner is a plus the starts at or below q - qb.  The round
 // then issues its U loads of src together and fetch(slot, loaded element)
 // makes each product.  ok[u] tells which pp[u] hold one.
-template <int BS, int U, class V, class R, class Fetch, class P>
+template <int BS, int U, class V, bool kNarrow, class R, class Fetch, class P>
 SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, const R* src, Fetch& fetch, P* pp,
                        bool* ok) {
   static_assert(U <= kRoundRowsMax, "round mask rows");
@@ -526,16 +526,35 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
     own[u] = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(w[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)w[u], 0u));
     cnt += __popcll(w[u]);
   }
-  int64_t idx[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) idx[u] = L.st[own[u]];
-#pragma unroll
-  for (int u = 0; u < U; ++u) idx[u] += qb + (ok[u] ? u * kWave + lane : lim - 1);
   using Bits = typename RawBits<sizeof(R)>::T;
-  const Bits* bsrc = reinterpret_cast<const Bits*>(src);
   Bits raw[U];
+  if constexpr (kNarrow) {
+    // the caller guarantees that src spans less than 4 GiB: a product's byte
+    // offset from src is then exact in 32-bit arithmetic (the partition
+    // index st + q is exact modulo 2^32), and each load is the uniform base
+    // plus one 32-bit offset
+    const char* base = reinterpret_cast<const char*>(src);
+    const uint32_t q0 = (uint32_t)qb;
+    uint32_t off[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) raw[u] = bsrc[idx[u]];
+    for (int u = 0; u < U; ++u) off[u] = (uint32_t)L.st[own[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = u * kWave + lane < lim - 1 ? u * kWave + lane : lim - 1;  // ok[u] ? position : last
+      off[u] = (off[u] + q0 + (uint32_t)x) * (uint32_t)sizeof(R);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) raw[u] = *reinterpret_cast<const Bits*>(base + off[u]);
+  } else {
+    int64_t idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) idx[u] = L.st[own[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) idx[u] += qb + (ok[u] ? u * kWave + lane : lim - 1);
+    const Bits* bsrc = reinterpret_cast<const Bits*>(src);
+#pragma unroll
+    for (int u = 0; u < U; ++u) raw[u] = bsrc[idx[u]];
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) pin_loaded(raw[u]);
 #pragma unroll
@@ -548,7 +567,7 @@ SG_DEV void slab_round(SrcLds<V, BS>& L, int nc, int64_t total, int64_t qb, cons
 // minimum), so lanes past the chunk's end apply the last product again
 // instead of branching.  Those repeats all hit one LDS word, and atomics on
 // one address serialize: worth it only where LDS is not the limit.
-template <int BS, int U, class V, bool kRepeat, class R, class Fetch, class Apply>
+template <int BS, int U, class V, bool kRepeat, bool kNarrow, class R, class Fetch, class Apply>
 SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, Fetch& fetch, Apply& apply) {
   constexpr int NW = BS / kWave;
   constexpr int64_t kBlock = (int64_t)kWave * U;
@@ -556,7 +575,7 @@ SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, 
   for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
     P pp[U];
     bool ok[U];
-    slab_round<BS, U, V>(L, nc, total, qb, src, fetch, pp, ok);
+    slab_round<BS, U, V, kNarrow>(L, nc, total, qb, src, fetch, pp, ok);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (kRepeat || ok[u]) apply(pp[u]);
@@ -567,12 +586,12 @@ SG_DEV void slab_iterate(SrcLds<V, BS>& L, int nc, int64_t total, const R* src, 
 // unless the caller already loaded the single chunk (`loaded`: nl slots,
 // total products).  The columns and A values of chunk c+1 are loaded while
 // chunk c is gathered, so a chunk waits for its segment bounds only.
-template <int BS, int U, class V, bool kVals, bool kRepeat, class R, class Fetch, class Apply>
+template <int BS, int U, class V, bool kVals, bool kRepeat, bool kNarrow, class R, class Fetch, class Apply>
 SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_val, int64_t a0, int32_t nsrc,
                           int32_t s, int32_t tr0, int32_t tr1, bool whole, bool loaded, int nl, int64_t total,
                           SrcLds<V, BS>& L, const R* src, Fetch& fetch, Apply& apply) {
   if (loaded) {
-    slab_iterate<BS, U, V, kRepeat>(L, nl, total, src, fetch, apply);
+    slab_iterate<BS, U, V, kRepeat, kNarrow>(L, nl, total, src, fetch, apply);
     return;
   }
   const int64_t tid = threadIdx.x;
@@ -593,7 +612,7 @@ SG_DEV void slab_products(const SlabB<V>& b, const int32_t* a_col, const V* a_va
     block_sync();
     int ns;
     const int64_t tc = src_compact<V, kVals, BS>(L, st, len, av, &ns);
-    slab_iterate<BS, U, V, kRepeat>(L, ns, tc, src, fetch, apply);
+    slab_iterate<BS, U, V, kRepeat, kNarrow>(L, ns, tc, src, fetch, apply);
   }
 }
 
@@ -605,7 +624,8 @@ constexpr int kSlabU = 8;
 // Task g = (slab s = g / nd, dense row h = g % nd), slab-major, from the
 // interleaved queues.  The per-tile popcounts of the slab's bitmap are written
 // raw to off2[h*(T+1) + t]; k_off2_finish turns them into per-row offsets.
-template <int BS>
+// kNarrow: the bitmap-code array spans less than 4 GiB (32-bit gathers).
+template <int BS, bool kNarrow>
 __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const DenseRow* dr, const int32_t* a_col,
                                                  Bins bins, int32_t S, int32_t* off2, uint4* spn, int32_t* ctr) {
   constexpr int NW = BS / kWave;
@@ -630,8 +650,8 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
     auto apply = [&](int32_t code) {
       atomicOr(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s_bm) + (code >> 5)), 1u << (code & 31));
     };
-    slab_products<BS, kSlabU, uint8_t, false, false>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0, 0, L,
-                                                     b.pbit, fetch, apply);
+    slab_products<BS, kSlabU, uint8_t, false, false, kNarrow>(b, a_col, nullptr, d.a0, d.nsrc, s, 0, G, true, false, 0,
+                                                              0, L, b.pbit, fetch, apply);
     block_sync();
     // per-tile counts: wavefront w takes tiles w, w + NW, ..., lane l the
     // words [4l, 4l + 4) and [256 + 4l, 256 + 4l + 4) of each (two 16-byte
@@ -747,13 +767,13 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     const bool hround = (int64_t)wv * kWave * kSlabU < total;
     // pass 1: the window's column set
     if (held) {
-      slab_round<BS, kSlabU, V>(L, nl, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
+      slab_round<BS, kSlabU, V, false>(L, nl, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
       if (hround)
 #pragma unroll
         for (int u = 0; u < kSlabU; ++u) a1(pp[u].c);
     } else {
-      slab_products<BS, kSlabU, V, true, true>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl, total, L,
-                                               b.pcv, f1, a1);
+      slab_products<BS, kSlabU, V, true, true, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl,
+                                                      total, L, b.pcv, f1, a1);
     }
     block_sync();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lane l the kpl
@@ -794,8 +814,8 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
       for (int u = 0; u < kSlabU; ++u)
         if (Sr::kIdempotent ? hround : ok[u]) a2(pp[u]);
     } else {
-      slab_products<BS, kSlabU, V, true, Sr::kIdempotent>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one,
-                                                          nl, total, L, b.pcv, f2, a2);
+      slab_products<BS, kSlabU, V, true, Sr::kIdempotent, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole,
+                                                                 one, nl, total, L, b.pcv, f2, a2);
     }
     block_sync();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
@@ -914,10 +934,10 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
         int nl;
         const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
-        slab_iterate<BS, kSlabU, V, false>(L, nl, total, b.pcv, f, ap);
+        slab_iterate<BS, kSlabU, V, false, false>(L, nl, total, b.pcv, f, ap);
       } else {
-        slab_products<BS, kSlabU, V, true, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0, false,
-                                                  false, 0, 0, L, b.pcv, f, ap);
+        slab_products<BS, kSlabU, V, true, false, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
+                                                         false, false, 0, 0, L, b.pcv, f, ap);
       }
       block_sync();
       // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and

@@ -140,3 +140,26 @@ def test_heavy_tile_span_counts(h, sr):
     check_product(h, sr, A, B, what="heavy span counts")
     st = h.stats()
     assert st["tile_tasks"] == 1 and st["tile_entries"] == c0.size, st
+
+
+@pytest.mark.parametrize("sr", [MINPLUS, I64])
+@pytest.mark.parametrize("g32", [0, 1])
+def test_symbolic_gather_widths(h, sr, g32):
+    """The symbolic slab pass with 32-bit gathers (the default below 2^30
+    entries of B) and with 64-bit gathers (forced), on a product whose rows
+    are all dense."""
+    _reset(h)
+    h.set_option("force_path", "dense")
+    h.set_option("gather32", g32)
+    try:
+        A = with_vals(synth.rmat(12, 16, seed=250), sr, 251)
+        check_product(h, sr, A, A, what=f"gather32={g32}")
+    finally:
+        h.set_option("gather32", 1)
+        _reset(h)
+
+
+def test_gather32_option_errors(h):
+    import paper_2504_06408_amd as sg
+    with pytest.raises(sg.SgError):
+        h.set_option("gather32", 2)
