@@ -118,8 +118,8 @@ sg_status sg_handle_destroy(sg_handle* h);
  * see sg_handle_timings), "dense_slab" (0/1, default 1: dense rows of a single
  * product run per column slab of B over a slab partition of B; 0: per
  * column tile through a per-B-row tile offset table), "gather32" (0/1,
- * default 1: the slab path's symbolic gathers use 32-bit offsets when B has
- * fewer than 2^30 entries; 0: always 64-bit), "dense_tile_min"
+ * default 1: the slab path's gathers use 32-bit offsets when its partition of
+ * B spans less than 4 GiB; 0: always 64-bit), "dense_tile_min"
  * (1..2048: a dense row's column tile
  * with at least this many output entries is accumulated in a dense LDS array,
  * smaller ones in an LDS hash table).  Returns SG_ERR_INVALID for an unknown

@@ -147,6 +147,7 @@ sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B,
   r.pbit = (const int32_t*)sb.pbit.p;
   // 32-bit gathers need the bitmap-code array (4 bytes per entry) below 4 GiB
   r.gather32 = h->gather32 && B->nnz < ((int64_t)1 << 30);
+  r.b_nnz = B->nnz;
   r.pval = vals ? sb.pcv.p : nullptr;
   r.ls = ls;
   r.S = S;

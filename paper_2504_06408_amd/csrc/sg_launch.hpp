@@ -47,6 +47,7 @@ struct RowSource {
   const DenseRow* drow;   // per dense row: its A row
   uint4* spn;             // span counts of the dense rows' tiles (after off2 in its buffer)
   bool gather32;          // the symbolic slab pass may gather at 32-bit offsets
+  int64_t b_nnz;          // entries of the partitioned B
   int32_t ls, S;
   int32_t* qctr;  // counter block (kCtrInts ints) of the slab symbolic pass
 };
@@ -213,9 +214,11 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
                          heavy, sbook, c.task_ctr);
       hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, sbook, T, c.task_ctr);
       SlabB<V> b{c.src.prow, c.src.pbit, (const ColV<V>*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};
+      // 32-bit gathers when the (column, value) partition spans less than 4 GiB
+      const bool narrow = c.src.gather32 && c.src.b_nnz < ((int64_t)1 << 32) / (int64_t)sizeof(ColV<V>);
       {
-        auto k = k_num_slab<Sr, V, 512, kSlabCap>;
-        static int occ = occupancy(k, 512);
+        auto k = narrow ? k_num_slab<Sr, V, 512, kSlabCap, true> : k_num_slab<Sr, V, 512, kSlabCap, false>;
+        static int occ = occupancy(k_num_slab<Sr, V, 512, kSlabCap, true>, 512);
         const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
         c.marks.mark(kPhNumDenseSlab, 1);
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.C,
@@ -224,8 +227,8 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
         c.marks.mark(kPhNumDenseSlab, 0);
       }
       {
-        auto k = k_num_slab_heavy<Sr, V, 512>;
-        static int occ = occupancy(k, 512);
+        auto k = narrow ? k_num_slab_heavy<Sr, V, 512, true> : k_num_slab_heavy<Sr, V, 512, false>;
+        static int occ = occupancy(k_num_slab_heavy<Sr, V, 512, true>, 512);
         const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
         c.marks.mark(kPhNumDenseTiles, 1);
         hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.off2, c.spn,

@@ -710,7 +710,7 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
 // ---- numeric ---------------------------------------------------------------------
 // Light windows (at most CAP entries): bitmap + rank, two passes over the
 // products (sources loaded once when one chunk holds them).
-template <class Sr, class V, int BS, int CAP>
+template <class Sr, class V, int BS, int CAP, bool kNarrow>
 __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a_col, const V* a_val, OutC C,
                                                  const SlabTask* tasks, const int32_t* boff, int32_t nd,
                                                  int32_t* ctr, int32_t* err) {
@@ -767,13 +767,13 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     const bool hround = (int64_t)wv * kWave * kSlabU < total;
     // pass 1: the window's column set
     if (held) {
-      slab_round<BS, kSlabU, V, false>(L, nl, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
+      slab_round<BS, kSlabU, V, kNarrow>(L, nl, total, (int64_t)wv * kWave * kSlabU, b.pcv, f2, pp, ok);
       if (hround)
 #pragma unroll
         for (int u = 0; u < kSlabU; ++u) a1(pp[u].c);
     } else {
-      slab_products<BS, kSlabU, V, true, true, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl,
-                                                      total, L, b.pcv, f1, a1);
+      slab_products<BS, kSlabU, V, true, true, kNarrow>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole, one, nl,
+                                                        total, L, b.pcv, f1, a1);
     }
     block_sync();
     // ranks: wavefront wv owns words [wv*wpw, (wv+1)*wpw), lane l the kpl
@@ -814,8 +814,8 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
       for (int u = 0; u < kSlabU; ++u)
         if (Sr::kIdempotent ? hround : ok[u]) a2(pp[u]);
     } else {
-      slab_products<BS, kSlabU, V, true, Sr::kIdempotent, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1, whole,
-                                                                 one, nl, total, L, b.pcv, f2, a2);
+      slab_products<BS, kSlabU, V, true, Sr::kIdempotent, kNarrow>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, tr0, tr1,
+                                                                   whole, one, nl, total, L, b.pcv, f2, a2);
     }
     block_sync();
     // write-out: column ids from the bitmap walk (no LDS reads inside the
@@ -854,7 +854,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
 // workgroup per CU.  Wavefront w compacts span w of the tile; where the
 // symbolic pass recorded the tile's span counts they give each wavefront its
 // output offset, otherwise the wavefronts count their spans first.
-template <class Sr, class V, int BS>
+template <class Sr, class V, int BS, bool kNarrow>
 __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_num_slab_heavy(
     SlabB<V> b, const int32_t* a_col, const V* a_val, const int32_t* off2, const uint4* spn, OutC C,
     const SlabTask* tasks, const int32_t* boff, int32_t nd, int32_t* ctr, int32_t* err) {
@@ -934,10 +934,10 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
         int nl;
         const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
-        slab_iterate<BS, kSlabU, V, false, false>(L, nl, total, b.pcv, f, ap);
+        slab_iterate<BS, kSlabU, V, false, kNarrow>(L, nl, total, b.pcv, f, ap);
       } else {
-        slab_products<BS, kSlabU, V, true, false, false>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
-                                                         false, false, 0, 0, L, b.pcv, f, ap);
+        slab_products<BS, kSlabU, V, true, false, kNarrow>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
+                                                           false, false, 0, 0, L, b.pcv, f, ap);
       }
       block_sync();
       // compaction: wavefront wv owns slots [wv*kSpan, (wv+1)*kSpan) and
