@@ -120,29 +120,25 @@ def cpu_baseline(A, B, sr, p, target_s):
             "sample": f"{k} rows drawn uniformly (seed 3) of the same product, {prods} products, {dt:.2f} s"}
 
 
-def parity_sample(A, B, sr, p, C, per_bin=12, rows=None):
-    """Rows of the timed result against the oracle: a stratified sample over
-    product-count decades, or the given rows (exact semirings bit for bit;
-    float sums: the gated tolerance and plain max / median relative error)."""
+def _device_rows(C, rows):
+    """Host copies (rowptr, col, val) of rows `rows` of a device CSR."""
     import torch
-    import oracle
-    import synth
-    if rows is None:
-        rows = []
-        edges = [1, 64, 4096, 65536, 1 << 20, 1 << 62]
-        for lo, hi in zip(edges[:-1], edges[1:]):
-            cand = np.nonzero((p >= lo) & (p < hi))[0]
-            if len(cand):
-                rows.extend(cand[synth.select(len(cand), min(per_bin, len(cand)), lo)].tolist())
-    rows = np.sort(np.array(rows, dtype=np.int64))
     rp = C.rowptr.cpu().numpy()
-    idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
-    ti = torch.from_numpy(idx).to(C.col.device)
-    g_col, g_val = C.col[ti].cpu().numpy(), C.val[ti].cpu().numpy()
+    rows = np.asarray(rows, dtype=np.int64)
     g_rp = np.zeros(len(rows) + 1, np.int64)
     np.cumsum(rp[rows + 1] - rp[rows], out=g_rp[1:])
-    ref = oracle.get().spgemm(sr, A, B, rows=rows)
-    out = {"rows": int(len(rows)), "entries": int(len(idx)),
+    if g_rp[-1] == 0:
+        return g_rp, np.zeros(0, np.int32), C.val[:0].cpu().numpy()
+    idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+    ti = torch.from_numpy(idx).to(C.col.device)
+    return g_rp, C.col[ti].cpu().numpy(), C.val[ti].cpu().numpy()
+
+
+def compare_rows(sr, g_rp, g_col, g_val, ref):
+    """GPU rows against oracle rows: the pattern exactly; values bit for bit
+    (int64, bool, (min,+)) or within the gated tolerance with plain max /
+    median relative error (float sums)."""
+    out = {"rows": int(len(g_rp) - 1), "entries": int(g_rp[-1]),
            "pattern_equal": bool(np.array_equal(g_rp, ref.rowptr) and np.array_equal(g_col, ref.col))}
     if not out["pattern_equal"]:
         return out
@@ -162,6 +158,41 @@ def parity_sample(A, B, sr, p, C, per_bin=12, rows=None):
         out["max_rel_err"] = float(rel.max()) if len(rel) else 0.0
         out["median_rel_err"] = float(np.median(rel)) if len(rel) else 0.0
     return out
+
+
+def merge_reports(reps):
+    """One summary of several compare_rows reports."""
+    out = {"rows": sum(r["rows"] for r in reps), "entries": sum(r["entries"] for r in reps),
+           "pattern_equal": all(r["pattern_equal"] for r in reps)}
+    if "bit_exact" in reps[0]:
+        out["bit_exact"] = all(r.get("bit_exact", False) for r in reps)
+    if "within_tol" in reps[0]:
+        out["within_tol"] = all(r.get("within_tol", False) for r in reps)
+        out["max_rel_err"] = max(r.get("max_rel_err", 0.0) for r in reps)
+    return out
+
+
+def stratified_rows(p, per_bin, seed_base=0):
+    """Up to per_bin rows from each product-count decade."""
+    import synth
+    rows = []
+    edges = [1, 64, 4096, 65536, 1 << 20, 1 << 62]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        cand = np.nonzero((p >= lo) & (p < hi))[0]
+        if len(cand):
+            rows.extend(cand[synth.select(len(cand), min(per_bin, len(cand)), lo + seed_base)].tolist())
+    return np.sort(np.array(rows, dtype=np.int64))
+
+
+def parity_sample(A, B, sr, p, C, per_bin=12, rows=None):
+    """Rows of the timed result against the oracle: a stratified sample over
+    product-count decades, or the given rows."""
+    import oracle
+    if rows is None:
+        rows = stratified_rows(p, per_bin)
+    rows = np.sort(np.asarray(rows, dtype=np.int64))
+    ref = oracle.get().spgemm(sr, A, B, rows=rows)
+    return compare_rows(sr, *_device_rows(C, rows), ref)
 
 
 def batched_leg(sg, torch, h, sr, dA, dB, P, steps, ms_per_call):
@@ -234,11 +265,42 @@ def summa_leg(sg, torch, h, scale, steps):
         plan.execute()
     torch.cuda.synchronize()
     ms_b = (time.perf_counter() - t0) * 1e3 / steps
-    plan.results()
+    par = summa_parity(sg, A, g, plan, len(As), per_bin=8)
     plan.destroy()
     return {"workload": f"R-MAT s{scale} cut 8x8, 512 fp64 (+,x) stage products + 64 merges", "products": prods,
             "ms_per_call_path": round(ms_pc, 3), "ms_batched": round(ms_b, 3),
-            "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3)}
+            "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3),
+            "parity_sample": par}
+
+
+def summa_parity(sg, A, g, plan, nprod, per_bin=8):
+    """Block identity (paper, Section 2.1) on sampled rows: row i of output
+    block row I, read across the g merged blocks (I, J) with their column
+    offsets, equals row I*rb + i of the oracle's full A.A.  Rows are
+    stratified by product count over the whole matrix."""
+    import oracle
+    p = products_per_row(A, A)
+    rows = stratified_rows(p, per_bin, 7)
+    rb = -(-A.nrows // g)
+    cb = -(-A.ncols // g)
+    sid = 3
+    res = plan.results()
+    views = [sg.view_results(r, sid) for r in res[nprod:]]
+    g_rp = np.zeros(len(rows) + 1, np.int64)
+    cols, vals = [], []
+    for k, r in enumerate(rows):
+        I, i = divmod(int(r), rb)
+        n_r = 0
+        for J in range(g):
+            brp, bcl, bvl = _device_rows(views[I * g + J], [i])
+            cols.append(bcl.astype(np.int64) + J * cb)
+            vals.append(bvl)
+            n_r += len(bcl)
+        g_rp[k + 1] = g_rp[k] + n_r
+    ref = oracle.get().spgemm(sid, A, A, rows=rows)
+    out = compare_rows(sid, g_rp, np.concatenate(cols).astype(np.int32), np.concatenate(vals), ref)
+    out["check"] = "merged blocks across each sampled row vs the oracle's full A.A"
+    return out
 
 
 def three_hop_leg(sg, torch, h, A, dA, steps):
@@ -326,13 +388,14 @@ def er_batch_leg(sg, torch, h, count, steps):
     replays) against a per-call loop."""
     import synth
     n, d = synth.batch_params(count, 1024, 65536, 4, 32, 5)
-    As, Bs, prods = [], [], 0
+    As, Bs, hosts, prods = [], [], [], 0
     for i in range(count):
         a = synth.er(int(n[i]), int(n[i]), int(d[i]), 1000 + 2 * i)
         b = synth.er(int(n[i]), int(n[i]), int(d[i]), 1001 + 2 * i)
         a = a.with_values(synth.values(synth.VAL_F64_UNIFORM, a.nnz, 0, 1, 3000 + 2 * i))
         b = b.with_values(synth.values(synth.VAL_F64_UNIFORM, b.nnz, 0, 1, 3001 + 2 * i))
         prods += int(np.diff(b.rowptr)[a.col].sum())
+        hosts.append((a, b))
         As.append(sg.DeviceCSR.from_host(a))
         Bs.append(sg.DeviceCSR.from_host(b))
     sr = sg.semiring(sg.PLUS_TIMES_F64)
@@ -356,11 +419,113 @@ def er_batch_leg(sg, torch, h, count, steps):
         plan.execute()
     torch.cuda.synchronize()
     ms_b = (time.perf_counter() - t0) * 1e3 / steps
-    plan.results()
+    # parity: every instance's largest row plus 4 random rows of 16
+    # instances (the 8 largest and 8 drawn at random) against the oracle
+    import oracle
+    res = plan.results()
+    pick = sorted(set(np.argsort(n)[-8:].tolist()) | set(synth.select(count, min(8, count), 21).tolist()))
+    reps = []
+    for q in pick:
+        a, b = hosts[q]
+        pq = products_per_row(a, b)
+        rows = np.unique(np.concatenate([[int(np.argmax(pq))], synth.select(a.nrows, 4, 22 + q)]))
+        Cq = sg.view_results(res[q], 3)
+        reps.append(compare_rows(3, *_device_rows(Cq, rows), oracle.get().spgemm(3, a, b, rows=rows)))
     plan.destroy()
+    par = merge_reports(reps)
+    par["instances"] = len(pick)
     return {"workload": f"{count} ER fp64 (+,x) products, n log-uniform in [1k, 64k], d in {{4..32}}",
             "products": prods, "ms_per_call_path": round(ms_pc, 3), "ms_batched": round(ms_b, 3),
-            "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3)}
+            "batched_speedup": round(ms_pc / ms_b, 3), "batched_products_per_s": prods / (ms_b * 1e-3),
+            "parity_sample": par}
+
+
+def measure_product(sg, torch, h, A, B, sr_id, steps, warmup, hash_max=None, workload=None):
+    """Time `steps` whole two-pass products C = A.B (symbolic with its nnz
+    read-back, then numeric into a pre-reserved output) after `warmup`
+    untimed ones; return the figures, the roofline of the dominant
+    single-kernel phase and the last result C (device)."""
+    dev = "cuda:0"
+    p = products_per_row(A, B)
+    P = int(p.sum())
+    dA = sg.DeviceCSR.from_host(A, dev)
+    dB = dA if B is A else sg.DeviceCSR.from_host(B, dev)
+    sr = sg.semiring(sr_id)
+    vb = VAL_BYTES[sr_id]
+    # pre-reserved output: sized by one symbolic pass before timing
+    rowptr, nnzC = h.symbolic(dA, dB)
+    col = torch.empty(nnzC, dtype=torch.int32, device=dev)
+    val = torch.empty(nnzC, dtype={1: torch.int64, 2: torch.float32, 3: torch.float64, 4: torch.uint8,
+                                   5: torch.float32}[sr_id], device=dev)
+
+    def step():
+        rp, nz = h.symbolic(dA, dB)
+        C = sg.DeviceCSR(A.nrows, B.ncols, rp, col[:nz], val[:nz])
+        h.numeric(sr, dA, dB, C)
+        return C, nz
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    h.check()
+    phase_runs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        C, nz = step()
+        phase_runs.append(h.timings())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.check()
+    assert nz == nnzC
+    ms = (t1 - t0) * 1e3 / steps
+
+    n, nnzA, nnzB = A.nrows, A.nnz, B.nnz
+    b_sym = 8 * (n + 1) + 4 * nnzA + 8 * (B.nrows + 1) + 4 * nnzB + 8 * (n + 1)
+    b_num = 8 * (n + 1) + (4 + vb) * nnzA + 8 * (B.nrows + 1) + (4 + vb) * nnzB + 8 * (n + 1) + (4 + vb) * nnzC
+    b_alg = b_sym + b_num
+    phases = {k: float(np.mean([r[k] for r in phase_runs])) for k in phase_runs[0]}
+    stats = h.stats()
+    # Roofline of the dominant single-kernel phase.  Algorithmic bytes per
+    # launch: the output entries that kernel writes ((4 + value bytes) each)
+    # plus one read of its inputs: the A rows it handles (col + value), B
+    # (col + value; col only in the symbolic pass) and 8 B of row offsets per
+    # dense row.
+    hm = 4096 if hash_max is None else hash_max
+    dense = p > hm
+    nd = int(dense.sum())
+    a_dense = int(np.diff(A.rowptr)[dense].sum())
+    kernels = {
+        "sym_dense_bitmap": 4 * a_dense + 4 * nnzB + 8 * nd,
+        "num_dense_slab": (4 + vb) * (stats["slab_entries"] + a_dense + nnzB) + 8 * nd,
+        "num_dense_tiles": (4 + vb) * (stats["tile_entries"] + a_dense + nnzB) + 8 * nd,
+        "num_dense_ranges": (4 + vb) * (stats["range_entries"] + a_dense + nnzB) + 8 * nd,
+    }
+    dom = max(kernels, key=lambda k: phases.get(k, 0.0))
+    kb = kernels[dom]
+    achieved = kb / (phases[dom] * 1e-3) / 1e9 if phases[dom] > 0 else 0.0
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(workload, dom),
+            "bytes_per_launch": int(kb), "ms_per_launch": round(phases[dom], 4)}
+    res = {"products": P, "nnz_C": int(nnzC), "ms_per_step": round(ms, 4), "value": P / (ms * 1e-3),
+           "unit": "semiring products/s",
+           "hbm_gbps_model": round(b_alg / (ms * 1e-3) / 1e9, 1),
+           "hbm_frac_model": round(b_alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4), "bytes_alg": int(b_alg),
+           "phases_ms": {k: round(v, 4) for k, v in phases.items()}, "dense_stats": stats, "roofline": roof}
+    return res, C, dA, dB, p
+
+
+def product_leg(sg, torch, h, name, steps, warmup):
+    """Another workload of the configuration list through the same per-call
+    two-pass product, with its own roofline and parity sample."""
+    A, B, sr_id, desc = make_inputs(name)
+    res, C, dA, dB, p = measure_product(sg, torch, h, A, B, sr_id, steps, warmup, workload=name)
+    out = {"workload": desc, "semiring": sg.SEMIRING_NAMES[sr_id], "dtype": DTYPE[sr_id]}
+    out.update(res)
+    out["parity_sample"] = parity_sample(A, B, sr_id, p, C)
+    del C, dA, dB
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -375,7 +540,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched legs")
     ap.add_argument("--summa-scale", type=int, default=18, help="R-MAT scale of the 8x8 SUMMA leg (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 3-hop, precision and ER-batch legs")
+                    help="skip the s18, 3-hop, precision and ER-batch legs")
     ap.add_argument("--er-batch", type=int, default=256, help="ER products in the batch leg (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB copy kernel (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -390,114 +555,51 @@ def main():
 
     t_gen = time.perf_counter()
     A, B, sr_id, desc = make_inputs(args.workload)
-    p = products_per_row(A, B)
-    P = int(p.sum())
-    print(f"# inputs ready in {time.perf_counter() - t_gen:.1f}s: n={A.nrows} nnz(A)={A.nnz} products={P}",
+    print(f"# inputs ready in {time.perf_counter() - t_gen:.1f}s: n={A.nrows} nnz(A)={A.nnz}",
           file=sys.stderr, flush=True)
-
-    dev = "cuda:0"
-    dA = sg.DeviceCSR.from_host(A, dev)
-    dB = dA if B is A else sg.DeviceCSR.from_host(B, dev)
     h = sg.Handle(0)
     h.set_option("timing", 1)
     if args.hash_max is not None:
         h.set_option("hash_max_products", args.hash_max)
     sr = sg.semiring(sr_id)
-    vb = VAL_BYTES[sr_id]
-
-    # pre-reserved output: sized by one symbolic pass before timing
-    rowptr, nnzC = h.symbolic(dA, dB)
-    col = torch.empty(nnzC, dtype=torch.int32, device=dev)
-    val = torch.empty(nnzC, dtype={1: torch.int64, 2: torch.float32, 3: torch.float64, 4: torch.uint8,
-                                   5: torch.float32}[sr_id], device=dev)
-
-    def step():
-        rp, nz = h.symbolic(dA, dB)
-        C = sg.DeviceCSR(A.nrows, B.ncols, rp, col[:nz], val[:nz])
-        h.numeric(sr, dA, dB, C)
-        return C, nz
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    h.check()
-
-    phase_runs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        C, nz = step()
-        phase_runs.append(h.timings())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    h.check()
-    assert nz == nnzC
-    ms = (t1 - t0) * 1e3 / args.steps
+    res, C, dA, dB, p = measure_product(sg, torch, h, A, B, sr_id, args.steps, args.warmup, args.hash_max,
+                                        args.workload)
+    P, ms = res["products"], res["ms_per_step"]
     print(f"# {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
-
-    n, nnzA, nnzB = A.nrows, A.nnz, B.nnz
-    b_sym = 8 * (n + 1) + 4 * nnzA + 8 * (B.nrows + 1) + 4 * nnzB + 8 * (n + 1)
-    b_num = 8 * (n + 1) + (4 + vb) * nnzA + 8 * (B.nrows + 1) + (4 + vb) * nnzB + 8 * (n + 1) + (4 + vb) * nnzC
-    b_alg = b_sym + b_num
-
-    phases = {k: float(np.mean([r[k] for r in phase_runs])) for k in phase_runs[0]}
-    stats = h.stats()
-    # Roofline of the dominant single-kernel phase.  Algorithmic bytes per
-    # launch: the output entries that kernel writes ((4 + value bytes) each)
-    # plus one read of its inputs: the A rows it handles (col + value), B
-    # (col + value; col only in the symbolic pass) and 8 B of row offsets per
-    # dense row.
-    hm = 4096 if args.hash_max is None else args.hash_max
-    dense = p > hm
-    nd = int(dense.sum())
-    a_dense = int(np.diff(A.rowptr)[dense].sum())
-    kernels = {
-        "sym_dense_bitmap": 4 * a_dense + 4 * nnzB + 8 * nd,
-        "num_dense_slab": (4 + vb) * (stats["slab_entries"] + a_dense + nnzB) + 8 * nd,
-        "num_dense_tiles": (4 + vb) * (stats["tile_entries"] + a_dense + nnzB) + 8 * nd,
-        "num_dense_ranges": (4 + vb) * (stats["range_entries"] + a_dense + nnzB) + 8 * nd,
-    }
-    dom = max(kernels, key=lambda k: phases.get(k, 0.0))
-    kb = kernels[dom]
-    achieved = kb / (phases[dom] * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(args.workload, dom),
-            "bytes_per_launch": int(kb),
-            "ms_per_launch": round(phases[dom], 4)}
-
     out = {
         "metric": METRIC,
-        "value": P / (ms * 1e-3),
+        "value": res["value"],
         "unit": "semiring products/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": DTYPE[sr_id],
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "semiring": sg.SEMIRING_NAMES[sr_id], "n": int(A.nrows),
-                   "nnz_A": int(nnzA), "products": P, "nnz_C": int(nnzC), "path": "per-call symbolic+numeric"},
-        "hbm_gbps_model": round(b_alg / (ms * 1e-3) / 1e9, 1),
-        "hbm_frac_model": round(b_alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
-        "bytes_alg": int(b_alg),
-        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
-        "dense_stats": stats,
-        "roofline": roof,
+                   "nnz_A": int(A.nnz), "products": P, "nnz_C": res["nnz_C"], "path": "per-call symbolic+numeric"},
     }
+    for k in ("hbm_gbps_model", "hbm_frac_model", "bytes_alg", "phases_ms", "dense_stats", "roofline"):
+        out[k] = res[k]
     t_par = time.perf_counter()
     out["parity_sample"] = parity_sample(A, B, sr_id, p, C)
     print(f"# parity sample {out['parity_sample']} in {time.perf_counter() - t_par:.1f}s", file=sys.stderr, flush=True)
-    del C, col, val, rowptr
+    del C
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_leg(sg, torch, h, sr, dA, dB, P, args.steps, ms)
+        print(f"# batched leg {out['batched']['ms_per_step']} ms", file=sys.stderr, flush=True)
         if args.summa_scale > 0:
             out["summa"] = summa_leg(sg, torch, h, args.summa_scale, args.steps)
+            print(f"# summa leg {out['summa']['ms_batched']} ms", file=sys.stderr, flush=True)
     if not args.no_extra and args.workload == "rmat20_minplus":
         t_x = time.perf_counter()
+        for name in ("rmat18_bool", "rmat18_i64"):
+            out[name] = product_leg(sg, torch, h, name, args.steps, args.warmup)
+            print(f"# {name} leg {out[name]['ms_per_step']} ms", file=sys.stderr, flush=True)
         out["three_hop"] = three_hop_leg(sg, torch, h, A, dA, args.steps)
         torch.cuda.empty_cache()
         out["precision"] = precision_leg(sg, torch, h, 20)
@@ -508,7 +610,7 @@ def main():
         print(f"# extra legs in {time.perf_counter() - t_x:.1f}s", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         n = 1 << 27
-        src = torch.ones(n, dtype=torch.int32, device=dev)
+        src = torch.ones(n, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.mul(src, 1, out=dst)
         torch.cuda.synchronize()
