@@ -144,6 +144,25 @@ sg_status sg_spgemm_symbolic(sg_handle* h, const sg_csr* A, const sg_csr* B, int
 sg_status sg_spgemm_numeric(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, sg_csr* C,
                             void* stream);
 
+/* Variant of sg_spgemm_numeric for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, same result, same stream semantics
+ * (no wait for the stream), but it calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch (row bins, B's column-slab partition, the
+ * dense-row tile offsets and task lists) comes from one fixed device array of
+ * SG_NOALLOC_SCRATCH_BYTES per GPU, bound when a handle is created on that
+ * GPU and held until the process ends.  It never reuses the structure saved
+ * by the handle's last symbolic pass (everything is rebuilt from A, B and
+ * C->rowptr), so it does not depend on which call came before, but C->rowptr
+ * must still come from sg_spgemm_symbolic on the same A and B.  A product
+ * whose scratch exceeds the array returns SG_ERR_NOMEM before any kernel
+ * writes to C.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (two streams, two host threads) race and must
+ * be serialised by the caller; consecutive calls on one stream are safe. */
+#define SG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sg_status sg_spgemm_numeric_noalloc(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, sg_csr* C,
+                                    void* stream);
+
 /* Merge (paper, Section 4.4): C = parts[0] (+) ... (+) parts[nparts-1],
  * entry by entry, pattern = union.  parts is a host array of nparts
  * descriptors (device arrays) of one shape.  Same two-pass convention as the

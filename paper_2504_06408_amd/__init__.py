@@ -23,6 +23,7 @@ PLUS_TIMES_I64, PLUS_TIMES_F32, PLUS_TIMES_F64, OR_AND_BOOL, MIN_PLUS_F32 = 1, 2
 SEMIRING_NAMES = {1: "plus_times_i64", 2: "plus_times_f32", 3: "plus_times_f64", 4: "or_and_bool",
                   5: "min_plus_f32"}
 ACC_DEFAULT, ACC_COMPENSATED, ACC_PLAIN = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SG_NOALLOC_SCRATCH_BYTES
 NP_DTYPE = {1: np.int64, 2: np.float32, 3: np.float64, 4: np.uint8, 5: np.float32}
 
 STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID", -2: "SG_ERR_SHAPE", -3: "SG_ERR_SEMIRING", -4: "SG_ERR_NOMEM",
@@ -30,7 +31,8 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID", -2: "SG_ERR_SHAPE", -3: "SG_ERR_SEMI
 
 # every function include/spgemm.h declares
 EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_handle_set_option",
-           "sg_spgemm_symbolic", "sg_spgemm_numeric", "sg_spgemm_merge_symbolic", "sg_spgemm_merge_numeric",
+           "sg_spgemm_symbolic", "sg_spgemm_numeric", "sg_spgemm_numeric_noalloc", "sg_spgemm_merge_symbolic",
+           "sg_spgemm_merge_numeric",
            "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune",
            "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error")
 
@@ -78,6 +80,7 @@ def lib():
             "sg_handle_set_option": ([P, ctypes.c_char_p, ctypes.c_char_p], ci),
             "sg_spgemm_symbolic": ([P, CSR, CSR, P, ctypes.POINTER(i64), P], ci),
             "sg_spgemm_numeric": ([P, SR, CSR, CSR, CSR, P], ci),
+            "sg_spgemm_numeric_noalloc": ([P, SR, CSR, CSR, CSR, P], ci),
             "sg_spgemm_merge_symbolic": ([P, ci, CSR, P, ctypes.POINTER(i64), P], ci),
             "sg_spgemm_merge_numeric": ([P, SR, ci, CSR, CSR, P], ci),
             "sg_batch_plan": ([P, SR, ci, CSR, CSR, ci, ctypes.POINTER(i32), ctypes.c_size_t, ctypes.POINTER(P)], ci),
@@ -260,6 +263,13 @@ class Handle:
         a, b, c = A.desc(), B.desc(), C.desc()
         self._rc(lib().sg_spgemm_numeric(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b),
                                          ctypes.byref(c), _stream_ptr(stream)))
+
+    def numeric_noalloc(self, sr: sg_semiring, A: DeviceCSR, B: DeviceCSR, C: DeviceCSR, stream=None) -> None:
+        """Pass 2 with all scratch taken from the library's fixed device array
+        (no device allocation; SG_ERR_NOMEM beyond NOALLOC_SCRATCH_BYTES)."""
+        a, b, c = A.desc(), B.desc(), C.desc()
+        self._rc(lib().sg_spgemm_numeric_noalloc(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b),
+                                                 ctypes.byref(c), _stream_ptr(stream)))
 
     def spgemm(self, sr, A: DeviceCSR, B: DeviceCSR, stream=None) -> DeviceCSR:
         """C = A (x).(+) B (both passes); sr: semiring id or descriptor."""

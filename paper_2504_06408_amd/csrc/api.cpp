@@ -2,6 +2,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,51 @@ sg_status sg_check_hip(sg_handle* h, hipError_t e, const char* what) {
     const sg_status _s = (expr);    \
     if (_s != SG_OK) return _s;     \
   } while (0)
+
+// Scratch of sg_spgemm_numeric_noalloc: a fixed device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host it only names the symbol):
+// its device address is looked up once per device at handle creation and
+// kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[SG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), looked up on
+// the first call for that device.
+hipError_t bind_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
+sg_status Scratch::take(SgBuf& b, size_t bytes) {
+  if (!base) return sg_check_hip(h, b.ensure(bytes), "hipMalloc (scratch)");
+  const size_t o = (off + 255) & ~(size_t)255;
+  if (o > cap || bytes > cap - o)
+    return sg_fail(h, SG_ERR_NOMEM, "the product needs more scratch than the fixed " + std::to_string(cap >> 20) +
+                                        " MiB device array of the no-allocation entry point holds");
+  b.p = base + o;
+  b.cap = bytes;
+  off = o + bytes;
+  return SG_OK;
+}
 
 namespace sg {
 
@@ -120,24 +166,24 @@ sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const i
   return SG_OK;
 }
 
-sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
-                      int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st) {
+sg_status build_slabs(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols,
+                      bool vals, int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st) {
   const int32_t ls = slab_log(r.ncols), S = slab_count(r.ncols, ls);
   const int64_t nb = B->nrows;
   const size_t ne = (size_t)(B->nnz > 0 ? B->nnz : 1);
   const int32_t G = 1 << (ls - kTileLog);
   if (cols) {
-    SG_HIP(h, sb.bnd.ensure(sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
-    SG_HIP(h, sb.rpt.ensure(sizeof(int32_t) * (size_t)S * (size_t)nb * (size_t)(G + 1)));
-    SG_HIP(h, sb.prow.ensure(sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
-    SG_HIP(h, sb.pbit.ensure(sizeof(int32_t) * ne));
+    SG_TRY(sc.take(sb.bnd, sizeof(int32_t) * (size_t)nb * (size_t)(S + 1)));
+    SG_TRY(sc.take(sb.rpt, sizeof(int32_t) * (size_t)S * (size_t)nb * (size_t)(G + 1)));
+    SG_TRY(sc.take(sb.prow, sizeof(int64_t) * ((size_t)S * (size_t)nb + 1)));
+    SG_TRY(sc.take(sb.pbit, sizeof(int32_t) * ne));
   }
   // numeric partition entries: (column, value) pairs, 8 bytes (16 for 8-byte values)
-  if (vals) SG_HIP(h, sb.pcv.ensure((size_t)(vbytes >= 8 ? 16 : 8) * ne));
+  if (vals) SG_TRY(sc.take(sb.pcv, (size_t)(vbytes >= 8 ? 16 : 8) * ne));
   // destinations of B's entries (int32 positions) for the value scatters of
   // later numeric passes on the same structure
   const bool use_perm = B->nnz <= INT32_MAX;
-  if (cols && use_perm) SG_HIP(h, sb.perm.ensure(sizeof(int32_t) * ne));
+  if (cols && use_perm) SG_TRY(sc.take(sb.perm, sizeof(int32_t) * ne));
   launch_slab_partition(B->rowptr, B->col, B->val, vbytes, nb, B->nnz, ls, S, r.T, (int32_t*)sb.bnd.p,
                         (int32_t*)sb.rpt.p, (int64_t*)sb.prow.p, partial, (int32_t*)sb.pbit.p,
                         vals ? sb.pcv.p : nullptr, use_perm ? (int32_t*)sb.perm.p : nullptr, cols, vals, err, h->cus,
@@ -155,9 +201,10 @@ sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B,
   return SG_OK;
 }
 
-sg_status build_dense_rows(sg_handle* h, SlabBufs& sb, RowSource& r, const BinPlan& plan, hipStream_t st) {
+sg_status build_dense_rows(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, const BinPlan& plan,
+                           hipStream_t st) {
   const int32_t nd = plan.bins.nd_cap;
-  SG_HIP(h, sb.dr.ensure(sizeof(DenseRow) * (size_t)(nd > 0 ? nd : 1)));
+  SG_TRY(sc.take(sb.dr, sizeof(DenseRow) * (size_t)(nd > 0 ? nd : 1)));
   launch_dense_rows(plan, r.a_rowptr, (DenseRow*)sb.dr.p, h->cus, st);
   r.drow = (const DenseRow*)sb.dr.p;
   return SG_OK;
@@ -290,8 +337,9 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
       launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
     }
     if (slab) {
-      SG_TRY(build_slabs(h, h->sb, r, B, 0, true, false, spartial, h->d_flags, h->d_flags + kCtrBase, st));
-      SG_TRY(build_dense_rows(h, h->sb, r, plan, st));
+      Scratch sc{h};
+      SG_TRY(build_slabs(h, sc, h->sb, r, B, 0, true, false, spartial, h->d_flags, h->d_flags + kCtrBase, st));
+      SG_TRY(build_dense_rows(h, sc, h->sb, r, plan, st));
     }
     mk.mark(kPhSymBounds, 0);
   }
@@ -312,16 +360,29 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   return SG_OK;
 }
 
+// Buffers a numeric call draws its scratch from (the handle's own, or
+// call-local views into the fixed array of the no-allocation entry point).
+struct NumBufs {
+  SgBuf& ws;
+  SlabBufs& sb;
+  SgBuf& off2;
+  SgBuf& task;
+  SgBuf& rp2;
+};
+
+// use_cache: the handle's saved structure of the last symbolic pass may be
+// reused (per-row counts, B's partition, dense-row tile offsets).  Without it
+// every structure-dependent table is rebuilt into `bufs`.
 sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const sg_csr* B, sg_csr* C,
-                      const SgCacheKey& key, hipStream_t st) {
+                      const SgCacheKey& key, hipStream_t st, Scratch& sc, const NumBufs& bufs, bool use_cache) {
   const int64_t n = r.nrows;
   SgArena measure;
   measure.off = plan_rows_bytes(n);
   measure.take<int64_t>(n);
   measure.take<int64_t>(slab_partials(h, r));
-  SG_HIP(h, h->ws.ensure(measure.off));
+  SG_TRY(sc.take(bufs.ws, measure.off));
   SgArena ar;
-  ar.base = (char*)h->ws.p;
+  ar.base = (char*)bufs.ws.p;
   BinPlan plan;
   const Policy pol = make_policy(h, 1, sr);
   clear_phases(h, kPhNumAnalyze, kPhSymDenseBitmap);
@@ -330,7 +391,8 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   // Same structure as the last symbolic call: its per-row counts give the bins
   // without touching A or B again.  Dense classification depends only on the
   // product count and the key's options, so the dense list is unchanged.
-  const bool same = h->cache_valid && h->cache_key == key && h->cache_T == r.T && h->cache_n == n;
+  const bool same =
+      use_cache && h->cache_valid && h->cache_key == key && h->cache_T == r.T && h->cache_n == n;
   mk.mark(kPhNumAnalyze, 1);
   if (same)
     SG_TRY(plan_rows(h, r, pol, C->rowptr, nullptr, ar, plan, st, (int64_t*)h->p_buf.p, (int32_t*)h->nt_buf.p, true));
@@ -343,25 +405,24 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
     if (slab) {
       // structure from the last symbolic pass when cached; values every call
       int64_t* spartial = ar.take<int64_t>(slab_partials(h, r));
-      SG_TRY(build_slabs(h, h->sb, r, B, sr->value_bytes, !cached, true, spartial, h->d_flags, h->d_flags + kCtrBase, st));
-      SG_TRY(build_dense_rows(h, h->sb, r, plan, st));
+      SG_TRY(build_slabs(h, sc, bufs.sb, r, B, sr->value_bytes, !cached, true, spartial, h->d_flags,
+                         h->d_flags + kCtrBase, st));
+      SG_TRY(build_dense_rows(h, sc, bufs.sb, r, plan, st));
     } else if (r.mode == kModeProduct && r.T > 1) {
       if (!cached) {
-        SG_HIP(h, h->rp2_buf.ensure(sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
-        launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)h->rp2_buf.p, h->cus, st);
+        SG_TRY(sc.take(bufs.rp2, sizeof(int32_t) * (size_t)B->nrows * (size_t)(r.T + 1)));
+        launch_tile_bounds(B->rowptr, B->col, B->nrows, r.T, (int32_t*)bufs.rp2.p, h->cus, st);
       }
-      r.rp2 = (const int32_t*)h->rp2_buf.p;
+      r.rp2 = (const int32_t*)bufs.rp2.p;
     }
-    if (slab) {
-      SG_HIP(h, h->off2_buf.ensure(off2_span_bytes(nd, r.T)));
-      r.spn = (uint4*)((char*)h->off2_buf.p + span_offset(nd, r.T));
-    }
+    // the slab path keeps span counts after the tile offsets
+    SG_TRY(sc.take(bufs.off2, slab ? off2_span_bytes(nd, r.T) : sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
+    if (slab) r.spn = (uint4*)((char*)bufs.off2.p + span_offset(nd, r.T));
     if (!cached) {
-      SG_HIP(h, h->off2_buf.ensure(slab ? off2_span_bytes(nd, r.T)
-                                        : sizeof(int32_t) * (size_t)nd * (size_t)(r.T + 1)));
-      int64_t* scratch = ar.take<int64_t>(n);
-      launch_symbolic_dense(r, plan, scratch, (int32_t*)h->off2_buf.p, h->cus, st);
-      h->cache_valid = false;  // off2 now belongs to this call's inputs only
+      int64_t* counts = ar.take<int64_t>(n);
+      launch_symbolic_dense(r, plan, counts, (int32_t*)bufs.off2.p, h->cus, st);
+      // off2 of the handle now belongs to this call's inputs only
+      if (!sc.fixed()) h->cache_valid = false;
     }
   }
   mk.mark(kPhNumAnalyze, 0);
@@ -370,19 +431,19 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.src = r;
   c.plan = plan;
   c.C = OutC{C->rowptr, C->col, C->val};
-  c.off2 = (const int32_t*)h->off2_buf.p;
+  c.off2 = (const int32_t*)bufs.off2.p;
   c.spn = r.spn;
   c.err = h->d_flags;
   c.task_ctr = h->d_flags + kCtrBase;
   c.task_cap = (int64_t)(nd > 0 ? nd : 1) * r.T;
   if (slab) {
     const size_t tb = 2 * sizeof(SlabTask) * (size_t)nd * (size_t)r.S;  // light and heavy lists
-    SG_HIP(h, h->task_buf.ensure(tb + sizeof(int32_t) * (6 * (size_t)r.T + 3)));
-    c.slab_tasks = (SlabTask*)h->task_buf.p;
-    c.slab_book = (int32_t*)((char*)h->task_buf.p + tb);
-  } else {
-    SG_HIP(h, h->task_buf.ensure(task_buffer_bytes(c.task_cap, r.T)));
-    c.tasks = (Task*)h->task_buf.p;
+    SG_TRY(sc.take(bufs.task, tb + sizeof(int32_t) * (6 * (size_t)r.T + 3)));
+    c.slab_tasks = (SlabTask*)bufs.task.p;
+    c.slab_book = (int32_t*)((char*)bufs.task.p + tb);
+  } else if (nd > 0) {
+    SG_TRY(sc.take(bufs.task, task_buffer_bytes(c.task_cap, r.T)));
+    c.tasks = (Task*)bufs.task.p;
   }
   c.tile_min = h->tile_min;
   c.cus = h->cus;
@@ -398,6 +459,13 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   }
   SG_HIP(h, hipGetLastError());
   return SG_OK;
+}
+
+sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const sg_csr* B, sg_csr* C,
+                      const SgCacheKey& key, hipStream_t st) {
+  Scratch sc{h};
+  const NumBufs bufs{h->ws, h->sb, h->off2_buf, h->task_buf, h->rp2_buf};
+  return run_numeric(h, sr, r, B, C, key, st, sc, bufs, true);
 }
 
 const char* env(const char* name) {
@@ -469,6 +537,7 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
   return SG_OK;
 }
 
+
 sg_status sg_tune_load(sg_handle* h, const char* path);  // tune.cpp
 
 sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out) {
@@ -486,6 +555,10 @@ sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out)
     return SG_ERR_HIP;
   }
   h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (bind_scratch(device) != hipSuccess) {
+    delete h;
+    return SG_ERR_HIP;
+  }
   if (hipMalloc(&h->d_flags, kFlagInts * sizeof(int32_t)) != hipSuccess) {
     delete h;
     return SG_ERR_NOMEM;
@@ -604,6 +677,43 @@ sg_status sg_spgemm_numeric(sg_handle* h, const sg_semiring* sr, const sg_csr* A
   r.ncols = B->ncols;
   r.T = tiles_of(B->ncols);
   return run_numeric(h, sr, r, B, C, product_key(h, A, B), st);
+}
+
+sg_status sg_spgemm_numeric_noalloc(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B,
+                                    sg_csr* C, void* stream) {
+  if (!h) return SG_ERR_INVALID;
+  SG_TRY(check_semiring(h, sr));
+  SG_TRY(check_csr(h, A, "A"));
+  SG_TRY(check_csr(h, B, "B"));
+  SG_TRY(check_csr(h, C, "C"));
+  if (A->ncols != B->nrows || C->nrows != A->nrows || C->ncols != B->ncols)
+    return sg_fail(h, SG_ERR_SHAPE, "shapes of A, B and C do not match");
+  if ((A->nnz > 0 && !A->val) || (B->nnz > 0 && !B->val) || (C->nnz > 0 && !C->val))
+    return sg_fail(h, SG_ERR_INVALID, "a value array is NULL");
+  SG_HIP(h, hipSetDevice(h->device));
+  char* base = (char*)scratch_ptr(h->device);
+  if (!base) return sg_fail(h, SG_ERR_HIP, "the fixed scratch array is not bound on this device");
+  hipStream_t st = (hipStream_t)stream;
+  if (A->nrows == 0 || C->nnz == 0) return SG_OK;
+  SG_TRY(validate_input(h, A, "A", st));
+  SG_TRY(validate_input(h, B, "B", st));
+  RowSource r{};
+  r.a_rowptr = A->rowptr;
+  r.a_col = A->col;
+  r.a_val = A->val;
+  r.b_rowptr = B->rowptr;
+  r.b_col = B->col;
+  r.b_val = B->val;
+  r.b_nrows = B->nrows;
+  r.nrows = A->nrows;
+  r.ncols = B->ncols;
+  r.T = tiles_of(B->ncols);
+  Scratch sc{h, base, (size_t)SG_NOALLOC_SCRATCH_BYTES, 0};
+  // call-local views into the fixed array; never released
+  SgBuf ws, off2, task, rp2;
+  SlabBufs sb;
+  const NumBufs bufs{ws, sb, off2, task, rp2};
+  return run_numeric(h, sr, r, B, C, product_key(h, A, B), st, sc, bufs, false);
 }
 
 static sg_status check_parts(sg_handle* h, int nparts, const sg_csr* parts) {

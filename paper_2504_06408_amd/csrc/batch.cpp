@@ -161,9 +161,10 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
     // structure once (patterns do not change after planning); values are
     // re-scattered by every replay
     SG_HIP(h, S.spart.ensure(sizeof(int64_t) * (slab_partials(h, S.src) + 1)));
-    SG_TRY(build_slabs(h, S.sb, S.src, &S.b, P->sr.value_bytes, true, true, (int64_t*)S.spart.p, P->d_flag + 1,
+    Scratch sc{h};
+    SG_TRY(build_slabs(h, sc, S.sb, S.src, &S.b, P->sr.value_bytes, true, true, (int64_t*)S.spart.p, P->d_flag + 1,
                        P->d_flag + kCtrBase, st));
-    SG_TRY(build_dense_rows(h, S.sb, S.src, bp, st));
+    SG_TRY(build_dense_rows(h, sc, S.sb, S.src, bp, st));
   } else {
     S.slab = false;
     S.src.S = 0;
@@ -217,8 +218,9 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   launch_scan_inclusive(S.off + 1, S.R, S.partial, st);
   launch_rebin(S.p, S.nt, S.off, S.R, pn, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, st);
   launch_pool_guard(S.off + S.R, pool_cap(S, (size_t)P->sr.value_bytes), S.bin_count, P->d_flag, st);
+  Scratch sc{h};
   if (S.slab)  // the current values into the partition (buffers sized at plan time)
-    (void)build_slabs(h, S.sb, S.src, &S.b, P->sr.value_bytes, false, true, (int64_t*)S.spart.p, P->d_flag + 1,
+    (void)build_slabs(h, sc, S.sb, S.src, &S.b, P->sr.value_bytes, false, true, (int64_t*)S.spart.p, P->d_flag + 1,
                       P->d_flag + kCtrBase, st);
   NumCtx c{};
   c.src = S.src;

@@ -38,6 +38,19 @@ struct SgBuf {
   }
 };
 
+// Where a call's device scratch comes from: the grow-only buffers (grown
+// with hipMalloc when too small), or consecutive pieces of one fixed device
+// array that is never grown or freed (base != nullptr).  In the fixed mode
+// the SgBuf handed to take() becomes a view into the array; such views are
+// call-local and must never be released.
+struct Scratch {
+  struct sg_handle* h = nullptr;
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  bool fixed() const { return base != nullptr; }
+  sg_status take(SgBuf& b, size_t bytes);
+};
+
 // Column-slab partition of one B (per-row slab bounds, tile offsets inside
 // the segments, segment starts, column ids, (column, value) pairs, each B
 // entry's position) and the dense-row table of the product using it.
@@ -127,10 +140,10 @@ size_t plan_rows_bytes(int64_t nrows);
 // cols, the structure (bounds, tile offsets, segment starts, column ids and
 // each entry's position); with vals, the (column, value) pairs.  partial:
 // slab_partials() int64 of scratch.  Fills r's slab fields.
-sg_status build_slabs(sg_handle* h, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
+sg_status build_slabs(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols, bool vals,
                       int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st);
 // Per dense row of the plan: its A row (first entry, length, row id).
-sg_status build_dense_rows(sg_handle* h, SlabBufs& sb, RowSource& r, const BinPlan& plan, hipStream_t st);
+sg_status build_dense_rows(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, const BinPlan& plan, hipStream_t st);
 // int64 scratch the partition's scan needs (0 when r does not use slabs).
 size_t slab_partials(const sg_handle* h, const RowSource& r);
 // Timing hooks of the handle for a call on stream st (inactive unless the
