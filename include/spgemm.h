@@ -25,9 +25,14 @@
  *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is
  *    queued on it; only the *_symbolic calls and sg_batch_plan wait for it.
  *  - Errors: every call returns an sg_status and never aborts or throws.
- *    sg_last_error() gives a message.  An asynchronous device fault surfaces
- *    as SG_ERR_HIP on a later call.  On failure no output array holds a
- *    partial result that the caller may rely on.
+ *    sg_last_error() gives a message.  An asynchronous HIP fault surfaces as
+ *    SG_ERR_HIP on a later call that waits for the device.  The kernels'
+ *    own consistency check (a numeric pass that filled a different number of
+ *    entries than its symbolic pass counted, or B with unsorted or
+ *    out-of-range columns) sets a device flag that the next *_symbolic call
+ *    on the handle, or sg_handle_check, reports as SG_ERR_INVALID (and
+ *    clears).  On failure no output array holds a partial result that the
+ *    caller may rely on.
  *  - A and B may alias (A.A).  C must not alias A or B.
  *  - One handle serves one host thread at a time.
  */
@@ -71,9 +76,11 @@ typedef enum {
 
 /* Accumulation of SG_PLUS_TIMES_F32 sums (ignored by the other semirings).
  *  SG_ACC_DEFAULT     : compensated (two-sum plus exact product error, kept
- *                       as a float pair per accumulator slot) for rows with
- *                       more than comp_min_terms stored entries in A's row
- *                       and more than comp_min_products products; plain
+ *                       as a float pair per accumulator slot) for hash rows
+ *                       (at most hash_max_products products) with more than
+ *                       comp_min_terms stored entries in A's row and more
+ *                       than comp_min_products products, and for every dense
+ *                       row (more than hash_max_products products); plain
  *                       binary32 otherwise.
  *  SG_ACC_COMPENSATED : compensated for every row that is not a small row
  *                       (at most 64 products).
@@ -119,10 +126,15 @@ sg_status sg_handle_destroy(sg_handle* h);
  * product run per column slab of B over a slab partition of B; 0: per
  * column tile through a per-B-row tile offset table), "gather32" (0/1,
  * default 1: the slab path's gathers use 32-bit offsets when its partition of
- * B spans less than 4 GiB; 0: always 64-bit), "dense_tile_min"
- * (1..2048: a dense row's column tile
- * with at least this many output entries is accumulated in a dense LDS array,
- * smaller ones in an LDS hash table).  Returns SG_ERR_INVALID for an unknown
+ * B spans less than 4 GiB; 0: always 64-bit), "slab_log" (0 = chosen from
+ * B's width, or 14..17: the slab path cuts B's columns into slabs of
+ * 2^slab_log columns), "light_cap" (0 = the light kernel's LDS capacity, or
+ * 1..32768: a dense row's slab with at most this many output entries is a
+ * light task, a fuller one a heavy task; set here it applies to every
+ * semiring), "dense_tile_min" (1..2048, whole-row tile path of batches and
+ * dense_slab=0 only: a dense row's column tile with at least this many
+ * output entries is accumulated in a dense LDS array, smaller ones in an LDS
+ * hash table).  Returns SG_ERR_INVALID for an unknown
  * name or a bad value. */
 sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value);
 
@@ -194,10 +206,24 @@ sg_status sg_batch_execute(sg_plan* plan, void* stream);
 sg_status sg_batch_results(sg_plan* plan, sg_csr* out_C);
 sg_status sg_plan_destroy(sg_plan* plan);
 
-/* Autotuner: times the candidate path thresholds on C = A (x).(+) B with
- * semiring sr and writes the best as a tuning table (JSON) to out_json
- * (host path).  The handle adopts the result.  Waits for its own work. */
+/* Autotuner (paper, Section 4.3: the tunable parameters of the local
+ * multiply): times the whole two-pass product C = A (x).(+) B with semiring
+ * sr under candidate settings of the knobs the default path reads --
+ * "hash_max_products", "slab_log" and "light_cap" (see
+ * sg_handle_set_option) -- walking them one at a time from the defaults, and
+ * writes the fastest as a tuning table (JSON, host path out_json) keyed by
+ * sr's semiring id and value width, with the default and tuned times.  The
+ * handle adopts the result.  Waits for its own work; allocates and frees its
+ * own output buffers. */
 sg_status sg_tune(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg_csr* B, const char* out_json);
+
+/* Adopt the tuning table at host path `path` (written by sg_tune).  With
+ * sr != NULL a table made for another semiring id or value width is refused
+ * with SG_ERR_SEMIRING.  The structural knobs (hash_max_products, slab_log)
+ * apply to every product of the handle; the table's light_cap applies only
+ * to numeric calls with the table's semiring.  sg_handle_create loads its
+ * tuning_json through this call with sr = NULL. */
+sg_status sg_tune_load(sg_handle* h, const sg_semiring* sr, const char* path);
 
 /* Phases timed when the handle option "timing" is "1" (a pair of HIP events
  * is recorded on the call's stream around each phase).  Phases 10..13 are

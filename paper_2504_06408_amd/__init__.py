@@ -33,7 +33,7 @@ STATUS = {0: "SG_OK", -1: "SG_ERR_INVALID", -2: "SG_ERR_SHAPE", -3: "SG_ERR_SEMI
 EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_handle_set_option",
            "sg_spgemm_symbolic", "sg_spgemm_numeric", "sg_spgemm_numeric_noalloc", "sg_spgemm_merge_symbolic",
            "sg_spgemm_merge_numeric",
-           "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune",
+           "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune", "sg_tune_load",
            "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error")
 
 PHASES = ("sym_analyze", "sym_bounds", "sym_small", "sym_hash", "sym_dense", "sym_scan", "num_analyze", "num_small",
@@ -88,6 +88,7 @@ def lib():
             "sg_batch_results": ([P, CSR], ci),
             "sg_plan_destroy": ([P], ci),
             "sg_tune": ([P, SR, CSR, CSR, ctypes.c_char_p], ci),
+            "sg_tune_load": ([P, SR, ctypes.c_char_p], ci),
             "sg_handle_check": ([P], ci),
             "sg_handle_timings": ([P, ctypes.POINTER(ctypes.c_double), ci], ci),
             "sg_handle_stats": ([P, ctypes.POINTER(i64), ci], ci),
@@ -329,6 +330,13 @@ class Handle:
             sr = semiring(sr)
         a, b = A.desc(), B.desc()
         self._rc(lib().sg_tune(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b), out_json.encode()))
+
+    def tune_load(self, sr, path: str) -> None:
+        """Adopt a tuning table; sr (id or descriptor, or None) must match the
+        table's semiring."""
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        self._rc(lib().sg_tune_load(self.ptr, None if sr is None else ctypes.byref(sr), path.encode()))
 
 
 class _DevArray:

@@ -168,7 +168,7 @@ sg_status plan_rows(sg_handle* h, const RowSource& r, const Policy& pol, const i
 
 sg_status build_slabs(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, const sg_csr* B, int vbytes, bool cols,
                       bool vals, int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st) {
-  const int32_t ls = slab_log(r.ncols), S = slab_count(r.ncols, ls);
+  const int32_t ls = slab_log(r.ncols, h->slab_ls), S = slab_count(r.ncols, ls);
   const int64_t nb = B->nrows;
   const size_t ne = (size_t)(B->nnz > 0 ? B->nnz : 1);
   const int32_t G = 1 << (ls - kTileLog);
@@ -210,15 +210,27 @@ sg_status build_dense_rows(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r
   return SG_OK;
 }
 
+int32_t light_cap_for(const sg_handle* h, const sg_semiring* sr) {
+  // a tuned cap belongs to the semiring it was tuned on; a cap set as an
+  // option (tuned_sr == 0) applies to every semiring
+  if (h->light_cap <= 0) return 0;
+  if (h->tuned_sr != 0 && (sr == nullptr || sr->id != h->tuned_sr || sr->value_bytes != h->tuned_vb)) return 0;
+  return h->light_cap;
+}
+
 size_t slab_partials(const sg_handle* h, const RowSource& r) {
   if (r.mode != kModeProduct || !h->slab) return 0;
-  const int32_t ls = slab_log(r.ncols);
+  const int32_t ls = slab_log(r.ncols, h->slab_ls);
   return (size_t)scan_partials_len((int64_t)slab_count(r.ncols, ls) * r.b_nrows);
 }
 
 }  // namespace sg
 
 namespace {
+
+const char* const kInconsistent =
+    "inconsistent structure: a numeric pass filled a different number of entries than its symbolic pass, or B "
+    "holds unsorted or out-of-range columns";
 
 sg_status check_csr(sg_handle* h, const sg_csr* M, const char* name) {
   if (!M) return sg_fail(h, SG_ERR_INVALID, std::string(name) + " is NULL");
@@ -268,6 +280,7 @@ SgCacheKey product_key(const sg_handle* h, const sg_csr* A, const sg_csr* B) {
   k.w[11] = (uint64_t)h->force;
   k.w[12] = (uint64_t)h->hash_max;
   k.w[13] = (uint64_t)h->slab;
+  k.w[14] = (uint64_t)h->slab_ls;
   return k;
 }
 
@@ -350,8 +363,19 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
   mk.mark(kPhSymScan, 0);
   SG_HIP(h, hipGetLastError());
   SG_HIP(h, hipMemcpyAsync(h->h_pin, C_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  // the device-side consistency flag (set by an earlier numeric pass of this
+  // handle, or by this pass's partition of B) comes back with nnz(C)
+  SG_HIP(h, hipMemcpyAsync(h->h_pin + 1, h->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   SG_HIP(h, hipStreamSynchronize(st));
   *nnzC = h->h_pin[0];
+  int32_t flag = 0;
+  std::memcpy(&flag, h->h_pin + 1, sizeof(flag));
+  if (flag) {
+    h->cache_valid = false;
+    launch_fill_i32(h->d_flags, 1, 0, st);
+    (void)hipStreamSynchronize(st);
+    return sg_fail(h, SG_ERR_INVALID, kInconsistent);
+  }
   h->cache_valid = true;
   h->cache_key = key;
   h->cache_T = r.T;
@@ -448,6 +472,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   c.tile_min = h->tile_min;
   c.cus = h->cus;
   c.comp_dense = pol.comp_mode != kCompNone;
+  c.light_cap = light_cap_for(h, sr);
   h->last_nd = nd;
   switch (sr->id) {
     case SG_PLUS_TIMES_I64: launch_numeric_i64(c, st); break;
@@ -505,6 +530,21 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
       return sg_fail(h, SG_ERR_INVALID, "dense_tile_min must be in [1, 2048]");
     h->tile_min = (int32_t)x;
     return SG_OK;
+  } else if (n == "slab_log") {
+    char* end = nullptr;
+    const long long x = std::strtoll(value, &end, 10);
+    if (!end || *end || (x != 0 && (x < kSlabLogMin || x > kSlabLogMax)))
+      return sg_fail(h, SG_ERR_INVALID, "slab_log must be 0 (automatic) or in [14, 17]");
+    h->slab_ls = (int32_t)x;
+  } else if (n == "light_cap") {
+    char* end = nullptr;
+    const long long x = std::strtoll(value, &end, 10);
+    if (!end || *end || x < 0 || x > 32768)
+      return sg_fail(h, SG_ERR_INVALID, "light_cap must be 0 (the LDS capacity) or in [1, 32768]");
+    h->light_cap = (int32_t)x;
+    h->tuned_sr = 0;  // set by hand: applies to every semiring
+    h->tuned_vb = 0;
+    return SG_OK;
   } else if (n == "dense_slab") {
     if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "dense_slab must be 0 or 1");
     h->slab = v == "1";
@@ -537,8 +577,6 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
   return SG_OK;
 }
 
-
-sg_status sg_tune_load(sg_handle* h, const char* path);  // tune.cpp
 
 sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out) {
   if (!out) return SG_ERR_INVALID;
@@ -584,7 +622,7 @@ sg_status sg_handle_create(int device, const char* tuning_json, sg_handle** out)
   }
   const char* tj = tuning_json ? tuning_json : env("SG_TUNING");
   if (tj) {
-    const sg_status s = sg_tune_load(h, tj);
+    const sg_status s = sg_tune_load(h, nullptr, tj);
     if (s != SG_OK) {
       sg_handle_destroy(h);
       return s;
@@ -790,9 +828,7 @@ sg_status sg_handle_check(sg_handle* h) {
   SG_HIP(h, hipMemcpy(&v, h->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (v) {
     SG_HIP(h, hipMemset(h->d_flags, 0, sizeof(int32_t)));
-    return sg_fail(h, SG_ERR_INVALID,
-                   "inconsistent structure: a numeric pass filled a different number of entries than its symbolic "
-                   "pass, or B holds unsorted or out-of-range columns");
+    return sg_fail(h, SG_ERR_INVALID, kInconsistent);
   }
   return SG_OK;
 }

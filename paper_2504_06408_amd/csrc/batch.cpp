@@ -239,6 +239,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   }
   c.tile_min = h->tile_min;
   c.cus = h->cus;
+  c.light_cap = light_cap_for(h, &P->sr);
   c.comp_dense = pn.comp_mode != kCompNone;
   switch (P->sr.id) {
     case SG_PLUS_TIMES_I64: launch_numeric_i64(c, st); break;

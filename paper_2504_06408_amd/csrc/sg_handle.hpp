@@ -111,6 +111,10 @@ struct sg_handle {
   int slab = 1;              // dense rows of single products use the column-slab path
   int gather32 = 1;          // slab symbolic gathers at 32-bit offsets where B allows
   int32_t tile_min = sg::kTileMinDefault;
+  int32_t slab_ls = 0;     // slab width 2^slab_ls of the column-slab path (0: chosen from ncols)
+  int32_t light_cap = 0;   // most entries of a light slab task (0: the LDS capacity)
+  int32_t tuned_sr = 0;    // semiring (id, value bytes) a loaded tuning table was made for
+  int32_t tuned_vb = 0;
   std::vector<sg::PartDesc> parts_host;
   bool cache_valid = false;
   SgCacheKey cache_key{};
@@ -144,6 +148,9 @@ sg_status build_slabs(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, con
                       int64_t* partial, int32_t* err, int32_t* qctr, hipStream_t st);
 // Per dense row of the plan: its A row (first entry, length, row id).
 sg_status build_dense_rows(sg_handle* h, Scratch& sc, SlabBufs& sb, RowSource& r, const BinPlan& plan, hipStream_t st);
+// Light-task cap of a numeric call with semiring sr (0: the kernel's LDS
+// capacity); a tuned cap applies only to the semiring it was tuned on.
+int32_t light_cap_for(const sg_handle* h, const sg_semiring* sr);
 // int64 scratch the partition's scan needs (0 when r does not use slabs).
 size_t slab_partials(const sg_handle* h, const RowSource& r);
 // Timing hooks of the handle for a call on stream st (inactive unless the

@@ -92,7 +92,8 @@ struct NumCtx {
   int32_t* slab_book;    // ... and their bucket bookkeeping (6*T + 3 ints)
   int32_t tile_min;
   int cus;
-  int comp_dense;  // float sums: dense rows use compensated accumulation
+  int comp_dense;     // float sums: dense rows use compensated accumulation
+  int32_t light_cap;  // slab path: most entries of a light task (0: the LDS capacity)
 };
 
 // Bytes of the dense-row task buffer: three task lists of task_cap entries
@@ -108,6 +109,10 @@ inline int32_t slab_log(int64_t ncols) {
   int32_t ls = kSlabLogMin;
   while (ls < kSlabLogMax && ((int64_t)1 << ls) * 8 < ncols) ++ls;
   return ls;
+}
+// The same with a tuned width (0: the default above).
+inline int32_t slab_log(int64_t ncols, int32_t tuned) {
+  return tuned >= kSlabLogMin && tuned <= kSlabLogMax ? tuned : slab_log(ncols);
 }
 inline int32_t slab_count(int64_t ncols, int32_t ls) {
   return (int32_t)((ncols + ((int64_t)1 << ls) - 1) >> ls);
@@ -200,6 +205,7 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
   constexpr int kSlabCap = slab_cap<Sr>();
   if constexpr (kProduct) {
     if (slab) {
+      const int32_t cap = c.light_cap > 0 && c.light_cap < kSlabCap ? c.light_cap : kSlabCap;
       const int32_t T = c.src.T;
       const int32_t nd = c.plan.bins.nd_cap;  // bucket capacity (the count itself may only be on the device)
       int32_t* sbook = c.slab_book;
@@ -210,7 +216,7 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
       hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)T, 256, 1024)), dim3(256), 0, st, sbook,
                          3 * (int64_t)T, (int32_t)0);
       hipLaunchKernelGGL(k_slab_tasks<256>, dim3(grid_for(nd, 256, c.cus * 8)), dim3(256), 0, st, c.plan.bins,
-                         c.src.drow, c.off2, T, G, c.src.S, (int32_t)kSlabCap, (const int64_t*)c.C.rowptr, light,
+                         c.src.drow, c.off2, T, G, c.src.S, cap, (const int64_t*)c.C.rowptr, light,
                          heavy, sbook, c.task_ctr);
       hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, sbook, T, c.task_ctr);
       SlabB<V> b{c.src.prow, c.src.pbit, (const ColV<V>*)c.src.pval, c.src.rpt, c.src.b_nrows, G, T};

@@ -163,3 +163,55 @@ def test_gather32_option_errors(h):
     import paper_2504_06408_amd as sg
     with pytest.raises(sg.SgError):
         h.set_option("gather32", 2)
+
+
+def _reset_knobs(h):
+    h.set_option("slab_log", 0)
+    h.set_option("light_cap", 0)
+    _reset(h)
+
+
+@pytest.mark.parametrize("sr", ALL)
+@pytest.mark.parametrize("ls", [14, 15, 17])
+@pytest.mark.parametrize("cap", [0, 200])
+def test_slab_width_and_light_cap(h, sr, ls, cap):
+    """The tunable slab width and light-task cap: an s11 R-MAT times a B of
+    70,000 columns (five column tiles, the last one ragged) with every row
+    dense, so slab widths of 1, 2 and 8 tiles (one slab wider than B) and a cap
+    that sends most slabs to the heavy kernel all meet the oracle."""
+    _reset_knobs(h)
+    h.set_option("force_path", "dense")
+    h.set_option("slab_log", ls)
+    h.set_option("light_cap", cap)
+    try:
+        A = with_vals(synth.rmat(11, 16, seed=300), sr, 301)
+        B = with_vals(synth.er(2048, 70000, 40, 302), sr, 303)
+        check_product(h, sr, A, B, what=f"slab_log={ls} light_cap={cap}")
+        check_product(h, sr, A, A, what=f"A.A slab_log={ls} light_cap={cap}")
+    finally:
+        _reset_knobs(h)
+
+
+def test_light_cap_moves_tasks_to_heavy(h):
+    """A smaller light cap turns light slab tasks into heavy ones (the task
+    statistics of the numeric pass), with the same result."""
+    _reset_knobs(h)
+    h.set_option("force_path", "dense")
+    try:
+        A = with_vals(synth.rmat(12, 16, seed=310), MINPLUS, 311)
+        check_product(h, MINPLUS, A, A, what="light_cap default")
+        s0 = h.stats()
+        h.set_option("light_cap", 64)
+        check_product(h, MINPLUS, A, A, what="light_cap 64")
+        s1 = h.stats()
+        assert s1["tile_tasks"] > s0["tile_tasks"] and s1["slab_tasks"] < s0["slab_tasks"], (s0, s1)
+        assert s0["slab_entries"] + s0["tile_entries"] == s1["slab_entries"] + s1["tile_entries"]
+    finally:
+        _reset_knobs(h)
+
+
+def test_knob_option_errors(h):
+    import paper_2504_06408_amd as sg
+    for name, bad in [("slab_log", 13), ("slab_log", 18), ("light_cap", -1), ("light_cap", 40000)]:
+        with pytest.raises(sg.SgError):
+            h.set_option(name, bad)

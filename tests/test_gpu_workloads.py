@@ -83,20 +83,36 @@ def test_precision_fp32_vs_fp64(h):
 
 
 def test_autotuner_writes_table(h, tmp_path):
+    """The tuner searches the knobs the slab path reads and keys its table by
+    semiring and value width; a tuned handle (and a new handle made from the
+    table) still meets the oracle; a table made for another semiring is
+    refused."""
     import paper_2504_06408_amd as sg
     h.set_option("force_path", "auto")
-    A = with_vals(synth.rmat(11, 16, seed=3), MINPLUS, 4)
+    A = with_vals(synth.rmat(12, 16, seed=3), MINPLUS, 4)
     dA = to_dev(A)
     path = os.path.join(str(tmp_path), "tune.json")
     h.tune(sg.semiring(MINPLUS), dA, dA, path)
     t = json.load(open(path))
-    assert 0 <= t["hash_max_products"] <= 4096 and t["semiring"] == MINPLUS
-    # the tuned handle still matches the oracle; a new handle loads the table
+    assert t["semiring"] == MINPLUS and t["value_bytes"] == 4
+    assert t["hash_max_products"] in (1024, 2048, 4096)
+    assert 14 <= t["slab_log"] <= 17
+    assert t["light_cap"] in (8192, 4096, 2048)
+    assert t["tuned_ms"] <= t["default_ms"] and len(t["timings_ms"]) >= 5
     check_product(h, MINPLUS, A, A, what="tuned")
     h2 = sg.Handle(0, tuning=path)
-    check_product(h2, MINPLUS, A, A, what="loaded table")
-    h2.close()
+    try:
+        check_product(h2, MINPLUS, A, A, what="handle made from the table")
+        h2.tune_load(MINPLUS, path)
+        with pytest.raises(sg.SgError) as e:
+            h2.tune_load(F64, path)
+        assert e.value.status == -3
+    finally:
+        h2.close()
+    # the autotuner leaves the handle on the tuned settings; restore the defaults
     h.set_option("hash_max_products", 4096)
+    h.set_option("slab_log", 0)
+    h.set_option("light_cap", 0)
 
 
 @pytest.mark.parametrize("sr", [BOOL, I64])
