@@ -336,4 +336,163 @@ def all_pins():
     out.append(("invariants", pin_invariants))
     out.append(("shortest_paths", pin_shortest_paths))
     out.append(("golden", pin_golden))
+    out.append(("power_minplus", pin_power_minplus))
+    out.append(("power_bool_int", pin_power_bool_int))
+    out.append(("dcsc", pin_dcsc))
     return out
+
+
+# ---- powers (paper, Section 2.2) -------------------------------------------------
+
+def _bellman_ford_rounds(n, W, rounds):
+    """All-pairs lightest paths of at most `rounds` edges by synchronous
+    Bellman-Ford relaxation over W's edge list (a textbook algorithm, not a
+    matrix product): distance 0 to itself, +inf elsewhere, then `rounds`
+    rounds in which every edge (u, v, w) offers d[s, u] + w to d[s, v]."""
+    u = np.repeat(np.arange(n), np.diff(W.rowptr))
+    v = W.col.astype(np.int64)
+    w = W.val.astype(np.float64)
+    d = np.full((n, n), np.inf)
+    np.fill_diagonal(d, 0.0)
+    for _ in range(rounds):
+        nd = d.copy()
+        for e in range(len(u)):
+            np.minimum(nd[:, v[e]], d[:, u[e]] + w[e], out=nd[:, v[e]])
+        d = nd
+    return d
+
+
+def _dense_of(M, absent):
+    d = np.full((M.nrows, M.ncols), absent, dtype=np.float64)
+    d[np.repeat(np.arange(M.nrows), np.diff(M.rowptr)), M.col] = M.val
+    return d
+
+
+def pin_power_minplus(orc):
+    """(min,+) powers of I (+) W: k linear steps equal k rounds of
+    Bellman-Ford; squaring to the fixed point equals scipy's all-pairs
+    shortest paths (the distance matrix) and agrees with linear steps."""
+    from oracle import power as pw
+    n = 48
+    W = synth.random_small(n, n, 0.06, 500)
+    W = W.with_values(rand_values(MINPLUS, W.nnz, 501, "int"))
+    for k in (1, 2, 3, 5):
+        r = pw.power(orc, MINPLUS, W, k, self_loops=True)
+        assert r.hops == k and r.products == k - 1
+        assert np.array_equal(_dense_of(r.D, np.inf), _bellman_ford_rounds(n, W, k)), f"(min,+) {k} hops"
+    fix = pw.power(orc, MINPLUS, W, 0, self_loops=True, squaring=True, fixpoint=True)
+    assert fix.converged
+    dense = sp.csr_matrix((W.val.astype(np.float64), W.col, W.rowptr), shape=(n, n))
+    assert np.array_equal(_dense_of(fix.D, np.inf), shortest_path(dense, method="D", directed=True))
+    lin = pw.power(orc, MINPLUS, W, 0, self_loops=True, fixpoint=True)
+    assert lin.converged and pw.same(lin.D, fix.D)
+    sq4 = pw.power(orc, MINPLUS, W, 4, self_loops=True, squaring=True)
+    assert sq4.hops == 4 and sq4.products == 2
+    assert pw.same(sq4.D, pw.power(orc, MINPLUS, W, 4, self_loops=True).D)
+    # every pair i < j joined directly (heavy edge, weight 10 (j - i)^2) and
+    # through the chain of unit edges: the pattern of the powers is final at
+    # once, the values keep falling until paths of 7 edges are allowed
+    m = 8
+    iu, ju = np.triu_indices(m, 1)
+    Wt = synth.CSR(m, m, np.concatenate([[0], np.cumsum(np.bincount(iu, minlength=m))]).astype(np.int64),
+                   ju.astype(np.int32), np.where(ju - iu == 1, 1.0, 10.0 * (ju - iu) ** 2).astype(np.float32))
+    fix = pw.power(orc, MINPLUS, Wt, 0, self_loops=True, squaring=True, fixpoint=True)
+    ref = np.where(np.arange(m)[None, :] >= np.arange(m)[:, None], np.arange(m)[None, :] - np.arange(m)[:, None], np.inf)
+    assert fix.converged and np.array_equal(_dense_of(fix.D, np.inf), ref), "values fall after the pattern is final"
+    # without self loops: walks of exactly two edges (the hand-worked golden)
+    g = _read_golden("minplus_4node.txt")
+    W4, _ = _dense_to_csr(g["W"], "inf")
+    r = pw.power(orc, MINPLUS, W4.with_values(W4.val.astype(np.float32)), 2)
+    assert np.array_equal(_dense_of(r.D, np.inf), g["W2"])
+
+
+def pin_power_bool_int(orc):
+    """(or,and) closure of I (+) W = reachability (scipy breadth-first
+    shortest paths are finite); (+,x) int64 W^k = numpy's integer matrix
+    power (walk counts); float64 W^3 = scipy's sparse product chain."""
+    from oracle import power as pw
+    n = 40
+    W = synth.random_small(n, n, 0.05, 510)
+    Wb = W.with_values(np.ones(W.nnz, np.uint8))
+    fix = pw.power(orc, BOOL, Wb, 0, self_loops=True, squaring=True, fixpoint=True)
+    assert fix.converged
+    reach = np.isfinite(shortest_path(sp.csr_matrix((np.ones(W.nnz), W.col, W.rowptr), shape=(n, n)),
+                                      unweighted=True, directed=True))
+    got = _dense_of(fix.D, 0) != 0
+    assert np.array_equal(got, reach), "(or,and) closure"
+    assert fix.D.nrows == n and len(fix.D.col) == int(reach.sum())
+    Wi = W.with_values(rand_values(I64, W.nnz, 511, "positive"))
+    r = pw.power(orc, I64, Wi, 4)
+    dense = np.zeros((n, n), np.int64)
+    dense[np.repeat(np.arange(n), np.diff(W.rowptr)), W.col] = Wi.val
+    ref = np.linalg.matrix_power(dense, 4)
+    got = np.zeros((n, n), np.int64)
+    got[np.repeat(np.arange(n), np.diff(r.D.rowptr)), r.D.col] = r.D.val
+    assert np.array_equal(got, ref), "(+,x) int64 W^4"
+    Wf = W.with_values(rand_values(F64, W.nnz, 512, "positive"))
+    r = pw.power(orc, F64, Wf, 3)
+    S = sp.csr_matrix((Wf.val, W.col, W.rowptr), shape=(n, n))
+    S3 = (S @ S @ S).tocsr()
+    S3.sort_indices()
+    assert np.array_equal(r.D.rowptr, S3.indptr) and np.array_equal(r.D.col, S3.indices)
+    np.testing.assert_allclose(r.D.val, S3.data, rtol=1e-13)
+
+
+# ---- DCSC / CSC adapter (paper, Section 4.1) -------------------------------------
+
+def pin_dcsc(orc):
+    """Decompression and compression against the hand-worked example and
+    against scipy's column pointers of a hypersparse matrix (non-empty
+    columns taken from its coordinate list); CSC products against scipy."""
+    from oracle import dcsc as dc
+    g = _read_golden("dcsc_4x7.txt")
+    jc = g["JC"][0].astype(np.int32)
+    cp = g["CP"][0].astype(np.int64)
+    assert np.array_equal(dc.decompress(7, jc, cp), g["COLPTR"][0].astype(np.int64))
+    j2, c2 = dc.compress(g["COLPTR"][0].astype(np.int64))
+    assert np.array_equal(j2, jc) and np.array_equal(c2, cp)
+    A = sp.csc_matrix(g["A"])
+    assert np.array_equal(A.indptr, g["COLPTR"][0]) and np.array_equal(A.indices, g["IR"][0])
+    # hypersparse: 60 x 3000 with ~90 entries, most columns empty
+    H = sp.random(60, 3000, density=0.0005, format="coo", random_state=np.random.RandomState(7))
+    Hc = H.tocsc()
+    Hc.sort_indices()
+    cols, counts = np.unique(H.col, return_counts=True)
+    cp_h = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    assert np.array_equal(dc.decompress(3000, cols.astype(np.int32), cp_h), Hc.indptr)
+    j3, c3 = dc.compress(Hc.indptr)
+    assert np.array_equal(j3, cols) and np.array_equal(c3, cp_h)
+    # CSC products (A is 50 x 70, B is 70 x 40, positive values: no cancellation)
+    rs = np.random.RandomState(8)
+    Ad = sp.random(50, 70, density=0.08, format="csc", random_state=rs, data_rvs=lambda k: rs.uniform(0.5, 2, k))
+    Bd = sp.random(70, 40, density=0.08, format="csc", random_state=rs, data_rvs=lambda k: rs.uniform(0.5, 2, k))
+    for M in (Ad, Bd):
+        M.sort_indices()
+    Acsc = dc.Csc(50, 70, Ad.indptr.astype(np.int64), Ad.indices.astype(np.int32), Ad.data)
+    Bcsc = dc.Csc(70, 40, Bd.indptr.astype(np.int64), Bd.indices.astype(np.int32), Bd.data)
+    Ar = dc.csc_to_csr(Acsc)
+    Acr = Ad.tocsr()
+    Acr.sort_indices()
+    assert np.array_equal(Ar.rowptr, Acr.indptr) and np.array_equal(Ar.col, Acr.indices)
+    C = dc.csc_spgemm(orc, F64, Acsc, Bcsc)
+    R = (Ad @ Bd).tocsc()
+    R.sort_indices()
+    assert np.array_equal(C.colptr, R.indptr) and np.array_equal(C.row, R.indices)
+    np.testing.assert_allclose(C.val, R.data, rtol=1e-14)
+    Ci = dc.csc_spgemm(orc, I64, dc.Csc(50, 70, Acsc.colptr, Acsc.row, np.round(Ad.data * 4).astype(np.int64)),
+                       dc.Csc(70, 40, Bcsc.colptr, Bcsc.row, np.round(Bd.data * 4).astype(np.int64)))
+    Ri = (sp.csc_matrix((np.round(Ad.data * 4), Ad.indices, Ad.indptr), shape=(50, 70)) @
+          sp.csc_matrix((np.round(Bd.data * 4), Bd.indices, Bd.indptr), shape=(70, 40))).tocsc()
+    Ri.sort_indices()
+    assert np.array_equal(Ci.colptr, Ri.indptr) and np.array_equal(Ci.val, Ri.data.astype(np.int64))
+    # a square pair: A.B differs from B.A, so operand order is pinned too
+    Sq = sp.random(30, 30, density=0.1, format="csc", random_state=rs, data_rvs=lambda k: rs.uniform(0.5, 2, k))
+    Tq = sp.random(30, 30, density=0.1, format="csc", random_state=rs, data_rvs=lambda k: rs.uniform(0.5, 2, k))
+    for M in (Sq, Tq):
+        M.sort_indices()
+    C = dc.csc_spgemm(orc, F64, dc.Csc(30, 30, Sq.indptr.astype(np.int64), Sq.indices.astype(np.int32), Sq.data),
+                      dc.Csc(30, 30, Tq.indptr.astype(np.int64), Tq.indices.astype(np.int32), Tq.data))
+    R = (Sq @ Tq).tocsc()
+    R.sort_indices()
+    assert np.array_equal(C.colptr, R.indptr) and np.array_equal(C.row, R.indices)
+    np.testing.assert_allclose(C.val, R.data, rtol=1e-14)

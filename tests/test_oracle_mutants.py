@@ -36,3 +36,35 @@ def test_mutant_is_caught(tmp_path, k):
         if caught:
             break
     assert caught, f"no pin caught mutant {k} ({MUTANTS[k]})"
+
+
+# planted mistakes in the Python parts of the oracle (module switch MUTANT)
+PY_MUTANTS = {
+    ("power", 1): "linear powers multiply by the current power instead of W'",
+    ("power", 2): "self loops are never merged in",
+    ("power", 3): "the fixed-point test ignores the values",
+    ("dcsc", 4): "decompression counts the column itself as before it",
+    ("dcsc", 5): "compression drops the last non-empty column",
+    ("dcsc", 6): "the CSC product multiplies in the wrong order",
+}
+
+
+@pytest.mark.parametrize("mod,k", sorted(PY_MUTANTS), ids=[f"{m}{k}" for m, k in sorted(PY_MUTANTS)])
+def test_python_mutant_is_caught(orc, mod, k):
+    import importlib
+    m = importlib.import_module(f"oracle.{mod}")
+    caught = []
+    m.MUTANT = k
+    try:
+        for name, fn in all_pins():
+            try:
+                fn(orc)
+            except AssertionError:
+                caught.append(name)
+            except Exception as e:
+                caught.append(f"{name}:{type(e).__name__}")
+            if caught:
+                break
+    finally:
+        m.MUTANT = 0
+    assert caught, f"no pin caught {mod} mutant {k} ({PY_MUTANTS[(mod, k)]})"
