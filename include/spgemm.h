@@ -225,6 +225,75 @@ sg_status sg_tune(sg_handle* h, const sg_semiring* sr, const sg_csr* A, const sg
  * tuning_json through this call with sr = NULL. */
 sg_status sg_tune_load(sg_handle* h, const sg_semiring* sr, const char* path);
 
+/* ---- Column-major operands (paper, Section 4.1 and Algorithm 1) ----------
+ * CSC: colptr int64[ncols+1], row int32[nnz] (ascending within a column),
+ * val[nnz].  DCSC keeps only the nzc non-empty columns: jc int32[nzc]
+ * (their ids, ascending), cp int64[nzc+1] (cp[i] = first entry of column
+ * jc[i], cp[nzc] = nnz), row and val as in CSC.  All arrays are device
+ * pointers owned by the caller. */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  int64_t* colptr; /* device, ncols+1 */
+  int32_t* row;    /* device, nnz */
+  void* val;       /* device, nnz values */
+} sg_csc;
+
+typedef struct {
+  int64_t nrows, ncols, nzc, nnz;
+  int32_t* jc;  /* device, nzc */
+  int64_t* cp;  /* device, nzc+1 */
+  int32_t* row; /* device, nnz */
+  void* val;    /* device, nnz values */
+} sg_dcsc;
+
+/* Decompress DCSC column pointers (Algorithm 1): colptr[j] (device,
+ * caller-allocated, ncols+1) = the entries of the columns before j, so every
+ * column the compressed list skips gets an empty segment.  The row and
+ * value arrays need no change: with colptr they form A in CSC.  Does not
+ * wait for the stream. */
+sg_status sg_dcsc_decompress(sg_handle* h, const sg_dcsc* A, int64_t* colptr, void* stream);
+
+/* Compress CSC column pointers colptr[0..ncols] (device) to DCSC: jc (device,
+ * capacity ncols) and cp (device, capacity ncols+1) receive the non-empty
+ * columns and their offsets, *nzc (host) their count.  Waits for the
+ * stream. */
+sg_status sg_dcsc_compress(sg_handle* h, int64_t ncols, const int64_t* colptr, int32_t* jc, int64_t* cp,
+                           int64_t* nzc, void* stream);
+
+/* C = A (x).(+) B for CSC operands, C in CSC (Section 4.1: the CSC arrays of
+ * a matrix are the CSR arrays of its transpose and AB = (B^T A^T)^T, so the
+ * product runs as the CSR product of the swapped operands with no copy or
+ * transposition).  Each product is formed as b_kj (x) a_ik, which equals
+ * a_ik (x) b_kj for the five semirings (all have commutative (x)).  Same
+ * two-pass convention as sg_spgemm_symbolic/numeric, with column pointers in
+ * place of row pointers. */
+sg_status sg_spgemm_csc_symbolic(sg_handle* h, const sg_csc* A, const sg_csc* B, int64_t* C_colptr, int64_t* nnzC,
+                                 void* stream);
+sg_status sg_spgemm_csc_numeric(sg_handle* h, const sg_semiring* sr, const sg_csc* A, const sg_csc* B, sg_csc* C,
+                                void* stream);
+
+/* ---- Powers of a square matrix (paper, Section 2.2) ------------------------
+ * Over (min,+) the k-th power of a weighted adjacency matrix W holds the
+ * lightest walks of exactly k edges; with the semiring one on the diagonal
+ * (W' = I (+) W, flag SG_POWER_SELF_LOOPS) the shortest paths of at most k
+ * edges, which stop changing at the distance matrix.  Over (or,and) the
+ * powers of I (+) W give reachability, over (+,x) walk counts.
+ * sg_power_run computes D_1 = W' and then D_{h+1} = D_h W' (linear steps)
+ * or D_{2h} = D_h D_h (SG_POWER_SQUARING) with the product entry points,
+ * until h >= max_hops (max_hops <= 0: twice the matrix size), or, with
+ * SG_POWER_FIXPOINT (needs SG_POWER_SELF_LOOPS and (min,+) or (or,and)),
+ * until a product equals its left operand in pattern and value bits.  The
+ * result lives in memory the power object owns (until sg_power_destroy);
+ * sg_power_result gives a descriptor of it, the exponent h it holds, the
+ * number of products run and whether the fixed point was reached.  Waits
+ * for the stream. */
+enum { SG_POWER_SELF_LOOPS = 1, SG_POWER_SQUARING = 2, SG_POWER_FIXPOINT = 4 };
+typedef struct sg_power sg_power;
+sg_status sg_power_run(sg_handle* h, const sg_semiring* sr, const sg_csr* W, int32_t max_hops, uint32_t flags,
+                       void* stream, sg_power** out);
+sg_status sg_power_result(const sg_power* p, sg_csr* D, int32_t* hops, int32_t* products, int32_t* converged);
+sg_status sg_power_destroy(sg_power* p);
+
 /* Phases timed when the handle option "timing" is "1" (a pair of HIP events
  * is recorded on the call's stream around each phase).  Phases 10..13 are
  * single kernels nested inside phases 4 and 9. */

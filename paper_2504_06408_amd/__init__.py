@@ -34,7 +34,10 @@ EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_hand
            "sg_spgemm_symbolic", "sg_spgemm_numeric", "sg_spgemm_numeric_noalloc", "sg_spgemm_merge_symbolic",
            "sg_spgemm_merge_numeric",
            "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune", "sg_tune_load",
-           "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error")
+           "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error",
+           "sg_dcsc_decompress", "sg_dcsc_compress", "sg_spgemm_csc_symbolic", "sg_spgemm_csc_numeric",
+           "sg_power_run", "sg_power_result", "sg_power_destroy")
+POWER_SELF_LOOPS, POWER_SQUARING, POWER_FIXPOINT = 1, 2, 4
 
 PHASES = ("sym_analyze", "sym_bounds", "sym_small", "sym_hash", "sym_dense", "sym_scan", "num_analyze", "num_small",
           "num_hash", "num_dense", "sym_dense_bitmap", "num_dense_slab", "num_dense_tiles", "num_dense_ranges")
@@ -55,6 +58,17 @@ class sg_semiring(ctypes.Structure):
 class sg_csr(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class sg_csc(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("colptr", ctypes.c_void_p), ("row", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class sg_dcsc(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nzc", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("jc", ctypes.c_void_p), ("cp", ctypes.c_void_p), ("row", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
 
 
 _lib = None
@@ -92,6 +106,15 @@ def lib():
             "sg_handle_check": ([P], ci),
             "sg_handle_timings": ([P, ctypes.POINTER(ctypes.c_double), ci], ci),
             "sg_handle_stats": ([P, ctypes.POINTER(i64), ci], ci),
+            "sg_dcsc_decompress": ([P, ctypes.POINTER(sg_dcsc), P, P], ci),
+            "sg_dcsc_compress": ([P, i64, P, P, P, ctypes.POINTER(i64), P], ci),
+            "sg_spgemm_csc_symbolic": ([P, ctypes.POINTER(sg_csc), ctypes.POINTER(sg_csc), P, ctypes.POINTER(i64), P],
+                                       ci),
+            "sg_spgemm_csc_numeric": ([P, SR, ctypes.POINTER(sg_csc), ctypes.POINTER(sg_csc), ctypes.POINTER(sg_csc),
+                                       P], ci),
+            "sg_power_run": ([P, SR, CSR, i32, ctypes.c_uint32, P, ctypes.POINTER(P)], ci),
+            "sg_power_result": ([P, CSR, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ci),
+            "sg_power_destroy": ([P], ci),
             "sg_status_string": ([ci], ctypes.c_char_p),
             "sg_last_error": ([P], ctypes.c_char_p),
         }
@@ -160,6 +183,27 @@ class DeviceCSR:
         cl = self.col.cpu().numpy()
         vl = None if self.val is None else self.val.cpu().numpy()
         return rp, cl, vl
+
+
+class DeviceCSC:
+    """CSC matrix in device memory: colptr int64[ncols+1], row int32[nnz]
+    (ascending within a column), val[nnz]."""
+
+    def __init__(self, nrows: int, ncols: int, colptr, row, val=None):
+        self.nrows, self.ncols = int(nrows), int(ncols)
+        self.colptr, self.row, self.val = colptr, row, val
+        self.nnz = int(row.numel())
+
+    def desc(self) -> sg_csc:
+        d = sg_csc()
+        d.nrows, d.ncols, d.nnz = self.nrows, self.ncols, self.nnz
+        d.colptr = self.colptr.data_ptr()
+        d.row = self.row.data_ptr() if self.nnz else 0
+        d.val = self.val.data_ptr() if (self.val is not None and self.nnz) else 0
+        return d
+
+    def to_numpy(self):
+        return self.colptr.cpu().numpy(), self.row.cpu().numpy(), (None if self.val is None else self.val.cpu().numpy())
 
 
 def _torch_dtype(sid: int):
@@ -330,6 +374,83 @@ class Handle:
             sr = semiring(sr)
         a, b = A.desc(), B.desc()
         self._rc(lib().sg_tune(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b), out_json.encode()))
+
+    # ---- column-major operands -----------------------------------------------------
+    def dcsc_decompress(self, nrows: int, ncols: int, jc, cp, row, val=None, stream=None) -> "DeviceCSC":
+        """CSC view of a DCSC matrix (device tensors jc int32[nzc], cp
+        int64[nzc+1], row, val): new column pointers, the same row and value
+        tensors."""
+        torch = _torch()
+        colptr = torch.empty(ncols + 1, dtype=torch.int64, device=cp.device)
+        d = sg_dcsc()
+        d.nrows, d.ncols, d.nzc, d.nnz = nrows, ncols, int(jc.numel()), int(row.numel())
+        d.jc = jc.data_ptr() if jc.numel() else 0
+        d.cp = cp.data_ptr()
+        d.row = row.data_ptr() if row.numel() else 0
+        d.val = val.data_ptr() if (val is not None and val.numel()) else 0
+        self._rc(lib().sg_dcsc_decompress(self.ptr, ctypes.byref(d), ctypes.c_void_p(colptr.data_ptr()),
+                                          _stream_ptr(stream)))
+        return DeviceCSC(nrows, ncols, colptr, row, val)
+
+    def dcsc_compress(self, colptr, stream=None):
+        """(jc, cp) device tensors of the non-empty columns of colptr."""
+        torch = _torch()
+        ncols = int(colptr.numel()) - 1
+        jc = torch.empty(max(ncols, 1), dtype=torch.int32, device=colptr.device)
+        cp = torch.empty(ncols + 1, dtype=torch.int64, device=colptr.device)
+        nzc = ctypes.c_int64()
+        self._rc(lib().sg_dcsc_compress(self.ptr, ncols, ctypes.c_void_p(colptr.data_ptr()),
+                                        ctypes.c_void_p(jc.data_ptr()), ctypes.c_void_p(cp.data_ptr()),
+                                        ctypes.byref(nzc), _stream_ptr(stream)))
+        k = int(nzc.value)
+        return jc[:k], cp[:k + 1]
+
+    def spgemm_csc(self, sr, A: "DeviceCSC", B: "DeviceCSC", stream=None) -> "DeviceCSC":
+        """C = A (x).(+) B for CSC operands, C in CSC (both passes)."""
+        torch = _torch()
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        a, b = A.desc(), B.desc()
+        colptr = torch.empty(B.ncols + 1, dtype=torch.int64, device=A.colptr.device)
+        nnz = ctypes.c_int64()
+        self._rc(lib().sg_spgemm_csc_symbolic(self.ptr, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.c_void_p(colptr.data_ptr()), ctypes.byref(nnz),
+                                              _stream_ptr(stream)))
+        dev = A.colptr.device
+        C = DeviceCSC(A.nrows, B.ncols, colptr, torch.empty(nnz.value, dtype=torch.int32, device=dev),
+                      torch.empty(nnz.value, dtype=_torch_dtype(sr.id), device=dev))
+        c = C.desc()
+        self._rc(lib().sg_spgemm_csc_numeric(self.ptr, ctypes.byref(sr), ctypes.byref(a), ctypes.byref(b),
+                                             ctypes.byref(c), _stream_ptr(stream)))
+        return C
+
+    # ---- powers -------------------------------------------------------------------
+    def power(self, sr, W: DeviceCSR, max_hops: int, self_loops: bool = False, squaring: bool = False,
+              fixpoint: bool = False, stream=None):
+        """(D, hops, products, converged): D = W'^hops (W' = I (+) W with
+        self loops) as a DeviceCSR of fresh tensors (sg_power_run)."""
+        torch = _torch()
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        flags = (POWER_SELF_LOOPS if self_loops else 0) | (POWER_SQUARING if squaring else 0) | \
+                (POWER_FIXPOINT if fixpoint else 0)
+        w = W.desc()
+        p = ctypes.c_void_p()
+        self._rc(lib().sg_power_run(self.ptr, ctypes.byref(sr), ctypes.byref(w), int(max_hops), flags,
+                                    _stream_ptr(stream), ctypes.byref(p)))
+        try:
+            d = sg_csr()
+            hops, prods, conv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            self._rc(lib().sg_power_result(p, ctypes.byref(d), ctypes.byref(hops), ctypes.byref(prods),
+                                           ctypes.byref(conv)))
+            dev = W.rowptr.device
+            D = DeviceCSR(d.nrows, d.ncols, _wrap(d.rowptr, d.nrows + 1, np.int64, dev).clone(),
+                          _wrap(d.col, d.nnz, np.int32, dev).clone(),
+                          _wrap(d.val, d.nnz, NP_DTYPE[sr.id], dev).clone())
+            torch.cuda.synchronize(dev)
+        finally:
+            lib().sg_power_destroy(p)
+        return D, int(hops.value), int(prods.value), bool(conv.value)
 
     def tune_load(self, sr, path: str) -> None:
         """Adopt a tuning table; sr (id or descriptor, or None) must match the
