@@ -303,6 +303,96 @@ def summa_parity(sg, A, g, plan, nprod, per_bin=8):
     return out
 
 
+def summa_waves_leg(sg, torch, h, scale, budget_frac=0.9, per_bin=4):
+    """The 8x8 Sparse SUMMA emulation at a scale whose 512 stage outputs do
+    not fit the GPU together (scale 22: ~1.1 TB of fp64 stage outputs): every
+    product is sized by a symbolic pass, the 64 output blocks are cut into
+    waves whose outputs fit a budget, and each wave runs as one batched plan
+    (graph replay) that is checked and freed before the next.  Time: the sum
+    of the waves' replays (each plan's one-off build is reported apart).
+    Check: the block identity (paper, Section 2.1) on stratified rows."""
+    import oracle
+    import synth
+    t0 = time.perf_counter()
+    A = synth.rmat(scale, 16, seed=1)
+    A = A.with_values(synth.values(synth.VAL_F64_UNIFORM, A.nnz, 0, 1, 2))
+    g = 8
+    blk = synth.block_split(A, g)
+    t_gen = time.perf_counter() - t0
+    dblk = [[sg.DeviceCSR.from_host(blk[I][J]) for J in range(g)] for I in range(g)]
+    As, Bs, go = [], [], [0]
+    prods = 0
+    for I in range(g):
+        for J in range(g):
+            for K in range(g):
+                As.append(dblk[I][K])
+                Bs.append(dblk[K][J])
+                prods += int(np.diff(blk[K][J].rowptr)[blk[I][K].col].sum())
+            go.append(len(As))
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(budget_frac * free)
+    sr = sg.semiring(sg.PLUS_TIMES_F64)
+    t0 = time.perf_counter()
+    W = h.waves(sr, As, Bs, go, budget)
+    t_size = time.perf_counter() - t0
+    print(f"# s{scale} waves: {W.count} waves, {sum(W.product_nnz)} stage-output entries, sized in {t_size:.1f}s",
+          file=sys.stderr, flush=True)
+    # sampled rows of the whole product: per row, its pieces from the g merged
+    # blocks of its block row, collected wave by wave
+    p = products_per_row(A, A)
+    rows = stratified_rows(p, per_bin, 7)
+    rb = -(-A.nrows // g)
+    cb = -(-A.ncols // g)
+    pieces = {}
+    waves, t_plan = [], 0.0
+    for w in range(W.count):
+        t0 = time.perf_counter()
+        W.run(w)  # builds the plan (one eager pass) and replays it once
+        torch.cuda.synchronize()
+        t_plan += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        W.run(w)  # the timed replay
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res = W.results()
+        g0, g1 = W.wave_groups[w], W.wave_groups[w + 1]
+        nprod = go[g1] - go[g0]
+        wp = 0
+        for grp in range(g0, g1):
+            I, J = divmod(grp, g)
+            wp += sum(int(np.diff(blk[K][J].rowptr)[blk[I][K].col].sum()) for K in range(g))
+            view = sg.view_results(res[nprod + grp - g0], 3)
+            for r in rows:
+                if int(r) // rb == I:
+                    _, bcl, bvl = _device_rows(view, [int(r) % rb])
+                    pieces[(int(r), J)] = (bcl.astype(np.int64) + J * cb, bvl)
+        waves.append({"groups": g1 - g0, "products": wp, "out_bytes_bound": int(W.wave_bytes[w]),
+                      "ms": round(ms, 3)})
+        print(f"# wave {w}: {g1 - g0} blocks, {wp:.3e} products, {ms:.1f} ms", file=sys.stderr, flush=True)
+    W.destroy()
+    del dblk, As, Bs
+    torch.cuda.empty_cache()
+    g_rp = np.zeros(len(rows) + 1, np.int64)
+    cols, vals = [], []
+    for k, r in enumerate(rows):
+        n_r = 0
+        for J in range(g):
+            c, v = pieces[(int(r), J)]
+            cols.append(c)
+            vals.append(v)
+            n_r += len(c)
+        g_rp[k + 1] = g_rp[k] + n_r
+    ref = oracle.get().spgemm(3, A, A, rows=rows)
+    par = compare_rows(3, g_rp, np.concatenate(cols).astype(np.int32), np.concatenate(vals), ref)
+    par["check"] = "merged blocks across each sampled row vs the oracle's full A.A"
+    ms_total = sum(x["ms"] for x in waves)
+    return {"workload": f"R-MAT s{scale} cut 8x8, 512 fp64 (+,x) stage products + 64 merges, in waves",
+            "products": prods, "stage_output_entries": int(sum(W.product_nnz)), "waves": waves,
+            "wave_budget_bytes": budget, "ms_batched": round(ms_total, 3),
+            "batched_products_per_s": prods / (ms_total * 1e-3), "plan_s": round(t_plan, 2),
+            "sizing_s": round(t_size, 2), "generation_s": round(t_gen, 2), "parity_sample": par}
+
+
 def three_hop_leg(sg, torch, h, A, dA, steps):
     """(min,+) 3-hop on a seeded panel S of 4096 non-empty rows of the s20
     graph: X1 = A[S,:].A, X2 = X1.A (rows S of (A.A).A).  Timed as the two
@@ -539,6 +629,8 @@ def main():
     ap.add_argument("--hash-max", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched legs")
     ap.add_argument("--summa-scale", type=int, default=18, help="R-MAT scale of the 8x8 SUMMA leg (0: skip)")
+    ap.add_argument("--summa-waves-scale", type=int, default=22,
+                    help="R-MAT scale of the 8x8 SUMMA leg run in memory-budgeted waves (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the s18, 3-hop, precision and ER-batch legs")
     ap.add_argument("--er-batch", type=int, default=256, help="ER products in the batch leg (0: skip)")
@@ -595,6 +687,14 @@ def main():
         if args.summa_scale > 0:
             out["summa"] = summa_leg(sg, torch, h, args.summa_scale, args.steps)
             print(f"# summa leg {out['summa']['ms_batched']} ms", file=sys.stderr, flush=True)
+        if args.summa_waves_scale > 0:
+            t_w = time.perf_counter()
+            try:
+                out["summa_waves"] = summa_waves_leg(sg, torch, h, args.summa_waves_scale)
+            except sg.SgError as e:
+                out["summa_waves"] = {"error": str(e)}
+            torch.cuda.empty_cache()
+            print(f"# summa waves leg in {time.perf_counter() - t_w:.1f}s", file=sys.stderr, flush=True)
     if not args.no_extra and args.workload == "rmat20_minplus":
         t_x = time.perf_counter()
         for name in ("rmat18_bool", "rmat18_i64"):

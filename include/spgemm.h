@@ -206,6 +206,33 @@ sg_status sg_batch_execute(sg_plan* plan, void* stream);
 sg_status sg_batch_results(sg_plan* plan, sg_csr* out_C);
 sg_status sg_plan_destroy(sg_plan* plan);
 
+/* Memory-budgeted waves of a batch (Section 2.1, at a scale whose stage
+ * outputs exceed the GPU: e.g. the 512 stage products of an 8 x 8 SUMMA grid
+ * at R-MAT scale 22 hold ~1.1 TB).  group_offsets (host, ngroups+1, from 0
+ * to nprob, ascending) cuts the products into merge groups, as in
+ * sg_batch_plan; every product belongs to one group.  sg_waves_plan sizes
+ * each product's output with a symbolic pass and cuts the groups, in order,
+ * into waves whose output bytes (each group: its products' entries twice --
+ * the stage outputs and their merge, which holds at most as many -- times
+ * 4 + value_bytes) stay within budget_bytes; a group above the budget gives
+ * SG_ERR_NOMEM.  sg_waves_info reports the wave count, each product's nnz
+ * (product_nnz: nprob entries), the wave offsets over the groups
+ * (wave_groups: nwaves+1 entries) and each wave's output bytes (wave_bytes:
+ * nwaves entries); any of them may be NULL.  sg_waves_run makes wave w
+ * current -- freeing the previous wave's plan and building this wave's with
+ * sg_batch_plan when w is not already current -- and replays its graph on
+ * `stream`; sg_waves_results fills out_C with the current wave's results as
+ * sg_batch_results does: its products, then its merges.  The operands must
+ * stay unchanged and alive until sg_waves_destroy. */
+typedef struct sg_waves sg_waves;
+sg_status sg_waves_plan(sg_handle* h, const sg_semiring* sr, int nprob, const sg_csr* A, const sg_csr* B,
+                        int ngroups, const int32_t* group_offsets, size_t budget_bytes, sg_waves** out);
+sg_status sg_waves_info(const sg_waves* w, int* nwaves, int64_t* product_nnz, int32_t* wave_groups,
+                        size_t* wave_bytes);
+sg_status sg_waves_run(sg_waves* w, int wave, void* stream);
+sg_status sg_waves_results(sg_waves* w, sg_csr* out_C);
+sg_status sg_waves_destroy(sg_waves* w);
+
 /* Autotuner (paper, Section 4.3: the tunable parameters of the local
  * multiply): times the whole two-pass product C = A (x).(+) B with semiring
  * sr under candidate settings of the knobs the default path reads --

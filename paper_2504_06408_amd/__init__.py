@@ -36,7 +36,8 @@ EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_hand
            "sg_batch_plan", "sg_batch_execute", "sg_batch_results", "sg_plan_destroy", "sg_tune", "sg_tune_load",
            "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error",
            "sg_dcsc_decompress", "sg_dcsc_compress", "sg_spgemm_csc_symbolic", "sg_spgemm_csc_numeric",
-           "sg_power_run", "sg_power_result", "sg_power_destroy")
+           "sg_power_run", "sg_power_result", "sg_power_destroy", "sg_waves_plan", "sg_waves_info", "sg_waves_run",
+           "sg_waves_results", "sg_waves_destroy")
 POWER_SELF_LOOPS, POWER_SQUARING, POWER_FIXPOINT = 1, 2, 4
 
 PHASES = ("sym_analyze", "sym_bounds", "sym_small", "sym_hash", "sym_dense", "sym_scan", "num_analyze", "num_small",
@@ -115,6 +116,12 @@ def lib():
             "sg_power_run": ([P, SR, CSR, i32, ctypes.c_uint32, P, ctypes.POINTER(P)], ci),
             "sg_power_result": ([P, CSR, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ci),
             "sg_power_destroy": ([P], ci),
+            "sg_waves_plan": ([P, SR, ci, CSR, CSR, ci, ctypes.POINTER(i32), ctypes.c_size_t, ctypes.POINTER(P)], ci),
+            "sg_waves_info": ([P, ctypes.POINTER(ci), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                               ctypes.POINTER(ctypes.c_size_t)], ci),
+            "sg_waves_run": ([P, ci, P], ci),
+            "sg_waves_results": ([P, CSR], ci),
+            "sg_waves_destroy": ([P], ci),
             "sg_status_string": ([ci], ctypes.c_char_p),
             "sg_last_error": ([P], ctypes.c_char_p),
         }
@@ -250,6 +257,48 @@ class Plan:
             pass
 
 
+class Waves:
+    """Memory-budgeted waves of a batch (sg_waves_*)."""
+
+    def __init__(self, handle: "Handle", ptr, nprob: int, group_offsets, keep):
+        self.handle, self.ptr, self.nprob, self._keep = handle, ptr, nprob, keep
+        self.group_offsets = list(group_offsets)
+        n = ctypes.c_int()
+        handle._rc(lib().sg_waves_info(ptr, ctypes.byref(n), None, None, None))
+        self.count = int(n.value)
+        nnz = (ctypes.c_int64 * nprob)()
+        wg = (ctypes.c_int32 * (self.count + 1))()
+        wb = (ctypes.c_size_t * self.count)()
+        handle._rc(lib().sg_waves_info(ptr, ctypes.byref(n), nnz, wg, wb))
+        self.product_nnz = list(nnz)
+        self.wave_groups = list(wg)
+        self.wave_bytes = list(wb)
+        self.current = -1
+
+    def run(self, wave: int, stream=None):
+        self.handle._rc(lib().sg_waves_run(self.ptr, wave, _stream_ptr(stream)))
+        self.current = wave
+
+    def results(self) -> List[sg_csr]:
+        """The current wave's products, then its merges (views into its pool)."""
+        g0, g1 = self.wave_groups[self.current], self.wave_groups[self.current + 1]
+        n = (self.group_offsets[g1] - self.group_offsets[g0]) + (g1 - g0)
+        arr = (sg_csr * n)()
+        self.handle._rc(lib().sg_waves_results(self.ptr, arr))
+        return list(arr)
+
+    def destroy(self):
+        if self.ptr:
+            lib().sg_waves_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 class Handle:
     def __init__(self, device: int = 0, tuning: Optional[str] = None):
         p = ctypes.c_void_p()
@@ -368,6 +417,18 @@ class Handle:
         p = ctypes.c_void_p()
         self._rc(lib().sg_batch_plan(self.ptr, ctypes.byref(sr), n, a, b, ng, go, pool_bytes, ctypes.byref(p)))
         return Plan(self, p, n, ng, (As, Bs, sr))
+
+    def waves(self, sr, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], group_offsets, budget_bytes: int) -> Waves:
+        if isinstance(sr, int):
+            sr = semiring(sr)
+        n = len(As)
+        a = (sg_csr * n)(*[x.desc() for x in As])
+        b = (sg_csr * n)(*[x.desc() for x in Bs])
+        go = (ctypes.c_int32 * len(group_offsets))(*group_offsets)
+        p = ctypes.c_void_p()
+        self._rc(lib().sg_waves_plan(self.ptr, ctypes.byref(sr), n, a, b, len(group_offsets) - 1, go,
+                                     int(budget_bytes), ctypes.byref(p)))
+        return Waves(self, p, n, group_offsets, (As, Bs, sr))
 
     def tune(self, sr, A: DeviceCSR, B: DeviceCSR, out_json: str) -> None:
         if isinstance(sr, int):

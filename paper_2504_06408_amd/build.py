@@ -21,7 +21,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 SOURCES = ["k_struct.hip", "num_i64.hip", "num_f32.hip", "num_f64.hip", "num_bool.hip", "num_minplus.hip",
-           "api.cpp", "tune.cpp", "batch.cpp", "k_batch.hip", "k_adapt.hip", "adapt.cpp"]
+           "api.cpp", "tune.cpp", "batch.cpp", "k_batch.hip", "k_adapt.hip", "adapt.cpp", "waves.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -188,8 +188,8 @@ sg_status run_stage_eager(sg_plan* P, Stage& S, bool has_dense_inputs) {
 sg_status alloc_pool(sg_plan* P, Stage& S) {
   const size_t vb = (size_t)P->sr.value_bytes;
   const size_t n = (size_t)(S.nnz > 0 ? S.nnz : 1);
-  SG_HIP(P->h, S.col_buf.ensure(n * sizeof(int32_t)));
-  SG_HIP(P->h, S.val_buf.ensure(n * vb));
+  SG_HIP(P->h, S.col_buf.ensure(n * sizeof(int32_t), true));
+  SG_HIP(P->h, S.val_buf.ensure(n * vb, true));
   return SG_OK;
 }
 

@@ -19,10 +19,12 @@ constexpr int kFlagInts = kCtrBase + sg::kCtrInts;
 struct SgBuf {
   void* p = nullptr;
   size_t cap = 0;
-  hipError_t ensure(size_t bytes) {
+  // exact: allocate bytes only, with no headroom for later growth (pools
+  // sized once, where a quarter more can be tens of GB)
+  hipError_t ensure(size_t bytes, bool exact = false) {
     if (bytes <= cap && p) return hipSuccess;
     release();
-    const size_t nb = bytes + bytes / 4 + 4096;
+    const size_t nb = exact ? (bytes > 0 ? bytes : 1) : bytes + bytes / 4 + 4096;
     hipError_t e = hipMalloc(&p, nb);
     if (e != hipSuccess) {
       p = nullptr;
