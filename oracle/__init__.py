@@ -5,9 +5,10 @@ and the CPU-baseline leg of ``bench.py`` may import this package; the GPU
 library never does.  It shares no code with the GPU path: both are fed from
 the ``synth`` input generators only.
 
-What it computes: rows of C = A (x).(+) B over one of five semirings
-(paper, Section 2.2) and the entry-wise (+) merge of partial products
-(paper, Section 4.4), by plain row-by-row Gustavson with a ``std::map``
+What it computes: rows of C = A (x).(+) B over one of five semirings, or
+one of three semirings a user would define at run time (paper, Section
+2.2), and the entry-wise (+) merge of partial products (paper, Section
+4.4), by plain row-by-row Gustavson with a ``std::map``
 accumulator (``oracle.cpp`` has the definitions).  Results come back as numpy
 CSR arrays.
 """
@@ -28,9 +29,16 @@ DEFAULT_LIB = os.path.join(HERE, "liboracle.so")
 # enum by value only)
 PLUS_TIMES_I64, PLUS_TIMES_F32, PLUS_TIMES_F64, OR_AND_BOOL, MIN_PLUS_F32 = 1, 2, 3, 4, 5
 SEMIRINGS = (PLUS_TIMES_I64, PLUS_TIMES_F32, PLUS_TIMES_F64, OR_AND_BOOL, MIN_PLUS_F32)
-IN_DTYPE = {1: np.int64, 2: np.float32, 3: np.float64, 4: np.uint8, 5: np.float32}
-OUT_DTYPE = {1: np.int64, 2: np.float64, 3: np.float64, 4: np.uint8, 5: np.float32}
-NAMES = {1: "plus_times_i64", 2: "plus_times_f32", 3: "plus_times_f64", 4: "or_and_bool", 5: "min_plus_f32"}
+# semirings a user of the library would define at run time (the oracle's own
+# definitions of three of them)
+MAX_PLUS_F32, MAX_TIMES_F64, MIN_MAX_I64 = 6, 7, 8
+USER_SEMIRINGS = (MAX_PLUS_F32, MAX_TIMES_F64, MIN_MAX_I64)
+IN_DTYPE = {1: np.int64, 2: np.float32, 3: np.float64, 4: np.uint8, 5: np.float32, 6: np.float32, 7: np.float64,
+            8: np.int64}
+OUT_DTYPE = {1: np.int64, 2: np.float64, 3: np.float64, 4: np.uint8, 5: np.float32, 6: np.float32, 7: np.float64,
+             8: np.int64}
+NAMES = {1: "plus_times_i64", 2: "plus_times_f32", 3: "plus_times_f64", 4: "or_and_bool", 5: "min_plus_f32",
+         6: "max_plus_f32", 7: "max_times_f64", 8: "min_max_i64"}
 
 
 @dataclass

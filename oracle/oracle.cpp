@@ -28,6 +28,14 @@
 //   4  (or, and) bool : uint8, nonzero means true; result 0/1
 //   5  (min, +) f32   : (x) is float32 addition (rounded), (+) is the minimum
 //                       under IEEE '<'; 0 = +inf, 1 = +0.0
+//   6  (max, +) f32   : (x) is float32 addition (rounded), (+) the maximum
+//   7  (max, x) f64   : (x) is float64 multiplication (rounded), (+) the
+//                       maximum
+//   8  (min, max) i64 : (x) is the maximum, (+) the minimum (bottleneck
+//                       paths)
+// Ids 6..8 are semirings the paper's abstraction lets a user define (the
+// entry type, (+) and (x) redefined); the library builds such semirings at
+// run time, and these are the oracle's own definitions of three of them.
 // For the float sums it also returns, per entry, sum_k |A_ik * B_kj| in
 // float64 (the scale a rounding-error bound is relative to).
 //
@@ -136,6 +144,54 @@ struct MinPlusF32 {
     return (y < x) ? y : x;
 #endif
   }
+  static out_t out(acc_t x) { return x; }
+  static double mag(acc_t) { return 0.0; }
+};
+
+struct MaxPlusF32 {
+  using in_t = float;
+  using acc_t = float;
+  using out_t = float;
+  static constexpr bool has_abs = false;
+  static acc_t mul(in_t a, in_t b) {
+    volatile float s = a + b;  // float32 addition, rounded to nearest
+    return s;
+  }
+  static acc_t add(acc_t x, acc_t y) { return (y > x) ? y : x; }
+  static out_t out(acc_t x) { return x; }
+  static double mag(acc_t) { return 0.0; }
+};
+
+struct MaxTimesF64 {
+  using in_t = double;
+  using acc_t = double;
+  using out_t = double;
+  static constexpr bool has_abs = false;
+  static acc_t mul(in_t a, in_t b) { return a * b; }
+  static acc_t add(acc_t x, acc_t y) {
+#if ORACLE_MUTANT == 9
+    return (y < x) ? y : x;  // min instead of max
+#else
+    return (y > x) ? y : x;
+#endif
+  }
+  static out_t out(acc_t x) { return x; }
+  static double mag(acc_t) { return 0.0; }
+};
+
+struct MinMaxI64 {
+  using in_t = int64_t;
+  using acc_t = int64_t;
+  using out_t = int64_t;
+  static constexpr bool has_abs = false;
+  static acc_t mul(in_t a, in_t b) {
+#if ORACLE_MUTANT == 10
+    return (b < a) ? b : a;  // min instead of max
+#else
+    return (b > a) ? b : a;
+#endif
+  }
+  static acc_t add(acc_t x, acc_t y) { return (y < x) ? y : x; }
   static out_t out(acc_t x) { return x; }
   static double mag(acc_t) { return 0.0; }
 };
@@ -293,6 +349,9 @@ void* oracle_spgemm(int sr, int64_t a_nrows, int64_t a_ncols, const int64_t* a_r
     case 3: return spgemm_t<PlusTimesF64>(sr, A, B, rows, nsel, nthreads);
     case 4: return spgemm_t<OrAnd>(sr, A, B, rows, nsel, nthreads);
     case 5: return spgemm_t<MinPlusF32>(sr, A, B, rows, nsel, nthreads);
+    case 6: return spgemm_t<MaxPlusF32>(sr, A, B, rows, nsel, nthreads);
+    case 7: return spgemm_t<MaxTimesF64>(sr, A, B, rows, nsel, nthreads);
+    case 8: return spgemm_t<MinMaxI64>(sr, A, B, rows, nsel, nthreads);
     default: return nullptr;
   }
 }
@@ -309,6 +368,9 @@ void* oracle_merge(int sr, int nparts, int64_t nrows, int64_t ncols, const int64
     case 3: return merge_t<PlusTimesF64>(sr, nparts, parts.data(), rows, nsel, nthreads);
     case 4: return merge_t<OrAnd>(sr, nparts, parts.data(), rows, nsel, nthreads);
     case 5: return merge_t<MinPlusF32>(sr, nparts, parts.data(), rows, nsel, nthreads);
+    case 6: return merge_t<MaxPlusF32>(sr, nparts, parts.data(), rows, nsel, nthreads);
+    case 7: return merge_t<MaxTimesF64>(sr, nparts, parts.data(), rows, nsel, nthreads);
+    case 8: return merge_t<MinMaxI64>(sr, nparts, parts.data(), rows, nsel, nthreads);
     default: return nullptr;
   }
 }

@@ -339,6 +339,7 @@ def all_pins():
     out.append(("power_minplus", pin_power_minplus))
     out.append(("power_bool_int", pin_power_bool_int))
     out.append(("dcsc", pin_dcsc))
+    out.append(("user_semirings", pin_user_semirings))
     return out
 
 
@@ -496,3 +497,68 @@ def pin_dcsc(orc):
     R.sort_indices()
     assert np.array_equal(C.colptr, R.indptr) and np.array_equal(C.row, R.indices)
     np.testing.assert_allclose(C.val, R.data, rtol=1e-14)
+
+
+# ---- semirings a user defines (paper, Section 2.2) ---------------------------------
+
+def _dense_pair(A, B, absent):
+    da = np.full((A.nrows, A.ncols), absent, dtype=np.float64)
+    db = np.full((B.nrows, B.ncols), absent, dtype=np.float64)
+    da[np.repeat(np.arange(A.nrows), np.diff(A.rowptr)), A.col] = A.val
+    db[np.repeat(np.arange(B.nrows), np.diff(B.rowptr)), B.col] = B.val
+    ma = np.zeros(da.shape, bool)
+    mb = np.zeros(db.shape, bool)
+    ma[np.repeat(np.arange(A.nrows), np.diff(A.rowptr)), A.col] = True
+    mb[np.repeat(np.arange(B.nrows), np.diff(B.rowptr)), B.col] = True
+    return da, db, ma, mb
+
+
+def pin_user_semirings(orc):
+    """(max,+) f32 is (min,+) of the negated operands, negated, bit for bit
+    (negation commutes with rounding and swaps min and max); (max,x) f64 and
+    (min,max) int64 equal numpy's dense reductions over k (maximum of the
+    rounded products; minimum of the pairwise maxima) on the stored pairs."""
+    import oracle as o
+    A = synth.rmat(9, 8, seed=600)
+    B = synth.er(512, 300, 5, 601)
+    av = synth.values(synth.VAL_F32_UNIFORM, A.nnz, -50.0, 100.0, 602)
+    bv = synth.values(synth.VAL_F32_UNIFORM, B.nnz, -50.0, 100.0, 603)
+    mx = orc.spgemm(o.MAX_PLUS_F32, A.with_values(av), B.with_values(bv))
+    mn = orc.spgemm(MINPLUS, A.with_values(-av), B.with_values(-bv))
+    assert_same_pattern(mx.rowptr, mx.col, mn.rowptr, mn.col, "(max,+) pattern")
+    assert np.array_equal((-mn.val).view(np.uint32), mx.val.view(np.uint32)), "(max,+) = -(min,+)(-A,-B)"
+    # tiny dense checks
+    for s, (n, k, m) in enumerate([(7, 9, 6), (12, 5, 11), (20, 20, 20)]):
+        At = synth.random_small(n, k, 0.3, 610 + s)
+        Bt = synth.random_small(k, m, 0.3, 620 + s)
+        At = At.with_values(synth.values(synth.VAL_F64_UNIFORM, At.nnz, 0.5, 2.0, 630 + s))
+        Bt = Bt.with_values(synth.values(synth.VAL_F64_UNIFORM, Bt.nnz, 0.5, 2.0, 640 + s))
+        da, db, ma, mb = _dense_pair(At, Bt, 0.0)
+        pair = ma[:, :, None] & mb[None, :, :]
+        prod = np.where(pair, da[:, :, None] * db[None, :, :], -np.inf)
+        ref = prod.max(axis=1)
+        r = orc.spgemm(o.MAX_TIMES_F64, At, Bt)
+        got = np.full((n, m), -np.inf)
+        got[np.repeat(np.arange(n), np.diff(r.rowptr)), r.col] = r.val
+        assert np.array_equal(got, ref), "(max,x) f64 dense"
+        Ai = At.with_values(synth.values(synth.VAL_I64_UNIFORM, At.nnz, -1000, 1000, 650 + s))
+        Bi = Bt.with_values(synth.values(synth.VAL_I64_UNIFORM, Bt.nnz, -1000, 1000, 660 + s))
+        da, db, ma, mb = _dense_pair(Ai, Bi, 0)
+        big = np.iinfo(np.int64).max
+        mm = np.where(pair, np.maximum(da[:, :, None], db[None, :, :]), np.inf)
+        ref = mm.min(axis=1)
+        r = orc.spgemm(o.MIN_MAX_I64, Ai, Bi)
+        got = np.full((n, m), np.inf)
+        got[np.repeat(np.arange(n), np.diff(r.rowptr)), r.col] = r.val
+        assert np.array_equal(got, ref) and big > 0, "(min,max) int64 dense"
+    # merges fold with the semiring's (+)
+    parts = [synth.random_small(15, 17, 0.3, 670 + q) for q in range(3)]
+    parts = [p.with_values(synth.values(synth.VAL_I64_UNIFORM, p.nnz, -9, 9, 680 + q)) for q, p in enumerate(parts)]
+    m = orc.merge(o.MIN_MAX_I64, parts)
+    dense = np.full((3, 15, 17), np.inf)
+    for q, p in enumerate(parts):
+        dense[q][np.repeat(np.arange(15), np.diff(p.rowptr)), p.col] = p.val
+    ref = dense.min(axis=0)
+    got = np.full((15, 17), np.inf)
+    got[np.repeat(np.arange(15), np.diff(m.rowptr)), m.col] = m.val
+    assert np.array_equal(got, ref), "(min,max) merge"

@@ -18,6 +18,8 @@ MUTANTS = {
     6: "|product| sums use the signed value",
     7: "merge forgets the last part",
     8: "int64 products truncated to 32 bits",
+    9: "(max,x) takes the min",
+    10: "(min,max) multiplies by the min",
 }
 
 
