@@ -95,6 +95,28 @@ typedef struct {
   int64_t comp_min_products; /* default 0 */
 } sg_semiring;
 
+/* Semirings defined at run time (paper, Section 2.2: the user redefines the
+ * entry type, (+), (x), zero and one).  value_type is one of "float",
+ * "double", "int32_t", "uint32_t", "int64_t", "uint64_t"; add and mul are
+ * HIP device expressions in the two values a and b (of value_type) that
+ * give a (+) b and a (x) b; zero and one are expressions giving the
+ * identities of (+) and (x) (zero starts every accumulator, so
+ * zero (+) x = x must hold; one is used by sg_power's self loops).  The
+ * expressions may call device math functions (fminf, fmax, ...) and use
+ * INT32_MAX, INT64_MAX, UINT64_MAX and the like.  (+) must be commutative
+ * and associative; any order of folds may occur.  flags: SG_SR_IDEMPOTENT
+ * declares a (+) a = a (then repeated folds of one product are allowed and
+ * sg_power may stop at a fixed point). */
+enum { SG_SR_IDEMPOTENT = 1 };
+typedef struct {
+  const char* value_type;
+  const char* add;
+  const char* mul;
+  const char* zero;
+  const char* one;
+  uint32_t flags;
+} sg_semiring_def;
+
 typedef struct {
   int64_t nrows, ncols, nnz;
   int64_t* rowptr; /* device, nrows+1 */
@@ -109,6 +131,17 @@ typedef struct sg_plan sg_plan;
  * Returns SG_ERR_SEMIRING for an unknown id or flag, SG_ERR_INVALID for
  * out == NULL. */
 sg_status sg_semiring_make(sg_semiring_id id, uint32_t acc_flags, sg_semiring* out);
+
+/* Define a semiring at run time: the library's numeric kernels (small,
+ * hash, column-slab and tile paths) are compiled for it with hipRTC (once
+ * per distinct definition in the process, loaded on each device that uses
+ * it) and *out receives a descriptor (id >= 64, value_bytes of value_type)
+ * for sg_spgemm_numeric, sg_spgemm_numeric_noalloc,
+ * sg_spgemm_merge_numeric, the CSC entry points and sg_power_run; batched
+ * plans (sg_batch_plan, sg_waves_plan) take the five built-in semirings
+ * only.  A definition that does not compile gives SG_ERR_SEMIRING with the
+ * compiler's messages in sg_last_error.  Waits for the device. */
+sg_status sg_semiring_define(sg_handle* h, const sg_semiring_def* def, sg_semiring* out);
 
 /* Create a handle bound to HIP device `device` (made current by every call
  * that uses the handle).  tuning_json: path to a tuning table written by

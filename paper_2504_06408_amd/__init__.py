@@ -37,7 +37,7 @@ EXPORTS = ("sg_semiring_make", "sg_handle_create", "sg_handle_destroy", "sg_hand
            "sg_handle_check", "sg_handle_timings", "sg_handle_stats", "sg_status_string", "sg_last_error",
            "sg_dcsc_decompress", "sg_dcsc_compress", "sg_spgemm_csc_symbolic", "sg_spgemm_csc_numeric",
            "sg_power_run", "sg_power_result", "sg_power_destroy", "sg_waves_plan", "sg_waves_info", "sg_waves_run",
-           "sg_waves_results", "sg_waves_destroy")
+           "sg_waves_results", "sg_waves_destroy", "sg_semiring_define")
 POWER_SELF_LOOPS, POWER_SQUARING, POWER_FIXPOINT = 1, 2, 4
 
 PHASES = ("sym_analyze", "sym_bounds", "sym_small", "sym_hash", "sym_dense", "sym_scan", "num_analyze", "num_small",
@@ -71,6 +71,15 @@ class sg_dcsc(ctypes.Structure):
                 ("nnz", ctypes.c_int64), ("jc", ctypes.c_void_p), ("cp", ctypes.c_void_p), ("row", ctypes.c_void_p),
                 ("val", ctypes.c_void_p)]
 
+
+class sg_semiring_def(ctypes.Structure):
+    _fields_ = [("value_type", ctypes.c_char_p), ("add", ctypes.c_char_p), ("mul", ctypes.c_char_p),
+                ("zero", ctypes.c_char_p), ("one", ctypes.c_char_p), ("flags", ctypes.c_uint32)]
+
+
+SR_IDEMPOTENT = 1
+USER_VALUE_DTYPES = {"float": np.float32, "double": np.float64, "int32_t": np.int32, "uint32_t": np.uint32,
+                     "int64_t": np.int64, "uint64_t": np.uint64}
 
 _lib = None
 
@@ -122,6 +131,7 @@ def lib():
             "sg_waves_run": ([P, ci, P], ci),
             "sg_waves_results": ([P, CSR], ci),
             "sg_waves_destroy": ([P], ci),
+            "sg_semiring_define": ([P, ctypes.POINTER(sg_semiring_def), SR], ci),
             "sg_status_string": ([ci], ctypes.c_char_p),
             "sg_last_error": ([P], ctypes.c_char_p),
         }
@@ -215,7 +225,11 @@ class DeviceCSC:
 
 def _torch_dtype(sid: int):
     torch = _torch()
-    return {1: torch.int64, 2: torch.float32, 3: torch.float64, 4: torch.uint8, 5: torch.float32}[sid]
+    if sid in (1, 2, 3, 4, 5):
+        return {1: torch.int64, 2: torch.float32, 3: torch.float64, 4: torch.uint8, 5: torch.float32}[sid]
+    return {np.dtype(np.float32): torch.float32, np.dtype(np.float64): torch.float64, np.dtype(np.int32): torch.int32,
+            np.dtype(np.uint32): torch.uint32, np.dtype(np.int64): torch.int64,
+            np.dtype(np.uint64): torch.uint64}[np.dtype(NP_DTYPE[sid])]
 
 
 class Plan:
@@ -512,6 +526,17 @@ class Handle:
         finally:
             lib().sg_power_destroy(p)
         return D, int(hops.value), int(prods.value), bool(conv.value)
+
+    def define_semiring(self, value_type: str, add: str, mul: str, zero: str, one: str,
+                        idempotent: bool = False) -> sg_semiring:
+        """A semiring defined at run time (sg_semiring_define): add and mul
+        are device expressions in a and b, zero and one expressions."""
+        d = sg_semiring_def(value_type.encode(), add.encode(), mul.encode(), zero.encode(), one.encode(),
+                            SR_IDEMPOTENT if idempotent else 0)
+        s = sg_semiring()
+        self._rc(lib().sg_semiring_define(self.ptr, ctypes.byref(d), ctypes.byref(s)))
+        NP_DTYPE[s.id] = USER_VALUE_DTYPES[value_type]
+        return s
 
     def tune_load(self, sr, path: str) -> None:
         """Adopt a tuning table; sr (id or descriptor, or None) must match the

@@ -18,6 +18,7 @@
 
 #include "sg_adapt.hpp"
 #include "sg_handle.hpp"
+#include "sg_user.hpp"
 
 using namespace sg;
 
@@ -107,7 +108,9 @@ sg_status power_run(sg_power* P, const sg_semiring* sr, const sg_csr* W, int32_t
     SG_HIP(h, P->id_rp.ensure(sizeof(int64_t) * (size_t)(n + 1)));
     SG_HIP(h, P->id_col.ensure(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     SG_HIP(h, P->id_val.ensure((size_t)vb * (size_t)(n > 0 ? n : 1)));
-    launch_identity(n, one_bits(sr->id), vb, (int64_t*)P->id_rp.p, (int32_t*)P->id_col.p, P->id_val.p, h->cus, st);
+    uint64_t one = one_bits(sr->id);
+    if (sr->id >= kUserSemiringBase) SG_TRY(user_semiring_identities(h, sr->id, nullptr, &one));
+    launch_identity(n, one, vb, (int64_t*)P->id_rp.p, (int32_t*)P->id_col.p, P->id_val.p, h->cus, st);
     const sg_csr parts[2] = {sg_csr{n, n, n, (int64_t*)P->id_rp.p, (int32_t*)P->id_col.p, P->id_val.p}, *W};
     SG_HIP(h, P->rp[2].ensure(sizeof(int64_t) * (size_t)(n + 1)));
     int64_t nnz = 0;
@@ -180,16 +183,18 @@ sg_status sg_power_run(sg_handle* h, const sg_semiring* sr, const sg_csr* W, int
   if (!h || !out) return SG_ERR_INVALID;
   *out = nullptr;
   if (!sr || !W) return sg_fail(h, SG_ERR_INVALID, "semiring or W is NULL");
-  if (sr->id < 1 || sr->id > 5) return sg_fail(h, SG_ERR_SEMIRING, "unknown semiring id");
+  bool idem = sr->id == SG_OR_AND_BOOL || sr->id == SG_MIN_PLUS_F32;
+  const bool user = sr->id >= kUserSemiringBase && user_semiring(sr->id, nullptr, &idem);
+  if (!user && (sr->id < 1 || sr->id > 5)) return sg_fail(h, SG_ERR_SEMIRING, "unknown semiring id");
   if (W->nrows != W->ncols) return sg_fail(h, SG_ERR_SHAPE, "W must be square");
   if (W->nrows < 0 || W->nnz < 0 || !W->rowptr || (W->nnz > 0 && (!W->col || !W->val)))
     return sg_fail(h, SG_ERR_INVALID, "bad W descriptor");
   if (flags & ~(uint32_t)(SG_POWER_SELF_LOOPS | SG_POWER_SQUARING | SG_POWER_FIXPOINT))
     return sg_fail(h, SG_ERR_INVALID, "unknown power flag");
-  if ((flags & SG_POWER_FIXPOINT) &&
-      (!(flags & SG_POWER_SELF_LOOPS) || (sr->id != SG_OR_AND_BOOL && sr->id != SG_MIN_PLUS_F32)))
+  if ((flags & SG_POWER_FIXPOINT) && (!(flags & SG_POWER_SELF_LOOPS) || !idem))
     return sg_fail(h, SG_ERR_INVALID,
-                   "a fixed point needs self loops and an idempotent (+): (or,and) or (min,+)");
+                   "a fixed point needs self loops and an idempotent (+): (or,and), (min,+) or a run-time "
+                   "semiring defined with SG_SR_IDEMPOTENT");
   SG_HIP(h, hipSetDevice(h->device));
   sg_power* P = new sg_power;
   P->h = h;

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "sg_handle.hpp"
+#include "sg_user.hpp"
 
 using namespace sg;
 
@@ -245,6 +246,12 @@ sg_status check_csr(sg_handle* h, const sg_csr* M, const char* name) {
 sg_status check_semiring(sg_handle* h, const sg_semiring* sr) {
   if (!sr) return sg_fail(h, SG_ERR_INVALID, "semiring descriptor is NULL");
   static const int bytes[6] = {0, 8, 4, 8, 1, 4};
+  int vb = 0;
+  if (sr->id >= kUserSemiringBase && user_semiring(sr->id, &vb, nullptr)) {
+    if (sr->value_bytes != vb) return sg_fail(h, SG_ERR_SEMIRING, "value_bytes does not match the semiring");
+    if (sr->acc_flags != SG_ACC_DEFAULT) return sg_fail(h, SG_ERR_SEMIRING, "run-time semirings take no accumulation flag");
+    return SG_OK;
+  }
   if (sr->id < 1 || sr->id > 5) return sg_fail(h, SG_ERR_SEMIRING, "unknown semiring id");
   if (sr->value_bytes != bytes[sr->id]) return sg_fail(h, SG_ERR_SEMIRING, "value_bytes does not match the semiring");
   if (sr->acc_flags > SG_ACC_PLAIN) return sg_fail(h, SG_ERR_SEMIRING, "unknown accumulation flag");
@@ -480,7 +487,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
     case SG_PLUS_TIMES_F64: launch_numeric_f64(c, st); break;
     case SG_OR_AND_BOOL: launch_numeric_bool(c, st); break;
     case SG_MIN_PLUS_F32: launch_numeric_minplus(c, st); break;
-    default: return sg_fail(h, SG_ERR_SEMIRING, "unknown semiring id");
+    default: SG_TRY(launch_numeric_user(h, c, sr->id, st)); break;
   }
   SG_HIP(h, hipGetLastError());
   return SG_OK;

@@ -168,25 +168,39 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   return g < 1 ? 1 : (int)g;
 }
 
-template <class Sr, class Rows, int LGS, int BS>
-inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st) {
-  const int n = c.plan.count[bin];
-  if (n == 0) return;
-  auto k = k_num_hash<Sr, Rows, LGS, BS>;
-  static int occ = occupancy(k, BS);
-  hipLaunchKernelGGL(k, dim3(grid_for(n, 1, c.cus * occ * 4)), dim3(BS), 0, st, rows, c.plan.bins, bin, c.C, c.err);
+// A numeric kernel to launch: a kernel compiled into the library (fn, its
+// host stub) or a function of a module compiled at run time (mod), with the
+// workgroups of its block size that fit one CU.
+struct KRef {
+  const void* fn = nullptr;
+  hipFunction_t mod = nullptr;
+  int occ = 1;
+  bool ok() const { return fn != nullptr || mod != nullptr; }
+};
+
+inline KRef kref_static(const void* fn, int bs) {
+  KRef k;
+  k.fn = fn;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, bs, 0) == hipSuccess && n >= 1) k.occ = n;
+  return k;
 }
 
-template <class Sr, class Rows>
-inline void launch_num_hash_all(const Rows& rows, const NumCtx& c, int bin0, hipStream_t st) {
-  launch_num_hash_one<Sr, Rows, 7, 256>(rows, c, bin0 + 0, st);
-  launch_num_hash_one<Sr, Rows, 8, 256>(rows, c, bin0 + 1, st);
-  launch_num_hash_one<Sr, Rows, 9, 256>(rows, c, bin0 + 2, st);
-  launch_num_hash_one<Sr, Rows, 10, 256>(rows, c, bin0 + 3, st);
-  launch_num_hash_one<Sr, Rows, 11, 512>(rows, c, bin0 + 4, st);
-  launch_num_hash_one<Sr, Rows, 12, 512>(rows, c, bin0 + 5, st);
-  // the largest table with 4-byte accumulators leaves LDS for 1024 threads
-  launch_num_hash_one<Sr, Rows, 13, sizeof(typename Sr::Acc) <= 4 ? 1024 : 512>(rows, c, bin0 + 6, st);
+inline KRef kref_module(hipFunction_t f, int bs) {
+  KRef k;
+  k.mod = f;
+  int n = 0;
+  if (f && hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, bs, 0) == hipSuccess && n >= 1) k.occ = n;
+  return k;
+}
+
+// Launch k with kernel arguments args, which must have exactly the types of
+// the kernel's parameters (they are passed by address).
+template <class... A>
+inline void klaunch(const KRef& k, dim3 grid, dim3 block, hipStream_t st, A... args) {
+  void* p[] = {(void*)&args...};
+  if (k.mod) (void)hipModuleLaunchKernel(k.mod, grid.x, grid.y, grid.z, block.x, block.y, block.z, 0, st, p, nullptr);
+  else (void)hipLaunchKernel(k.fn, grid, block, p, 0, st);
 }
 
 // Dense rows: build the tile and range task lists from the per-tile counts,
@@ -195,8 +209,75 @@ constexpr int kRangeLg = 12;          // range tasks: hash table of 4096 slots
 constexpr int kRangeCap = 2048;       // entries per range task
 constexpr int kTileMinDefault = 1024; // entries that make a tile a dense-tile task
 
-template <class Sr, class Rows>
-inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) {
+// Block sizes of the numeric kernels (shared by the launchers and by the
+// run-time compilation of semirings, which instantiates the same kernels).
+// Hash bins: table of 2^(7+k) slots, k = 0..6; the largest table with 4-byte
+// accumulators leaves LDS for 1024 threads.
+constexpr int kHashBins = 7;
+constexpr int hash_bs(int k, int acc_bytes) { return k < 4 ? 256 : (k < 6 ? 512 : (acc_bytes <= 4 ? 1024 : 512)); }
+// Dense tiles: 8-byte accumulators need the whole LDS for one 16384-slot
+// tile, so a 1024-thread workgroup (16 waves) when the per-source items are
+// small.
+constexpr int tiles_bs(int acc_bytes, int item_bytes) { return (acc_bytes >= 8 && item_bytes <= 8) ? 1024 : 512; }
+constexpr int ranges_bs(int acc_bytes) { return acc_bytes >= 8 ? 256 : 512; }
+constexpr int kSlabBS = 512;
+
+// The library's own kernels (compiled in for the five semirings).
+struct KLib {
+  template <class Sr, class Rows>
+  KRef small() const {
+    static const KRef k = kref_static((const void*)k_num_small<Sr, Rows>, 256);
+    return k;
+  }
+  template <class Sr, class Rows, int LGS, int BS>
+  KRef hash() const {
+    static const KRef k = kref_static((const void*)k_num_hash<Sr, Rows, LGS, BS>, BS);
+    return k;
+  }
+  template <class Sr, int kCap, bool kNarrow>
+  KRef slab() const {
+    static const KRef k = kref_static((const void*)k_num_slab<Sr, typename Sr::V, kSlabBS, kCap, kNarrow>, kSlabBS);
+    return k;
+  }
+  template <class Sr, bool kNarrow>
+  KRef heavy() const {
+    static const KRef k = kref_static((const void*)k_num_slab_heavy<Sr, typename Sr::V, kSlabBS, kNarrow>, kSlabBS);
+    return k;
+  }
+  template <class Sr, class Rows, int BS>
+  KRef tiles() const {
+    static const KRef k = kref_static((const void*)k_num_tiles<Sr, Rows, BS>, BS);
+    return k;
+  }
+  template <class Sr, class Rows, int LGS, int BS>
+  KRef ranges() const {
+    static const KRef k = kref_static((const void*)k_num_ranges<Sr, Rows, LGS, BS>, BS);
+    return k;
+  }
+};
+
+template <class Sr, class Rows, int LGS, int BS, class Kp>
+inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st, const Kp& kp) {
+  const int n = c.plan.count[bin];
+  if (n == 0) return;
+  const KRef k = kp.template hash<Sr, Rows, LGS, BS>();
+  klaunch(k, dim3(grid_for(n, 1, c.cus * k.occ * 4)), dim3(BS), st, rows, c.plan.bins, (int)bin, c.C, c.err);
+}
+
+template <class Sr, class Rows, class Kp>
+inline void launch_num_hash_all(const Rows& rows, const NumCtx& c, int bin0, hipStream_t st, const Kp& kp) {
+  constexpr int A = (int)sizeof(typename Sr::Acc);
+  launch_num_hash_one<Sr, Rows, 7, hash_bs(0, A)>(rows, c, bin0 + 0, st, kp);
+  launch_num_hash_one<Sr, Rows, 8, hash_bs(1, A)>(rows, c, bin0 + 1, st, kp);
+  launch_num_hash_one<Sr, Rows, 9, hash_bs(2, A)>(rows, c, bin0 + 2, st, kp);
+  launch_num_hash_one<Sr, Rows, 10, hash_bs(3, A)>(rows, c, bin0 + 3, st, kp);
+  launch_num_hash_one<Sr, Rows, 11, hash_bs(4, A)>(rows, c, bin0 + 4, st, kp);
+  launch_num_hash_one<Sr, Rows, 12, hash_bs(5, A)>(rows, c, bin0 + 5, st, kp);
+  launch_num_hash_one<Sr, Rows, 13, hash_bs(6, A)>(rows, c, bin0 + 6, st, kp);
+}
+
+template <class Sr, class Rows, class Kp>
+inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st, const Kp& kp) {
   if (c.plan.ndense() == 0) return;
   using V = typename Sr::V;
   constexpr bool kProduct = std::is_same_v<Rows, OneRows<SpgemmSrc<V, true>>>;
@@ -223,23 +304,23 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
       // 32-bit gathers when the (column, value) partition spans less than 4 GiB
       const bool narrow = c.src.gather32 && c.src.b_nnz < ((int64_t)1 << 32) / (int64_t)sizeof(ColV<V>);
       {
-        auto k = narrow ? k_num_slab<Sr, V, 512, kSlabCap, true> : k_num_slab<Sr, V, 512, kSlabCap, false>;
-        static int occ = occupancy(k_num_slab<Sr, V, 512, kSlabCap, true>, 512);
+        const KRef k = narrow ? kp.template slab<Sr, kSlabCap, true>() : kp.template slab<Sr, kSlabCap, false>();
+        const int occ = kp.template slab<Sr, kSlabCap, true>().occ;
         const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
         c.marks.mark(kPhNumDenseSlab, 1);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.C,
-                           (const SlabTask*)light, (const int32_t*)book_off(sbook, T, kListSlab), nd, c.task_ctr,
-                           c.err);
+        klaunch(k, dim3(grid), dim3(kSlabBS), st, b, (const int32_t*)c.src.a_col, (const V*)c.src.a_val, c.C,
+                (const SlabTask*)light, (const int32_t*)book_off(sbook, T, kListSlab), (int32_t)nd, c.task_ctr,
+                c.err);
         c.marks.mark(kPhNumDenseSlab, 0);
       }
       {
-        auto k = narrow ? k_num_slab_heavy<Sr, V, 512, true> : k_num_slab_heavy<Sr, V, 512, false>;
-        static int occ = occupancy(k_num_slab_heavy<Sr, V, 512, true>, 512);
+        const KRef k = narrow ? kp.template heavy<Sr, true>() : kp.template heavy<Sr, false>();
+        const int occ = kp.template heavy<Sr, true>().occ;
         const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
         c.marks.mark(kPhNumDenseTiles, 1);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(512), 0, st, b, c.src.a_col, (const V*)c.src.a_val, c.off2, c.spn,
-                           c.C, (const SlabTask*)heavy, (const int32_t*)book_off(sbook, T, kListTile), nd, c.task_ctr,
-                           c.err);
+        klaunch(k, dim3(grid), dim3(kSlabBS), st, b, (const int32_t*)c.src.a_col, (const V*)c.src.a_val,
+                (const int32_t*)c.off2, (const uint4*)c.spn, c.C, (const SlabTask*)heavy,
+                (const int32_t*)book_off(sbook, T, kListTile), (int32_t)nd, c.task_ctr, c.err);
         c.marks.mark(kPhNumDenseTiles, 0);
       }
       return;
@@ -255,51 +336,46 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st) 
                      c.plan.bins, c.off2, Tmax, 0, 0, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
                      c.tasks + 2 * c.task_cap, book, c.task_ctr);
   hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, Tmax, c.task_ctr);
-  // 8-byte accumulators need the whole LDS for one 16384-slot tile: use a
-  // 1024-thread workgroup (16 waves) when the per-source items are small.
-  constexpr int BS =
-      (sizeof(typename Sr::Acc) >= 8 && sizeof(typename Rows::Src::Item) <= 8) ? 1024 : 512;
-  auto k = k_num_tiles<Sr, Rows, BS>;
-  static int occ = occupancy(k, BS);
-  const int grid = c.cus * occ > kQueues ? c.cus * occ : kQueues;
+  constexpr int BS = tiles_bs((int)sizeof(typename Sr::Acc), (int)sizeof(typename Rows::Src::Item));
+  const KRef k = kp.template tiles<Sr, Rows, BS>();
+  const int grid = c.cus * k.occ > kQueues ? c.cus * k.occ : kQueues;
   c.marks.mark(kPhNumDenseTiles, 1);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(BS), 0, st, rows, c.plan.bins, c.C, c.off2, c.tasks,
-                     (const int32_t*)book, c.task_ctr, c.err);
+  klaunch(k, dim3(grid), dim3(BS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2, (const Task*)c.tasks,
+          (const int32_t*)book, c.task_ctr, c.err);
   c.marks.mark(kPhNumDenseTiles, 0);
-  constexpr int RBS = sizeof(typename Sr::Acc) >= 8 ? 256 : 512;
-  auto k2 = k_num_ranges<Sr, Rows, kRangeLg, RBS>;
-  static int occ2 = occupancy(k2, RBS);
-  const int grid2 = c.cus * occ2 > kQueues ? c.cus * occ2 : kQueues;
+  constexpr int RBS = ranges_bs((int)sizeof(typename Sr::Acc));
+  const KRef k2 = kp.template ranges<Sr, Rows, kRangeLg, RBS>();
+  const int grid2 = c.cus * k2.occ > kQueues ? c.cus * k2.occ : kQueues;
   c.marks.mark(kPhNumDenseRanges, 1);
-  hipLaunchKernelGGL(k2, dim3(grid2), dim3(RBS), 0, st, rows, c.plan.bins, c.C, c.off2,
-                     c.tasks + c.task_cap, (const int32_t*)book, c.task_ctr, c.err);
+  klaunch(k2, dim3(grid2), dim3(RBS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2,
+          (const Task*)(c.tasks + c.task_cap), (const int32_t*)book, c.task_ctr, c.err);
   c.marks.mark(kPhNumDenseRanges, 0);
 }
 
-// Numeric pass for semiring Sr (SrC: its compensated variant, or Sr).
-template <class Sr, class SrC, class Rows>
-inline void launch_numeric_rows(const Rows& rows, const NumCtx& c, hipStream_t st) {
+// Numeric pass for semiring Sr (SrC: its compensated variant, or Sr), with
+// the kernels of provider kp.
+template <class Sr, class SrC, class Rows, class Kp>
+inline void launch_numeric_rows(const Rows& rows, const NumCtx& c, hipStream_t st, const Kp& kp) {
   c.marks.mark(kPhNumSmall, 1);
   if (c.plan.count[kBinSmall]) {
-    auto k = k_num_small<Sr, Rows>;
-    static int occ = occupancy(k, 256);
-    hipLaunchKernelGGL(k, dim3(grid_for(c.plan.count[kBinSmall], 4, c.cus * occ * 4)), dim3(256), 0, st, rows,
-                       c.plan.bins, kBinSmall, c.C, c.err);
+    const KRef k = kp.template small<Sr, Rows>();
+    klaunch(k, dim3(grid_for(c.plan.count[kBinSmall], 4, c.cus * k.occ * 4)), dim3(256), st, rows, c.plan.bins,
+            (int)kBinSmall, c.C, c.err);
   }
   c.marks.mark(kPhNumSmall, 0);
   c.marks.mark(kPhNumHash, 1);
-  launch_num_hash_all<Sr, Rows>(rows, c, kBinHash0, st);
-  launch_num_hash_all<SrC, Rows>(rows, c, kBinHashC0, st);
+  launch_num_hash_all<Sr, Rows>(rows, c, kBinHash0, st, kp);
+  launch_num_hash_all<SrC, Rows>(rows, c, kBinHashC0, st, kp);
   c.marks.mark(kPhNumHash, 0);
   c.marks.mark(kPhNumDense, 1);
-  if (c.comp_dense) launch_num_dense<SrC, Rows>(rows, c, st);
-  else launch_num_dense<Sr, Rows>(rows, c, st);
+  if (c.comp_dense) launch_num_dense<SrC, Rows>(rows, c, st, kp);
+  else launch_num_dense<Sr, Rows>(rows, c, st, kp);
   c.marks.mark(kPhNumDense, 0);
 }
 
-template <class Sr, class SrC>
-inline void launch_numeric(const NumCtx& c, hipStream_t st) {
-  with_rows<typename Sr::V, true>(c.src, [&](const auto& rows) { launch_numeric_rows<Sr, SrC>(rows, c, st); });
+template <class Sr, class SrC, class Kp = KLib>
+inline void launch_numeric(const NumCtx& c, hipStream_t st, const Kp& kp = Kp{}) {
+  with_rows<typename Sr::V, true>(c.src, [&](const auto& rows) { launch_numeric_rows<Sr, SrC>(rows, c, st, kp); });
 }
 
 // ---- entry points implemented in the .hip translation units -------------------------
