@@ -627,6 +627,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hash-max", type=int, default=None)
+    ap.add_argument("--slab-log", type=int, default=None, help="slab width 2^k columns of the dense path (14..17)")
+    ap.add_argument("--light-cap", type=int, default=None, help="most entries of a light slab task")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched legs")
     ap.add_argument("--summa-scale", type=int, default=18, help="R-MAT scale of the 8x8 SUMMA leg (0: skip)")
     ap.add_argument("--summa-waves-scale", type=int, default=22,
@@ -653,6 +655,10 @@ def main():
     h.set_option("timing", 1)
     if args.hash_max is not None:
         h.set_option("hash_max_products", args.hash_max)
+    if args.slab_log is not None:
+        h.set_option("slab_log", args.slab_log)
+    if args.light_cap is not None:
+        h.set_option("light_cap", args.light_cap)
     sr = sg.semiring(sr_id)
     res, C, dA, dB, p = measure_product(sg, torch, h, A, B, sr_id, args.steps, args.warmup, args.hash_max,
                                         args.workload)

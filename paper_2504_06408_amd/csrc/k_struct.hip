@@ -129,6 +129,16 @@ void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_o
   hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, rows, plan.bins, bin, cnt_out);
 }
 
+template <class Rows, int LGS>
+void sym_hash_wave_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
+  const int n = plan.count[bin];
+  if (n == 0) return;
+  constexpr int BS = 256;
+  auto k = k_sym_hash_wave<Rows, LGS, BS>;
+  static int occ = occupancy(k, BS);
+  hipLaunchKernelGGL(k, dim3(grid_for(n, BS / kWave, cus * occ * 4)), dim3(BS), 0, st, rows, plan.bins, bin, cnt_out);
+}
+
 template <class Rows>
 void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
                     hipStream_t st) {
@@ -152,11 +162,12 @@ void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int3
   }
   marks.mark(kPhSymSmall, 0);
   marks.mark(kPhSymHash, 1);
-  // hash bins hold tables of 2^8 .. 2^13 keys (symbolic tables start at 256)
-  sym_hash_one<Rows, 8, 256>(rows, plan, kBinHash0 + 1, cnt_out, cus, st);
-  sym_hash_one<Rows, 9, 256>(rows, plan, kBinHash0 + 2, cnt_out, cus, st);
-  sym_hash_one<Rows, 10, 256>(rows, plan, kBinHash0 + 3, cnt_out, cus, st);
-  sym_hash_one<Rows, 11, 512>(rows, plan, kBinHash0 + 4, cnt_out, cus, st);
+  // hash bins hold tables of 2^8 .. 2^13 keys (symbolic tables start at 256);
+  // rows of up to 1024 products take one wavefront each
+  sym_hash_wave_one<Rows, 8>(rows, plan, kBinHash0 + 1, cnt_out, cus, st);
+  sym_hash_wave_one<Rows, 9>(rows, plan, kBinHash0 + 2, cnt_out, cus, st);
+  sym_hash_wave_one<Rows, 10>(rows, plan, kBinHash0 + 3, cnt_out, cus, st);
+  sym_hash_wave_one<Rows, 11>(rows, plan, kBinHash0 + 4, cnt_out, cus, st);
   sym_hash_one<Rows, 12, 512>(rows, plan, kBinHash0 + 5, cnt_out, cus, st);
   sym_hash_one<Rows, 13, 512>(rows, plan, kBinHash0 + 6, cnt_out, cus, st);
   marks.mark(kPhSymHash, 0);

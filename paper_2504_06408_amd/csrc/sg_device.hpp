@@ -28,6 +28,15 @@ SG_DEV void block_sync() {
 }
 SG_DEV int wave_id() { return (int)(threadIdx.x >> 6); }
 
+// Orders the LDS accesses of one wavefront whose lanes exchange data through
+// LDS with no workgroup barrier: its LDS operations complete before any
+// lane goes on.
+SG_DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 SG_DEV unsigned long long lanes_below() {
   const int l = lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));

@@ -624,6 +624,197 @@ __global__ __launch_bounds__(BS) void k_sym_hash(Rows rows, Bins bins, int bin, 
   }
 }
 
+// Symbolic hash rows, one wavefront per row: each wavefront of the block
+// counts the distinct columns of its own rows in its own LDS table of 2^LGS
+// keys, with no workgroup barrier.  A row's sources are taken 64 at a time
+// (one per lane: a wavefront scan of their segment lengths); the chunk's
+// products are then spread over the lanes, kWaveU per lane per round, each
+// lane finding its product's source by a binary search over the 64 segment
+// offsets and issuing its round's gathers before inserting any column.
+constexpr int kWaveU = 4;
+
+template <class Rows, int LGS, int BS>
+__global__ __launch_bounds__(BS) void k_sym_hash_wave(Rows rows, Bins bins, int bin, int64_t* cnt_out) {
+  using Src = typename Rows::Src;
+  using Item = typename Src::Item;
+  constexpr int S = 1 << LGS, NW = BS / kWave;
+  __shared__ int32_t s_keys[NW][S];
+  __shared__ int64_t s_start[NW][kWave], s_off[NW][kWave];
+  __shared__ Item s_item[NW][kWave];
+  const int wv = wave_id(), l = lane_id();
+  int32_t* keys = s_keys[wv];
+  const int64_t* off = s_off[wv];
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  for (int r = blockIdx.x * NW + wv; r < n; r += gridDim.x * NW) {
+    const int64_t i = L[r];
+    for (int x = l; x < S; x += kWave) keys[x] = kEmptyKey;
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    int32_t fresh = 0;
+    for (int64_t j0 = 0; j0 < nsrc; j0 += kWave) {
+      Item it{};
+      int64_t st = 0, len = 0;
+      if (j0 + l < nsrc) s.load(j0 + l, it, st, len);
+      const int64_t inc = wave_incl_scan(len);
+      const int64_t tot = lane_value(inc, kWave - 1);
+      s_off[wv][l] = inc - len;
+      s_start[wv][l] = st;
+      s_item[wv][l] = it;
+      wave_lds_sync();
+      for (int64_t q0 = 0; q0 < tot; q0 += (int64_t)kWave * kWaveU) {
+        int32_t c[kWaveU];
+#pragma unroll
+        for (int u = 0; u < kWaveU; ++u) {
+          const int64_t q = q0 + u * kWave + l;
+          c[u] = kEmptyKey;
+          if (q < tot) {
+            // the owner: the last source whose offset is at most q (sources
+            // past the row's end have offset tot > q)
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+              if (off[lo + step] <= q) lo += step;
+            c[u] = s.col(s_item[wv][lo], s_start[wv][lo] + (q - off[lo]));
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kWaveU; ++u)
+          if (c[u] != kEmptyKey) {
+            bool fr;
+            hash_insert(keys, LGS, c[u], &fr);
+            fresh += fr ? 1 : 0;
+          }
+      }
+      wave_lds_sync();
+    }
+    const int32_t cnt = wave_sum(fresh);
+    if (l == 0) cnt_out[i] = cnt;
+    wave_lds_sync();
+  }
+}
+
+// Numeric rows of at most CAP entries over at most 32*WORDS columns, one
+// wavefront per row, no workgroup barrier: pass 1 sets the row's columns in
+// the wavefront's LDS bitmap, each lane turns the popcounts of its
+// consecutive bitmap words into their ranks (one wavefront scan), pass 2
+// folds every product into vals[rank(column)] -- the products are gathered
+// again -- and the write-out walks the bitmap (column ids in order, the
+// words cleared for the next row) and copies the values in rank order: no
+// hashing and no sort.
+template <class Sr, class Rows, int WORDS, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
+  using Src = typename Rows::Src;
+  using Item = typename Src::Item;
+  using Acc = typename Sr::Acc;
+  using V = typename Sr::V;
+  constexpr int NW = BS / kWave;
+  constexpr int kLaneWords = WORDS / kWave;
+  static_assert(WORDS % kWave == 0 && CAP <= 65535, "whole words per lane, 16-bit ranks");
+  __shared__ uint32_t s_bits[NW][WORDS];
+  __shared__ uint16_t s_rank[NW][WORDS];
+  __shared__ Acc s_val[NW][CAP];
+  __shared__ int64_t s_start[NW][kWave], s_off[NW][kWave];
+  __shared__ Item s_item[NW][kWave];
+  const int wv = wave_id(), l = lane_id();
+  uint32_t* bits = s_bits[wv];
+  uint16_t* rank = s_rank[wv];
+  Acc* vals = s_val[wv];
+  const int64_t* off = s_off[wv];
+  for (int x = l; x < WORDS; x += kWave) bits[x] = 0u;
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  for (int r = blockIdx.x * NW + wv; r < n; r += gridDim.x * NW) {
+    const int64_t i = L[r];
+    const int64_t o = uniform64(C.rowptr[i]);
+    const int32_t m = (int32_t)(C.rowptr[i + 1] - o);
+    for (int x = l; x < m && x < CAP; x += kWave) vals[x] = Sr::ident();
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    // the row's products, 64 sources at a time; f(col, value-index, item)
+    auto products = [&](auto&& f) {
+      for (int64_t j0 = 0; j0 < nsrc; j0 += kWave) {
+        Item it{};
+        int64_t st = 0, len = 0;
+        if (j0 + l < nsrc) s.load(j0 + l, it, st, len);
+        const int64_t inc = wave_incl_scan(len);
+        const int64_t tot = lane_value(inc, kWave - 1);
+        s_off[wv][l] = inc - len;
+        s_start[wv][l] = st;
+        s_item[wv][l] = it;
+        wave_lds_sync();
+        for (int64_t q0 = 0; q0 < tot; q0 += (int64_t)kWave * kWaveU) {
+          int32_t c[kWaveU];
+          int64_t idx[kWaveU];
+          int own[kWaveU];
+#pragma unroll
+          for (int u = 0; u < kWaveU; ++u) {
+            const int64_t q = q0 + u * kWave + l;
+            c[u] = -1;
+            idx[u] = 0;
+            own[u] = 0;
+            if (q < tot) {
+              int lo = 0;
+#pragma unroll
+              for (int step = kWave / 2; step > 0; step >>= 1)
+                if (off[lo + step] <= q) lo += step;
+              own[u] = lo;
+              idx[u] = s_start[wv][lo] + (q - off[lo]);
+              c[u] = s.col(s_item[wv][lo], idx[u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kWaveU; ++u)
+            if (c[u] >= 0) f(c[u] & (32 * WORDS - 1), idx[u], s_item[wv][own[u]]);
+        }
+        wave_lds_sync();
+      }
+    };
+    // pass 1: the column set
+    products([&](int32_t c, int64_t, const Item&) { atomicOr(&bits[c >> 5], 1u << (c & 31)); });
+    wave_lds_sync();
+    // ranks: lane l owns words [l*kLaneWords, (l+1)*kLaneWords)
+    const int w0 = l * kLaneWords;
+    int32_t lt = 0;
+    for (int k = 0; k < kLaneWords; ++k) lt += __popc(bits[w0 + k]);
+    const int32_t linc = wave_incl_scan(lt);
+    const int32_t total = lane_value(linc, kWave - 1);
+    int32_t rk = linc - lt;
+    for (int k = 0; k < kLaneWords; ++k) {
+      rank[w0 + k] = (uint16_t)rk;
+      rk += __popc(bits[w0 + k]);
+    }
+    if (l == 0 && total != m) atomicOr(err, 1);
+    wave_lds_sync();
+    // pass 2: fold every product into its compacted slot
+    products([&](int32_t c, int64_t idx, const Item& it) {
+      const int w = c >> 5;
+      const int32_t rr = (int32_t)rank[w] + __popc(bits[w] & ((1u << (c & 31)) - 1u));
+      if (rr < m && rr < CAP) Sr::lds_acc(&vals[rr], s.template value<Sr>(it, idx));
+    });
+    wave_lds_sync();
+    // write-out: column ids by walking the lane's words, values in rank order
+    uint32_t rr = (uint32_t)(linc - lt);
+    for (int k = 0; k < kLaneWords; ++k) {
+      uint32_t b = bits[w0 + k];
+      const int32_t cb = (w0 + k) * 32;
+      while (b) {
+        const int bt = __ffs((int)b) - 1;
+        b &= b - 1u;
+        if (rr < (uint32_t)m) C.col[o + rr] = cb + bt;
+        ++rr;
+      }
+      bits[w0 + k] = 0u;
+    }
+    for (int x = l; x < m && x < CAP; x += kWave) ((V*)C.val)[o + x] = Sr::out(vals[x]);
+    wave_lds_sync();
+  }
+}
+
 // LDS of one hash task: a table of 2^LGS keys and accumulators, the sort
 // buffer, the flattened iterator's per-source arrays and radix-sort counters.
 template <class Sr, class Src, int LGS, int BS>

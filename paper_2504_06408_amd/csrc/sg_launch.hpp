@@ -254,12 +254,34 @@ struct KLib {
     static const KRef k = kref_static((const void*)k_num_ranges<Sr, Rows, LGS, BS>, BS);
     return k;
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef wave_bitmap() const {
+    static const KRef k = kref_static((const void*)k_num_wave_bitmap<Sr, Rows, WORDS, CAP, BS>, BS);
+    return k;
+  }
 };
+
+// Hash rows of at most 2^(LGS-1) entries whose columns all lie below
+// 32 * kWaveWords (products whose B has at most four column tiles) run one
+// wavefront per row over a column bitmap instead of a workgroup per row.
+constexpr int kWaveWords = 2048;
+constexpr int kWaveBS = 128;
+constexpr int kWaveLgMax = 11;
 
 template <class Sr, class Rows, int LGS, int BS, class Kp>
 inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st, const Kp& kp) {
   const int n = c.plan.count[bin];
   if (n == 0) return;
+  if constexpr (LGS <= kWaveLgMax) {
+    if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kWaveWords) {
+      const KRef kw = kp.template wave_bitmap<Sr, Rows, kWaveWords, (1 << (LGS - 1)), kWaveBS>();
+      if (kw.ok()) {
+        klaunch(kw, dim3(grid_for(n, kWaveBS / kWave, c.cus * kw.occ * 4)), dim3(kWaveBS), st, rows, c.plan.bins,
+                (int)bin, c.C, c.err);
+        return;
+      }
+    }
+  }
   const KRef k = kp.template hash<Sr, Rows, LGS, BS>();
   klaunch(k, dim3(grid_for(n, 1, c.cus * k.occ * 4)), dim3(BS), st, rows, c.plan.bins, (int)bin, c.C, c.err);
 }

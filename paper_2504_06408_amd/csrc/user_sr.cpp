@@ -312,6 +312,11 @@ struct KUser {
   KRef ranges() const {
     return get(n_ranges(rows<Rows>(), LGS, BS));
   }
+  // (run-time semirings take the workgroup hash kernels for every hash row)
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef wave_bitmap() const {
+    return KRef{};
+  }
 };
 
 }  // namespace
