@@ -120,10 +120,20 @@ void analyze_rows(const Rows& rows, const RowSource& r, const Policy& pol, const
   hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, list);
 }
 
+constexpr int kSymRowWords = 2048;
+
 template <class Rows, int LGS, int BS>
 void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
   const int n = plan.count[bin];
   if (n == 0) return;
+  if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
+    // columns below 65536: a workgroup per row over a bitmap of the columns
+    constexpr int kBS = 256;
+    auto kb = k_sym_bitmap_row<Rows, kSymRowWords, kBS>;
+    static int occb = occupancy(kb, kBS);
+    hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
+    return;
+  }
   auto k = k_sym_hash<Rows, LGS, BS>;
   static int occ = occupancy(k, BS);
   hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, rows, plan.bins, bin, cnt_out);

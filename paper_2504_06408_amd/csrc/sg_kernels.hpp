@@ -777,14 +777,17 @@ __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, in
     // pass 1: the column set
     products([&](int32_t c, int64_t, const Item&) { atomicOr(&bits[c >> 5], 1u << (c & 31)); });
     wave_lds_sync();
-    // ranks: lane l owns words [l*kLaneWords, (l+1)*kLaneWords)
-    const int w0 = l * kLaneWords;
+    // ranks: lane l owns words [l*lw, (l+1)*lw), lw covering the product's
+    // own columns
+    const int64_t ncw = (s.ncols + 31) >> 5;
+    const int lw = ncw >= WORDS ? kLaneWords : (int)((ncw + kWave - 1) / kWave);
+    const int w0 = l * lw;
     int32_t lt = 0;
-    for (int k = 0; k < kLaneWords; ++k) lt += __popc(bits[w0 + k]);
+    for (int k = 0; k < lw; ++k) lt += __popc(bits[w0 + k]);
     const int32_t linc = wave_incl_scan(lt);
     const int32_t total = lane_value(linc, kWave - 1);
     int32_t rk = linc - lt;
-    for (int k = 0; k < kLaneWords; ++k) {
+    for (int k = 0; k < lw; ++k) {
       rank[w0 + k] = (uint16_t)rk;
       rk += __popc(bits[w0 + k]);
     }
@@ -799,7 +802,7 @@ __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, in
     wave_lds_sync();
     // write-out: column ids by walking the lane's words, values in rank order
     uint32_t rr = (uint32_t)(linc - lt);
-    for (int k = 0; k < kLaneWords; ++k) {
+    for (int k = 0; k < lw; ++k) {
       uint32_t b = bits[w0 + k];
       const int32_t cb = (w0 + k) * 32;
       while (b) {
@@ -812,6 +815,124 @@ __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, in
     }
     for (int x = l; x < m && x < CAP; x += kWave) ((V*)C.val)[o + x] = Sr::out(vals[x]);
     wave_lds_sync();
+  }
+}
+
+// Numeric rows of at most CAP entries over at most 32*WORDS columns, one
+// workgroup per row: the same bitmap-and-rank scheme as k_num_wave_bitmap
+// with the bitmap shared by the workgroup, so its LDS (bitmap, word ranks,
+// CAP accumulators and the product iterator's arrays) leaves room for
+// several rows per CU where a hash table with its sort buffer leaves one.
+// Thread t owns bitmap words [t*WORDS/BS, (t+1)*WORDS/BS): their popcounts,
+// one block scan, their ranks, and in the write-out their column ids.
+template <class Sr, class Rows, int WORDS, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
+  using Src = typename Rows::Src;
+  using Item = typename Src::Item;
+  using Acc = typename Sr::Acc;
+  using V = typename Sr::V;
+  constexpr int NW = BS / kWave;
+  constexpr int kThreadWords = WORDS / BS;
+  static_assert(WORDS % BS == 0 && CAP <= 65535, "whole words per thread, 16-bit ranks");
+  __shared__ uint32_t s_bits[WORDS];
+  __shared__ uint16_t s_rank[WORDS];
+  __shared__ Acc s_val[CAP];
+  __shared__ Item s_item[BS];
+  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  for (int x = threadIdx.x; x < WORDS; x += BS) s_bits[x] = 0u;
+  block_sync();
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  const int w0 = (int)threadIdx.x * kThreadWords;
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = L[r];
+    const int64_t o = C.rowptr[i];
+    const int32_t m = (int32_t)(C.rowptr[i + 1] - o);
+    for (int x = threadIdx.x; x < m && x < CAP; x += BS) s_val[x] = Sr::ident();
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    // pass 1: the column set (columns masked to the bitmap)
+    auto f1 = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
+    auto a1 = [&](int32_t c) { atomicOr(&s_bits[c >> 5], 1u << (c & 31)); };
+    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, f1, a1);
+    int32_t lt = 0;
+#pragma unroll
+    for (int k = 0; k < kThreadWords; ++k) lt += __popc(s_bits[w0 + k]);
+    int32_t total;
+    const int32_t ex = block_excl_scan<NW, int32_t>(lt, (int32_t*)s_wave, &total);
+    int32_t rk = ex;
+#pragma unroll
+    for (int k = 0; k < kThreadWords; ++k) {
+      s_rank[w0 + k] = (uint16_t)rk;
+      rk += __popc(s_bits[w0 + k]);
+    }
+    if (threadIdx.x == 0 && total != m) atomicOr(err, 1);
+    block_sync();
+    // pass 2: fold every product into its compacted slot
+    auto f2 = [&](const Item& it, int64_t idx) {
+      return ColVal<Acc>{s.col(it, idx) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
+    };
+    auto a2 = [&](const ColVal<Acc>& p) {
+      const int w = p.c >> 5;
+      const int32_t rr = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
+      if (rr < m && rr < CAP) Sr::lds_acc(&s_val[rr], p.v);
+    };
+    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, f2, a2);
+    // write-out: column ids from the thread's words, values in rank order
+    uint32_t rr = (uint32_t)ex;
+#pragma unroll
+    for (int k = 0; k < kThreadWords; ++k) {
+      uint32_t b = s_bits[w0 + k];
+      const int32_t cb = (w0 + k) * 32;
+      while (b) {
+        const int bt = __ffs((int)b) - 1;
+        b &= b - 1u;
+        if (rr < (uint32_t)m) C.col[o + rr] = cb + bt;
+        ++rr;
+      }
+      s_bits[w0 + k] = 0u;
+    }
+    for (int x = threadIdx.x; x < m && x < CAP; x += BS) ((V*)C.val)[o + x] = Sr::out(s_val[x]);
+    block_sync();
+  }
+}
+
+// Symbolic count of rows over at most 32*WORDS columns, one workgroup per
+// row: the distinct columns are the set bits of an LDS bitmap.
+template <class Rows, int WORDS, int BS>
+__global__ __launch_bounds__(BS) void k_sym_bitmap_row(Rows rows, Bins bins, int bin, int64_t* cnt_out) {
+  using Src = typename Rows::Src;
+  using Item = typename Src::Item;
+  constexpr int NW = BS / kWave;
+  constexpr int kThreadWords = WORDS / BS;
+  static_assert(WORDS % BS == 0, "whole words per thread");
+  __shared__ uint32_t s_bits[WORDS];
+  __shared__ Item s_item[BS];
+  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  for (int x = threadIdx.x; x < WORDS; x += BS) s_bits[x] = 0u;
+  block_sync();
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  const int w0 = (int)threadIdx.x * kThreadWords;
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = L[r];
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    auto f = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
+    auto a = [&](int32_t c) { atomicOr(&s_bits[c >> 5], 1u << (c & 31)); };
+    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, f, a);
+    int64_t lt = 0;
+#pragma unroll
+    for (int k = 0; k < kThreadWords; ++k) {
+      lt += __popc(s_bits[w0 + k]);
+      s_bits[w0 + k] = 0u;
+    }
+    const int64_t tot = block_sum<NW, int64_t>(lt, s_wave);
+    if (threadIdx.x == 0) cnt_out[i] = tot;
   }
 }
 

@@ -259,20 +259,38 @@ struct KLib {
     static const KRef k = kref_static((const void*)k_num_wave_bitmap<Sr, Rows, WORDS, CAP, BS>, BS);
     return k;
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef bitmap_row() const {
+    static const KRef k = kref_static((const void*)k_num_bitmap_row<Sr, Rows, WORDS, CAP, BS>, BS);
+    return k;
+  }
 };
 
-// Hash rows of at most 2^(LGS-1) entries whose columns all lie below
-// 32 * kWaveWords (products whose B has at most four column tiles) run one
-// wavefront per row over a column bitmap instead of a workgroup per row.
+// Hash rows whose columns all lie below 32 * kWaveWords (products whose B has
+// at most four column tiles) need no hash table: a bitmap of the columns and
+// per-word ranks place every entry.  Rows of up to 2^kWaveLgMax / 2 entries
+// run one wavefront per row, larger ones one workgroup per row over a shared
+// bitmap (the hash bins of 2^kRowBitmapLgMin slots and up).
 constexpr int kWaveWords = 2048;
 constexpr int kWaveBS = 128;
-constexpr int kWaveLgMax = 11;
+constexpr int kWaveLgMax = 9;
+constexpr int kRowBitmapBS = 256;
+constexpr int kRowBitmapLgMin = 10;
 
 template <class Sr, class Rows, int LGS, int BS, class Kp>
 inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st, const Kp& kp) {
   const int n = c.plan.count[bin];
   if (n == 0) return;
-  if constexpr (LGS <= kWaveLgMax) {
+  if constexpr (LGS >= kRowBitmapLgMin) {
+    if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kWaveWords) {
+      const KRef kb = kp.template bitmap_row<Sr, Rows, kWaveWords, (1 << (LGS - 1)), kRowBitmapBS>();
+      if (kb.ok()) {
+        klaunch(kb, dim3(grid_for(n, 1, c.cus * kb.occ * 4)), dim3(kRowBitmapBS), st, rows, c.plan.bins, (int)bin,
+                c.C, c.err);
+        return;
+      }
+    }
+  } else if constexpr (LGS <= kWaveLgMax) {
     if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kWaveWords) {
       const KRef kw = kp.template wave_bitmap<Sr, Rows, kWaveWords, (1 << (LGS - 1)), kWaveBS>();
       if (kw.ok()) {

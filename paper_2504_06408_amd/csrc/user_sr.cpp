@@ -317,6 +317,10 @@ struct KUser {
   KRef wave_bitmap() const {
     return KRef{};
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef bitmap_row() const {
+    return KRef{};
+  }
 };
 
 }  // namespace
