@@ -8,39 +8,47 @@ namespace sg {
 namespace {
 constexpr int kAnaBS = 256;
 
-// Per-bin totals, bin starts and per-(block, bin) scatter offsets.  One block
-// of 1024 threads: 16 lanes per bin split the blocks into 16 runs.
-__global__ __launch_bounds__(1024) void k_bin_offsets(const int32_t* hist, int32_t nblk, int32_t* blk_off,
-                                                      int32_t* bin_start, int32_t* bin_count) {
-  __shared__ int32_t s_cnt[kNB], s_start[kNB];
-  const int b = threadIdx.x >> 4, g = threadIdx.x & 15;
-  const int per = (nblk + 15) / 16;
-  const int lo = g * per;
-  const int hi = (lo + per) < nblk ? (lo + per) : nblk;
-  int32_t sum = 0;
-  for (int k = lo; k < hi; ++k) sum += hist[(int64_t)k * kNB + b];
-  int32_t incl = sum;
+// Per-(bin, block) scatter offsets within each bin and the per-bin totals.
+// The histogram is bin-major (hist[b*nblk + k]: rows of block k in bin b),
+// so workgroup b scans one contiguous row of it.
+constexpr int kBinScanBS = 1024, kBinScanPer = 4;
+__global__ __launch_bounds__(kBinScanBS) void k_bin_offsets(const int32_t* hist, int32_t nblk, int32_t* blk_off,
+                                                            int32_t* bin_count) {
+  __shared__ int32_t s_wave[kBinScanBS / kWave];
+  const int64_t row = (int64_t)blockIdx.x * nblk;
+  int32_t carry = 0;
+  for (int32_t k0 = 0; k0 < nblk; k0 += kBinScanBS * kBinScanPer) {
+    const int32_t base = k0 + (int32_t)threadIdx.x * kBinScanPer;
+    int32_t v[kBinScanPer];
+    int32_t sum = 0;
 #pragma unroll
-  for (int d = 1; d < 16; d <<= 1) {
-    const int32_t u = __shfl_up(incl, (unsigned)d, 16);
-    if (g >= d) incl += u;
+    for (int q = 0; q < kBinScanPer; ++q) {
+      v[q] = base + q < nblk ? hist[row + base + q] : 0;
+      sum += v[q];
+    }
+    int32_t tot;
+    int32_t run = carry + block_excl_scan<kBinScanBS / kWave, int32_t>(sum, s_wave, &tot);
+#pragma unroll
+    for (int q = 0; q < kBinScanPer; ++q) {
+      if (base + q < nblk) blk_off[row + base + q] = run;
+      run += v[q];
+    }
+    carry += tot;
   }
-  const int32_t excl = incl - sum;
-  if (g == 15) s_cnt[b] = incl;
-  __syncthreads();
-  if (threadIdx.x < kNB) {
-    const int32_t v = s_cnt[threadIdx.x];
-    const int32_t inc = wave_incl_scan(v);
-    s_start[threadIdx.x] = inc - v;
-    bin_start[threadIdx.x] = inc - v;
-    bin_count[threadIdx.x] = v;
-  }
-  __syncthreads();
-  int32_t run = s_start[b] + excl;
-  for (int k = lo; k < hi; ++k) {
-    blk_off[(int64_t)k * kNB + b] = run;
-    run += hist[(int64_t)k * kNB + b];
-  }
+  if (threadIdx.x == 0) bin_count[blockIdx.x] = carry;
+}
+
+// Bin starts: one wavefront scans the kNB (= 64) bin totals.
+__global__ __launch_bounds__(kWave) void k_bin_starts(const int32_t* bin_count, int32_t* bin_start) {
+  static_assert(kNB == kWave, "one lane per bin");
+  const int32_t v = bin_count[threadIdx.x];
+  bin_start[threadIdx.x] = wave_incl_scan(v) - v;
+}
+
+void bin_offsets(const int32_t* hist, int64_t nblk, int32_t* blk_off, int32_t* bin_start, int32_t* bin_count,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_offsets, dim3(kNB), dim3(kBinScanBS), 0, st, hist, (int32_t)nblk, blk_off, bin_count);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(kWave), 0, st, (const int32_t*)bin_count, bin_start);
 }
 
 // Per B row, rp2[k*(T+1) + t] = number of entries of row k with column below
@@ -116,8 +124,8 @@ void analyze_rows(const Rows& rows, const RowSource& r, const Policy& pol, const
   const int64_t nblk = analyze_blocks(r.nrows);
   hipLaunchKernelGGL((k_analyze<Rows, kAnaBS>), dim3(nblk), dim3(kAnaBS), 0, st, rows, r.nrows, pol, c_rowptr, p,
                      nt, bin, hist, cnt_out);
-  hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, hist, (int32_t)nblk, blk_off, bin_start, bin_count);
-  hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, list);
+  bin_offsets(hist, nblk, blk_off, bin_start, bin_count, st);
+  hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, bin_start, list);
 }
 
 constexpr int kSymRowWords = 2048;
@@ -247,8 +255,9 @@ void launch_rebin(const int64_t* p, const int32_t* nt, const int64_t* c_rowptr, 
                   int32_t* list, hipStream_t st) {
   const int64_t nblk = analyze_blocks(nrows);
   hipLaunchKernelGGL(k_rebin<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, p, nt, c_rowptr, nrows, pol, bin, hist);
-  hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1024), 0, st, hist, (int32_t)nblk, blk_off, bin_start, bin_count);
-  hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, nrows, blk_off, list);
+  bin_offsets(hist, nblk, blk_off, bin_start, bin_count, st);
+  hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, nrows, blk_off,
+                     (const int32_t*)bin_start, list);
 }
 
 void launch_tile_bounds(const int64_t* rowptr, const int32_t* col, int64_t nrows, int32_t T, int32_t* rp2, int cus,

@@ -347,6 +347,8 @@ struct OutC {
 };
 
 // ---- analysis and binning ---------------------------------------------------------
+// Each block of the analysis counts its rows per bin into a bin-major
+// histogram, hist[b * gridDim.x + blockIdx.x].
 
 template <class Rows, int BS>
 __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy pol, const int64_t* c_rowptr,
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(BS) void k_analyze(Rows rows, int64_t nrows, Policy
     if (!pol.numeric && b == kBinEmpty) cnt_out[i] = 0;
   }
   block_sync();
-  for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
+  for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)b * gridDim.x + blockIdx.x] = s_hist[b];
 }
 
 // Numeric-pass binning from the product counts the symbolic pass already
@@ -439,13 +441,13 @@ __global__ __launch_bounds__(BS) void k_rebin(const int64_t* p_in, const int32_t
     atomicAdd(&s_hist[b], 1);
   }
   block_sync();
-  for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)blockIdx.x * kNB + b] = s_hist[b];
+  for (int b = threadIdx.x; b < kNB; b += BS) hist[(int64_t)b * gridDim.x + blockIdx.x] = s_hist[b];
 }
 
 // Stable scatter of row ids into their bins (ascending row order per bin).
 template <int BS>
 __global__ __launch_bounds__(BS) void k_bin_scatter(const uint8_t* bin_in, int64_t nrows, const int32_t* blk_off,
-                                                      int32_t* list) {
+                                                      const int32_t* bin_start, int32_t* list) {
   constexpr int NW = BS / kWave;
   __shared__ int32_t s_cnt[NW][kNB];
   for (int x = threadIdx.x; x < NW * kNB; x += BS) (&s_cnt[0][0])[x] = 0;
@@ -467,7 +469,7 @@ __global__ __launch_bounds__(BS) void k_bin_scatter(const uint8_t* bin_in, int64
   if (valid) {
     int32_t pre = 0;
     for (int w = 0; w < wave_id(); ++w) pre += s_cnt[w][b];
-    list[blk_off[(int64_t)blockIdx.x * kNB + b] + pre + rank] = (int32_t)i;
+    list[bin_start[b] + blk_off[(int64_t)b * gridDim.x + blockIdx.x] + pre + rank] = (int32_t)i;
   }
 }
 
