@@ -268,9 +268,19 @@ struct SlabTask {
 };
 
 // Entries of a light task's LDS value array (32 KB of accumulators).
+// Light tasks with accumulators of 4 bytes or more also keep each entry's
+// column (its low 16 bits) at its rank, so the write-out is two coalesced
+// copies instead of a walk over the bitmap; the value and column arrays
+// share 42 KB of LDS.
+template <class Sr>
+constexpr bool light_cols_lds() {
+  return sizeof(typename Sr::Acc) >= 4;
+}
+constexpr int light_cap_of(int acc_bytes) { return (43008 / (acc_bytes + 2)) & ~63; }
+
 template <class Sr>
 constexpr int slab_cap() {
-  return 32768 / (int)sizeof(typename Sr::Acc);
+  return light_cols_lds<Sr>() ? light_cap_of((int)sizeof(typename Sr::Acc)) : 32768 / (int)sizeof(typename Sr::Acc);
 }
 
 constexpr int kTaskSlabsLds = 512;  // slabs whose bucket counters a block keeps in LDS
@@ -722,6 +732,8 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
   __shared__ uint32_t s_bits[kSlabWordsMax];
   __shared__ uint16_t s_rank[kSlabWordsMax];
   __shared__ Acc s_val[CAP];
+  constexpr bool kCols = light_cols_lds<Sr>();
+  __shared__ uint16_t s_col[kCols ? CAP : 1];
   __shared__ SrcLds<V, BS> L;
   __shared__ int32_t s_wt[NW];
   const int T = b.T, G = b.G;
@@ -758,7 +770,10 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     auto a2 = [&](const ColVal<Acc>& p) {
       const int w = (p.c >> 5) & (kSlabWordsMax - 1);
       const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
-      if (r < m) Sr::lds_acc(&s_val[r], p.v);
+      if (r < m) {
+        Sr::lds_acc(&s_val[r], p.v);
+        if constexpr (kCols) s_col[r] = (uint16_t)p.c;
+      }
     };
     ColVal<Acc> pp[kSlabU];
     bool ok[kSlabU];
@@ -825,6 +840,18 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     const int64_t o0 = uniform64(tk.out);
     char* colb = reinterpret_cast<char*>(C.col + o0);
     char* valb = reinterpret_cast<char*>((V*)C.val + o0);
+    if constexpr (kCols) {
+      // window columns are below 2^17; bit 16 is set exactly for the ranks
+      // from that of word 2048 on
+      const uint32_t split = nwords > 2048 ? (uint32_t)s_rank[2048] : (uint32_t)m;
+      for (uint32_t x = threadIdx.x; x < (uint32_t)m; x += BS) {
+        const int32_t c = (int32_t)s_col[x] | (x >= split ? 65536 : 0);
+        *reinterpret_cast<int32_t*>(colb + x * (uint32_t)sizeof(int32_t)) = (int32_t)cw0 + c;
+        *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(s_val[x]);
+      }
+      for (int it = 0; it < wpw; it += kWave) s_bits[wv * wpw + it + lane_id()] = 0u;
+      return;
+    }
     for (int it = 0; it < wpw; it += kWave) {
       const int w = wv * wpw + it + lane_id();
       uint32_t bits = s_bits[w];

@@ -59,7 +59,7 @@ bool find_int(const std::string& s, const char* key, long long* out) {
 int32_t full_light_cap(const sg_semiring* sr) {
   int acc = sr->value_bytes;
   if (sr->id == SG_PLUS_TIMES_F32 && sr->acc_flags != SG_ACC_PLAIN) acc = 8;
-  return 32768 / acc;
+  return acc >= 4 ? sg::light_cap_of(acc) : 32768 / acc;
 }
 
 struct Knobs {
