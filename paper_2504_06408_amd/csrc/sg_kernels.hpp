@@ -702,9 +702,9 @@ __global__ __launch_bounds__(BS) void k_sym_hash_wave(Rows rows, Bins bins, int 
 // wavefront per row, no workgroup barrier: pass 1 sets the row's columns in
 // the wavefront's LDS bitmap, each lane turns the popcounts of its
 // consecutive bitmap words into their ranks (one wavefront scan), pass 2
-// folds every product into vals[rank(column)] -- the products are gathered
-// again -- and the write-out walks the bitmap (column ids in order, the
-// words cleared for the next row) and copies the values in rank order: no
+// folds every product into vals[rank(column)] and stores its column (16 bits:
+// the columns lie below 65536) at the same rank -- the products are gathered
+// again -- and the write-out copies columns and values in rank order: no
 // hashing and no sort.
 template <class Sr, class Rows, int WORDS, int CAP, int BS>
 __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
@@ -718,12 +718,15 @@ __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, in
   __shared__ uint32_t s_bits[NW][WORDS];
   __shared__ uint16_t s_rank[NW][WORDS];
   __shared__ Acc s_val[NW][CAP];
+  __shared__ uint16_t s_col[NW][CAP];
   __shared__ int64_t s_start[NW][kWave], s_off[NW][kWave];
   __shared__ Item s_item[NW][kWave];
+  static_assert(32 * WORDS <= 65536, "16-bit columns");
   const int wv = wave_id(), l = lane_id();
   uint32_t* bits = s_bits[wv];
   uint16_t* rank = s_rank[wv];
   Acc* vals = s_val[wv];
+  uint16_t* cols = s_col[wv];
   const int64_t* off = s_off[wv];
   for (int x = l; x < WORDS; x += kWave) bits[x] = 0u;
   const int n = bins.count[bin];
@@ -799,23 +802,18 @@ __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, in
     products([&](int32_t c, int64_t idx, const Item& it) {
       const int w = c >> 5;
       const int32_t rr = (int32_t)rank[w] + __popc(bits[w] & ((1u << (c & 31)) - 1u));
-      if (rr < m && rr < CAP) Sr::lds_acc(&vals[rr], s.template value<Sr>(it, idx));
+      if (rr < m && rr < CAP) {
+        Sr::lds_acc(&vals[rr], s.template value<Sr>(it, idx));
+        cols[rr] = (uint16_t)c;
+      }
     });
     wave_lds_sync();
-    // write-out: column ids by walking the lane's words, values in rank order
-    uint32_t rr = (uint32_t)(linc - lt);
-    for (int k = 0; k < lw; ++k) {
-      uint32_t b = bits[w0 + k];
-      const int32_t cb = (w0 + k) * 32;
-      while (b) {
-        const int bt = __ffs((int)b) - 1;
-        b &= b - 1u;
-        if (rr < (uint32_t)m) C.col[o + rr] = cb + bt;
-        ++rr;
-      }
-      bits[w0 + k] = 0u;
+    // write-out in rank order; the row's words are cleared for the next row
+    for (int x = l; x < m && x < CAP; x += kWave) {
+      C.col[o + x] = (int32_t)cols[x];
+      ((V*)C.val)[o + x] = Sr::out(vals[x]);
     }
-    for (int x = l; x < m && x < CAP; x += kWave) ((V*)C.val)[o + x] = Sr::out(vals[x]);
+    for (int k = 0; k < lw; ++k) bits[w0 + k] = 0u;
     wave_lds_sync();
   }
 }
@@ -823,81 +821,92 @@ __global__ __launch_bounds__(BS) void k_num_wave_bitmap(Rows rows, Bins bins, in
 // Numeric rows of at most CAP entries over at most 32*WORDS columns, one
 // workgroup per row: the same bitmap-and-rank scheme as k_num_wave_bitmap
 // with the bitmap shared by the workgroup, so its LDS (bitmap, word ranks,
-// CAP accumulators and the product iterator's arrays) leaves room for
-// several rows per CU where a hash table with its sort buffer leaves one.
-// Thread t owns bitmap words [t*WORDS/BS, (t+1)*WORDS/BS): their popcounts,
-// one block scan, their ranks, and in the write-out their column ids.
-template <class Sr, class Rows, int WORDS, int CAP, int BS>
-__global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
-  using Src = typename Rows::Src;
+// CAP accumulators and columns, and the product iterator's arrays) leaves
+// room for several rows per CU where a hash table with its sort buffer
+// leaves one.  Thread t owns bitmap words [t*WORDS/BS, (t+1)*WORDS/BS):
+// their popcounts and, after one block scan, their ranks.  Pass 2 also
+// stores each entry's column (16 bits) at its rank, so the write-out copies
+// both arrays.
+template <class Sr, class Src, int WORDS, int CAP, int BS>
+struct BitmapRowSmem {
+  uint32_t bits[WORDS];
+  uint16_t rank[WORDS];
+  typename Sr::Acc val[CAP];
+  uint16_t col[CAP];
+  typename Src::Item item[BS];
+  int64_t start[BS], off[BS], wave[BS / kWave];
+};
+
+// One row (source s bound to local row li, m entries written from o); the
+// bitmap is clear on entry and on exit.
+template <class Sr, class Src, int WORDS, int CAP, int BS>
+SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, int64_t li, int64_t o, int32_t m,
+                            OutC C, int32_t* err) {
   using Item = typename Src::Item;
   using Acc = typename Sr::Acc;
   using V = typename Sr::V;
   constexpr int NW = BS / kWave;
   constexpr int kThreadWords = WORDS / BS;
   static_assert(WORDS % BS == 0 && CAP <= 65535, "whole words per thread, 16-bit ranks");
-  __shared__ uint32_t s_bits[WORDS];
-  __shared__ uint16_t s_rank[WORDS];
-  __shared__ Acc s_val[CAP];
-  __shared__ Item s_item[BS];
-  __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
-  for (int x = threadIdx.x; x < WORDS; x += BS) s_bits[x] = 0u;
+  static_assert(32 * WORDS <= 65536, "16-bit columns");
+  const int w0 = (int)threadIdx.x * kThreadWords;
+  for (int x = threadIdx.x; x < m && x < CAP; x += BS) sm.val[x] = Sr::ident();
+  const int64_t nsrc = s.bind(li, 0, s.T);
+  // pass 1: the column set (columns masked to the bitmap)
+  auto f1 = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
+  auto a1 = [&](int32_t c) { atomicOr(&sm.bits[c >> 5], 1u << (c & 31)); };
+  for_each_product<BS, kUnroll>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f1, a1);
+  int32_t lt = 0;
+#pragma unroll
+  for (int k = 0; k < kThreadWords; ++k) lt += __popc(sm.bits[w0 + k]);
+  int32_t total;
+  int32_t rk = block_excl_scan<NW, int32_t>(lt, (int32_t*)sm.wave, &total);
+#pragma unroll
+  for (int k = 0; k < kThreadWords; ++k) {
+    sm.rank[w0 + k] = (uint16_t)rk;
+    rk += __popc(sm.bits[w0 + k]);
+  }
+  if (threadIdx.x == 0 && total != m) atomicOr(err, 1);
+  block_sync();
+  // pass 2: fold every product into its compacted slot
+  auto f2 = [&](const Item& it, int64_t idx) {
+    return ColVal<Acc>{s.col(it, idx) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
+  };
+  auto a2 = [&](const ColVal<Acc>& p) {
+    const int w = p.c >> 5;
+    const int32_t rr = (int32_t)sm.rank[w] + __popc(sm.bits[w] & ((1u << (p.c & 31)) - 1u));
+    if (rr < m && rr < CAP) {
+      Sr::lds_acc(&sm.val[rr], p.v);
+      sm.col[rr] = (uint16_t)p.c;
+    }
+  };
+  for_each_product<BS, kUnroll>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f2, a2);
+  // write-out in rank order; the thread's words are cleared for the next row
+  for (int x = threadIdx.x; x < m && x < CAP; x += BS) {
+    C.col[o + x] = (int32_t)sm.col[x];
+    ((V*)C.val)[o + x] = Sr::out(sm.val[x]);
+  }
+#pragma unroll
+  for (int k = 0; k < kThreadWords; ++k) sm.bits[w0 + k] = 0u;
+  block_sync();
+}
+
+template <class Sr, class Rows, int WORDS, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
+  using Src = typename Rows::Src;
+  __shared__ BitmapRowSmem<Sr, Src, WORDS, CAP, BS> sm;
+  for (int x = threadIdx.x; x < WORDS; x += BS) sm.bits[x] = 0u;
   block_sync();
   const int n = bins.count[bin];
   const int32_t* L = bins.list + bins.start[bin];
-  const int w0 = (int)threadIdx.x * kThreadWords;
   for (int r = blockIdx.x; r < n; r += gridDim.x) {
     const int64_t i = L[r];
     const int64_t o = C.rowptr[i];
     const int32_t m = (int32_t)(C.rowptr[i + 1] - o);
-    for (int x = threadIdx.x; x < m && x < CAP; x += BS) s_val[x] = Sr::ident();
     Src s{};
     int64_t li;
     rows.get(i, s, li);
-    const int64_t nsrc = s.bind(li, 0, s.T);
-    // pass 1: the column set (columns masked to the bitmap)
-    auto f1 = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
-    auto a1 = [&](int32_t c) { atomicOr(&s_bits[c >> 5], 1u << (c & 31)); };
-    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, f1, a1);
-    int32_t lt = 0;
-#pragma unroll
-    for (int k = 0; k < kThreadWords; ++k) lt += __popc(s_bits[w0 + k]);
-    int32_t total;
-    const int32_t ex = block_excl_scan<NW, int32_t>(lt, (int32_t*)s_wave, &total);
-    int32_t rk = ex;
-#pragma unroll
-    for (int k = 0; k < kThreadWords; ++k) {
-      s_rank[w0 + k] = (uint16_t)rk;
-      rk += __popc(s_bits[w0 + k]);
-    }
-    if (threadIdx.x == 0 && total != m) atomicOr(err, 1);
-    block_sync();
-    // pass 2: fold every product into its compacted slot
-    auto f2 = [&](const Item& it, int64_t idx) {
-      return ColVal<Acc>{s.col(it, idx) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
-    };
-    auto a2 = [&](const ColVal<Acc>& p) {
-      const int w = p.c >> 5;
-      const int32_t rr = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
-      if (rr < m && rr < CAP) Sr::lds_acc(&s_val[rr], p.v);
-    };
-    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, f2, a2);
-    // write-out: column ids from the thread's words, values in rank order
-    uint32_t rr = (uint32_t)ex;
-#pragma unroll
-    for (int k = 0; k < kThreadWords; ++k) {
-      uint32_t b = s_bits[w0 + k];
-      const int32_t cb = (w0 + k) * 32;
-      while (b) {
-        const int bt = __ffs((int)b) - 1;
-        b &= b - 1u;
-        if (rr < (uint32_t)m) C.col[o + rr] = cb + bt;
-        ++rr;
-      }
-      s_bits[w0 + k] = 0u;
-    }
-    for (int x = threadIdx.x; x < m && x < CAP; x += BS) ((V*)C.val)[o + x] = Sr::out(s_val[x]);
-    block_sync();
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS>(sm, s, li, o, m, C, err);
   }
 }
 
@@ -1263,6 +1272,36 @@ SG_DEV Task bucket_task(const Task* tasks, const int32_t* off, int32_t Tmax, int
     else hi = mid - 1;
   }
   return tasks[(int64_t)lo * nd + (g - off[lo])];
+}
+
+// Dense rows over at most 32*WORDS columns (blocks of a SUMMA grid, narrow
+// products of a batch) with at most CAP entries: whole rows, one workgroup
+// each, by the bitmap-and-rank fold of the narrow hash rows.  The tasks are
+// the slab list of the dense task builder, run with one slab covering the
+// whole row and CAP as its cap; fuller rows stay on the tile and range
+// tasks.
+template <class Sr, class Rows, int WORDS, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_bitmap_dense(Rows rows, Bins bins, OutC C, const Task* tasks,
+                                                         const int32_t* book, int32_t* ctr, int32_t* err) {
+  using Src = typename Rows::Src;
+  __shared__ BitmapRowSmem<Sr, Src, WORDS, CAP, BS> sm;
+  __shared__ int64_t s_slot;
+  for (int x = threadIdx.x; x < WORDS; x += BS) sm.bits[x] = 0u;
+  block_sync();
+  const int32_t* L = bins.list + bins.start[kBinDense0];
+  const int32_t Tmax = rows.Tmax;
+  const int32_t nd = dense_rows(bins);
+  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &s_slot, [&](int64_t g) {
+    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListSlab), Tmax, nd, (int32_t)g);
+    const int64_t i = L[tk.h];
+    const int64_t o = C.rowptr[i];
+    const int32_t m = (int32_t)(C.rowptr[i + 1] - o);
+    if (threadIdx.x == 0 && m > CAP) atomicOr(err, 1);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS>(sm, s, li, o, m, C, err);
+  });
 }
 
 // Dense-tile tasks: persistent workgroups take tasks from a global counter; a

@@ -264,6 +264,11 @@ struct KLib {
     static const KRef k = kref_static((const void*)k_num_bitmap_row<Sr, Rows, WORDS, CAP, BS>, BS);
     return k;
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef bitmap_dense() const {
+    static const KRef k = kref_static((const void*)k_num_bitmap_dense<Sr, Rows, WORDS, CAP, BS>, BS);
+    return k;
+  }
 };
 
 // Hash rows whose columns all lie below 32 * kWaveWords (products whose B has
@@ -276,6 +281,17 @@ constexpr int kWaveBS = 128;
 constexpr int kWaveLgMax = 9;
 constexpr int kRowBitmapBS = 256;
 constexpr int kRowBitmapLgMin = 10;
+
+// Dense rows over narrow B: whole rows of up to dense_bitmap_cap entries in
+// one 1024-thread workgroup per CU (bitmap, ranks, the accumulators with
+// their 16-bit columns and the iterator's arrays fill the 160 KB of LDS).
+constexpr int kDenseBitmapBS = 1024;
+template <class Sr, class Rows>
+constexpr int dense_bitmap_cap() {
+  constexpr int fixed = kWaveWords * 6 + kDenseBitmapBS * ((int)sizeof(typename Rows::Src::Item) + 16) + 1024;
+  constexpr int cap = ((160 * 1024 - fixed) / ((int)sizeof(typename Sr::Acc) + 2)) & ~255;
+  return cap < 65280 ? cap : 65280;  // ranks are 16-bit
+}
 
 template <class Sr, class Rows, int LGS, int BS, class Kp>
 inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st, const Kp& kp) {
@@ -368,14 +384,28 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st, 
   }
   int32_t* book = task_book(c);
   const int32_t Tmax = rows.Tmax;
+  // over narrow B, whole rows of at most DCAP entries take the bitmap fold:
+  // the task builder puts them on its slab list (one slab spanning the row)
+  constexpr int DCAP = dense_bitmap_cap<Sr, Rows>();
+  KRef kb{};
+  if ((int64_t)Tmax * kTile <= (int64_t)32 * kWaveWords)
+    kb = kp.template bitmap_dense<Sr, Rows, kWaveWords, DCAP, kDenseBitmapBS>();
+  const bool bm = kb.ok();
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, c.task_ctr,
                      (int64_t)kCtrInts, (int32_t)0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)Tmax, 256, 1024)), dim3(256), 0, st, book,
                      3 * (int64_t)Tmax, (int32_t)0);
   hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
-                     c.plan.bins, c.off2, Tmax, 0, 0, c.tile_min, kRangeCap, c.tasks, c.tasks + c.task_cap,
-                     c.tasks + 2 * c.task_cap, book, c.task_ctr);
+                     c.plan.bins, c.off2, Tmax, bm ? Tmax : 0, bm ? DCAP : 0, c.tile_min, kRangeCap, c.tasks,
+                     c.tasks + c.task_cap, c.tasks + 2 * c.task_cap, book, c.task_ctr);
   hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, Tmax, c.task_ctr);
+  if (bm) {
+    const int grid = c.cus * kb.occ > kQueues ? c.cus * kb.occ : kQueues;
+    c.marks.mark(kPhNumDenseSlab, 1);
+    klaunch(kb, dim3(grid), dim3(kDenseBitmapBS), st, rows, c.plan.bins, c.C, (const Task*)(c.tasks + 2 * c.task_cap),
+            (const int32_t*)book, c.task_ctr, c.err);
+    c.marks.mark(kPhNumDenseSlab, 0);
+  }
   constexpr int BS = tiles_bs((int)sizeof(typename Sr::Acc), (int)sizeof(typename Rows::Src::Item));
   const KRef k = kp.template tiles<Sr, Rows, BS>();
   const int grid = c.cus * k.occ > kQueues ? c.cus * k.occ : kQueues;

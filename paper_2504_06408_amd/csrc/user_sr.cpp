@@ -321,6 +321,10 @@ struct KUser {
   KRef bitmap_row() const {
     return KRef{};
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef bitmap_dense() const {
+    return KRef{};
+  }
 };
 
 }  // namespace
