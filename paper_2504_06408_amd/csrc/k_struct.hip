@@ -137,7 +137,7 @@ void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_o
   if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
     // columns below 65536: a workgroup per row over a bitmap of the columns
     constexpr int kBS = 256;
-    auto kb = k_sym_bitmap_row<Rows, kSymRowWords, kBS>;
+    auto kb = k_sym_bitmap_row<Rows, kSymRowWords, kBS, row_unroll(1 << (LGS - 1), kBS)>;
     static int occb = occupancy(kb, kBS);
     hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
     return;
@@ -151,6 +151,16 @@ template <class Rows, int LGS>
 void sym_hash_wave_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
   const int n = plan.count[bin];
   if (n == 0) return;
+  if constexpr (LGS >= 10) {
+    if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
+      // columns below 65536: a workgroup per row over a bitmap of the columns
+      constexpr int kBS = 256;
+      auto kb = k_sym_bitmap_row<Rows, kSymRowWords, kBS, row_unroll(1 << (LGS - 1), kBS)>;
+      static int occb = occupancy(kb, kBS);
+      hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
+      return;
+    }
+  }
   constexpr int BS = 256;
   auto k = k_sym_hash_wave<Rows, LGS, BS>;
   static int occ = occupancy(k, BS);
@@ -162,8 +172,15 @@ void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int
                     hipStream_t st) {
   const int nd = plan.ndense();
   if (nd == 0) return;
+  if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
+    // narrow B: a bitmap of four tiles, 256-thread workgroups
+    auto k = k_sym_dense<Rows, 4, 256>;
+    static int occ = occupancy(k, 256);
+    hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(256), 0, st, rows, plan.bins, cnt_out, off2);
+    return;
+  }
   constexpr int BS = sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512;
-  auto k = k_sym_dense<Rows>;
+  auto k = k_sym_dense<Rows, kSymTiles, BS>;
   static int occ = occupancy(k, BS);
   hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(BS), 0, st, rows, plan.bins, cnt_out, off2);
 }

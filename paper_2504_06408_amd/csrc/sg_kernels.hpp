@@ -837,6 +837,11 @@ struct BitmapRowSmem {
   int64_t start[BS], off[BS], wave[BS / kWave];
 };
 
+// Products per lane per round of a workgroup-per-row fold over rows of about
+// P products: small enough that every wavefront of the workgroup gets a
+// block of the row, at most kUnroll.
+constexpr int row_unroll(int P, int BS) { return P / BS < 1 ? 1 : (P / BS > kUnroll ? kUnroll : P / BS); }
+
 // One row (source s bound to local row li, m entries written from o); the
 // bitmap is clear on entry and on exit.
 template <class Sr, class Src, int WORDS, int CAP, int BS>
@@ -849,13 +854,14 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
   constexpr int kThreadWords = WORDS / BS;
   static_assert(WORDS % BS == 0 && CAP <= 65535, "whole words per thread, 16-bit ranks");
   static_assert(32 * WORDS <= 65536, "16-bit columns");
+  constexpr int U = row_unroll(CAP, BS);
   const int w0 = (int)threadIdx.x * kThreadWords;
   for (int x = threadIdx.x; x < m && x < CAP; x += BS) sm.val[x] = Sr::ident();
   const int64_t nsrc = s.bind(li, 0, s.T);
   // pass 1: the column set (columns masked to the bitmap)
   auto f1 = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
   auto a1 = [&](int32_t c) { atomicOr(&sm.bits[c >> 5], 1u << (c & 31)); };
-  for_each_product<BS, kUnroll>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f1, a1);
+  for_each_product<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f1, a1);
   int32_t lt = 0;
 #pragma unroll
   for (int k = 0; k < kThreadWords; ++k) lt += __popc(sm.bits[w0 + k]);
@@ -880,7 +886,7 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
       sm.col[rr] = (uint16_t)p.c;
     }
   };
-  for_each_product<BS, kUnroll>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f2, a2);
+  for_each_product<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f2, a2);
   // write-out in rank order; the thread's words are cleared for the next row
   for (int x = threadIdx.x; x < m && x < CAP; x += BS) {
     C.col[o + x] = (int32_t)sm.col[x];
@@ -912,7 +918,7 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int
 
 // Symbolic count of rows over at most 32*WORDS columns, one workgroup per
 // row: the distinct columns are the set bits of an LDS bitmap.
-template <class Rows, int WORDS, int BS>
+template <class Rows, int WORDS, int BS, int U>
 __global__ __launch_bounds__(BS) void k_sym_bitmap_row(Rows rows, Bins bins, int bin, int64_t* cnt_out) {
   using Src = typename Rows::Src;
   using Item = typename Src::Item;
@@ -935,7 +941,7 @@ __global__ __launch_bounds__(BS) void k_sym_bitmap_row(Rows rows, Bins bins, int
     const int64_t nsrc = s.bind(li, 0, s.T);
     auto f = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
     auto a = [&](int32_t c) { atomicOr(&s_bits[c >> 5], 1u << (c & 31)); };
-    for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, f, a);
+    for_each_product<BS, U>(s, nsrc, s_item, s_start, s_off, s_wave, f, a);
     int64_t lt = 0;
 #pragma unroll
     for (int k = 0; k < kThreadWords; ++k) {
@@ -1046,20 +1052,21 @@ __global__ __launch_bounds__(BS) void k_num_hash(Rows rows, Bins bins, int bin, 
 
 // ---- dense rows: column tiles ----------------------------------------------------------
 
-// Symbolic: a bitmap over up to 64 tiles (1M columns, 128 KB of LDS) per pass;
-// per-tile popcounts give the row's count and its per-tile output offsets
+// Symbolic: a bitmap over up to TILES tiles (64: 1M columns, 128 KB of LDS;
+// 4 for narrow B, 8 KB, several workgroups per CU) per pass; per-tile
+// popcounts give the row's count and its per-tile output offsets
 // off2[h*(Tmax+1) + t] (t = 0..Tmax; entries past the row's own T repeat the
 // total).
-template <class Rows>
-__global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512) void k_sym_dense(
-    Rows rows, Bins bins, int64_t* cnt_out, int32_t* off2) {
+template <class Rows, int TILES, int BS>
+__global__ __launch_bounds__(BS) void k_sym_dense(Rows rows, Bins bins, int64_t* cnt_out, int32_t* off2) {
   using Src = typename Rows::Src;
-  constexpr int BS = sizeof(typename Src::Item) <= 8 ? 1024 : 512, NW = BS / kWave;
+  constexpr int NW = BS / kWave;
+  static_assert(TILES <= kWave, "one wavefront scans the tile counts");
   using Item = typename Src::Item;
-  __shared__ uint32_t s_bm[kSymTiles * kTileWords];
+  __shared__ uint32_t s_bm[TILES * kTileWords];
   __shared__ Item s_item[BS];
   __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
-  __shared__ int32_t s_tcnt[kSymTiles];
+  __shared__ int32_t s_tcnt[TILES];
   __shared__ int32_t s_run;
   const int32_t first = bins.start[kBinDense0];
   const int32_t nd = dense_rows(bins);
@@ -1073,8 +1080,8 @@ __global__ __launch_bounds__(sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512)
     const int32_t T = s.T;
     int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
     int32_t run = 0;
-    for (int st = 0; st < T; st += kSymTiles) {
-      const int t1 = (st + kSymTiles) < T ? (st + kSymTiles) : T;
+    for (int st = 0; st < T; st += TILES) {
+      const int t1 = (st + TILES) < T ? (st + TILES) : T;
       const int64_t c0 = (int64_t)st << kTileLog;
       // whole tiles: columns are interleaved over a tile's words (column x
       // of a tile: word x mod 512, bit x / 512), since only per-tile counts
