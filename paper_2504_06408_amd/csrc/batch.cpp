@@ -11,6 +11,7 @@
 // pipeline -- analysis, binning, tile bounds, symbolic, scan, pool guard,
 // numeric, for products and then merges, and the per-result row pointers --
 // into a hipGraph; sg_batch_execute only replays that graph.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <string>
@@ -127,6 +128,7 @@ struct sg_plan {
   GroupDesc* d_groups = nullptr;
   PartDesc* d_parts = nullptr;
   int64_t *d_rbase_p = nullptr, *d_rbase_m = nullptr, *d_lbase_p = nullptr, *d_lbase_m = nullptr;
+  int32_t *d_coarse_p = nullptr, *d_coarse_m = nullptr;  // owners of every 256th row
   int64_t *d_lrow_p = nullptr, *d_lrow_m = nullptr;
   int64_t ltot_p = 0, ltot_m = 0;
   int32_t* d_flag = nullptr;  // [0] pool overflow, [1] consistency, [kCtrBase, ...) task counters
@@ -286,6 +288,20 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   int nparts = 0;
   for (int g = 0; g < ng; ++g) nparts += P->go[(size_t)g + 1] - P->go[(size_t)g];
 
+  // owner of every 256th row of each row space (and of its last row)
+  auto coarse_of = [](const std::vector<int64_t>& rbase, int n, int64_t R) {
+    std::vector<int32_t> c((size_t)(R > 0 ? ((R - 1) >> kOwnerShift) + 2 : 2), 0);
+    for (size_t k = 0; k < c.size(); ++k) {
+      int64_t r = (int64_t)k << kOwnerShift;
+      r = r < R - 1 ? r : (R > 0 ? R - 1 : 0);
+      c[k] = (int32_t)(std::upper_bound(rbase.begin(), rbase.begin() + n, r) - rbase.begin()) - 1;
+      c[k] = c[k] < 0 ? 0 : c[k];
+    }
+    return c;
+  };
+  const std::vector<int32_t> coarse_p = coarse_of(P->rbase_p, np, Rp);
+  const std::vector<int32_t> coarse_m = coarse_of(P->rbase_m, ng > 0 ? ng : 1, Rm);
+
   SgArena m;
   m.take<ProbDesc>((size_t)np);
   m.take<GroupDesc>((size_t)(ng > 0 ? ng : 1));
@@ -297,6 +313,8 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   m.take<int64_t>((size_t)P->ltot_p);
   m.take<int64_t>((size_t)(P->ltot_m > 0 ? P->ltot_m : 1));
   m.take<int32_t>(kFlagInts);
+  m.take<int32_t>(coarse_p.size());
+  m.take<int32_t>(coarse_m.size());
   SG_HIP(h, P->tables.ensure(m.off));
   SgArena a;
   a.base = (char*)P->tables.p;
@@ -310,6 +328,8 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   P->d_lrow_p = a.take<int64_t>((size_t)P->ltot_p);
   P->d_lrow_m = a.take<int64_t>((size_t)(P->ltot_m > 0 ? P->ltot_m : 1));
   P->d_flag = a.take<int32_t>(kFlagInts);
+  P->d_coarse_p = a.take<int32_t>(coarse_p.size());
+  P->d_coarse_m = a.take<int32_t>(coarse_m.size());
 
   // one product and no merges: recorded as a single product on the
   // column-slab path (no tile-bounds tables needed)
@@ -351,6 +371,8 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
   SG_HIP(h, hipMemcpyAsync(P->d_probs, probs.data(), sizeof(ProbDesc) * (size_t)np, hipMemcpyHostToDevice, st));
   SG_HIP(h, hipMemcpyAsync(P->d_rbase_p, P->rbase_p.data(), sizeof(int64_t) * ((size_t)np + 1), hipMemcpyHostToDevice, st));
   SG_HIP(h, hipMemcpyAsync(P->d_rbase_m, P->rbase_m.data(), sizeof(int64_t) * ((size_t)ng + 1), hipMemcpyHostToDevice, st));
+  SG_HIP(h, hipMemcpyAsync(P->d_coarse_p, coarse_p.data(), sizeof(int32_t) * coarse_p.size(), hipMemcpyHostToDevice, st));
+  SG_HIP(h, hipMemcpyAsync(P->d_coarse_m, coarse_m.data(), sizeof(int32_t) * coarse_m.size(), hipMemcpyHostToDevice, st));
   SG_HIP(h, hipMemcpyAsync(P->d_lbase_p, lb_p.data(), sizeof(int64_t) * ((size_t)np + 1), hipMemcpyHostToDevice, st));
   SG_HIP(h, hipMemcpyAsync(P->d_lbase_m, lb_m.data(), sizeof(int64_t) * ((size_t)ng + 1), hipMemcpyHostToDevice, st));
   launch_fill_i32(P->d_flag, 8, 0, st);
@@ -377,6 +399,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
     S.src.mode = kModeBatchProducts;
     S.src.probs = P->d_probs;
     S.src.rbase = P->d_rbase_p;
+    S.src.coarse = P->d_coarse_p;
     S.src.ntable = np;
     S.src.nrows = Rp;
     S.src.T = Tmax_p;
@@ -405,6 +428,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
     M.src.mode = kModeBatchMerges;
     M.src.groups = P->d_groups;
     M.src.rbase = P->d_rbase_m;
+    M.src.coarse = P->d_coarse_m;
     M.src.ntable = ng;
     M.src.nrows = Rm;
     M.src.T = Tmax_m;

@@ -23,7 +23,7 @@ __global__ void k_pool_guard(const int64_t* off_end, int64_t cap_entries, int32_
 __global__ __launch_bounds__(256) void k_local_rowptr(const int64_t* off, const int64_t* rbase, const int64_t* lbase,
                                                       int32_t nres, int64_t total, int64_t* out) {
   for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
-    const int q = owner_of(lbase, nres, x);
+    const int q = owner_search(lbase, nres, x);
     const int64_t i = x - lbase[q];
     out[x] = off[rbase[q] + i] - off[rbase[q]];
   }

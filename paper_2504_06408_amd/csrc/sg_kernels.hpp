@@ -275,8 +275,24 @@ struct GroupDesc {
   int32_t T;
 };
 
-SG_DEV int owner_of(const int64_t* rbase, int32_t n, int64_t r) {
+// Owner of global row r: the last problem q with rbase[q] <= r.
+// owner_search looks among all n problems; owner_of only among those that
+// begin inside r's block of 2^kOwnerShift rows (none, for a block inside one
+// problem), from coarse[c], the owner of row min(c * 2^kOwnerShift, rows - 1),
+// kept for every block c and one more.
+constexpr int kOwnerShift = 8;
+SG_DEV int owner_search(const int64_t* rbase, int32_t n, int64_t r) {
   int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rbase[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+SG_DEV int owner_of(const int64_t* rbase, const int32_t* coarse, int64_t r) {
+  const int64_t c = r >> kOwnerShift;
+  int lo = coarse[c], hi = coarse[c + 1];
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (rbase[mid] <= r) lo = mid;
@@ -289,11 +305,12 @@ template <class V, bool kVals>
 struct TableRows {
   using Src = SpgemmSrc<V, kVals>;
   const ProbDesc* probs;
-  const int64_t* rbase;  // first global row of each product, ascending
+  const int64_t* rbase;   // first global row of each product, ascending
+  const int32_t* coarse;  // owners of every 256th row (owner_of)
   int32_t nprob;
   int32_t Tmax;
   SG_DEV void get(int64_t r, Src& s, int64_t& i) const {
-    const int q = owner_of(rbase, nprob, r);
+    const int q = owner_of(rbase, coarse, r);
     const ProbDesc& d = probs[q];
     s.a_rowptr = d.a_rowptr;
     s.a_col = d.a_col;
@@ -313,10 +330,11 @@ struct MergeTableRows {
   using Src = MergeSrc<V>;
   const GroupDesc* groups;
   const int64_t* rbase;
+  const int32_t* coarse;
   int32_t ngroups;
   int32_t Tmax;
   SG_DEV void get(int64_t r, Src& s, int64_t& i) const {
-    const int q = owner_of(rbase, ngroups, r);
+    const int q = owner_of(rbase, coarse, r);
     const GroupDesc& g = groups[q];
     s.parts = g.parts;
     s.nparts = g.nparts;

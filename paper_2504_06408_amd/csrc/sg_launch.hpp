@@ -34,6 +34,7 @@ struct RowSource {
   const ProbDesc* probs;
   const GroupDesc* groups;
   const int64_t* rbase;
+  const int32_t* coarse;  // owner of every 256th global row (see owner_of)
   int32_t ntable;
   // all
   int64_t nrows;  // (global) rows
@@ -150,8 +151,8 @@ inline void with_rows(const RowSource& r, F&& f) {
   switch (r.mode) {
     case kModeProduct: f(OneRows<SpgemmSrc<V, kVals>>{make_spgemm_src<V, kVals>(r), r.T}); break;
     case kModeMerge: f(OneRows<MergeSrc<V>>{make_merge_src<V>(r), r.T}); break;
-    case kModeBatchProducts: f(TableRows<V, kVals>{r.probs, r.rbase, r.ntable, r.T}); break;
-    case kModeBatchMerges: f(MergeTableRows<V>{r.groups, r.rbase, r.ntable, r.T}); break;
+    case kModeBatchProducts: f(TableRows<V, kVals>{r.probs, r.rbase, r.coarse, r.ntable, r.T}); break;
+    case kModeBatchMerges: f(MergeTableRows<V>{r.groups, r.rbase, r.coarse, r.ntable, r.T}); break;
   }
 }
 
