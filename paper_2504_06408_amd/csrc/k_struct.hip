@@ -128,20 +128,34 @@ void analyze_rows(const Rows& rows, const RowSource& r, const Policy& pol, const
   hipLaunchKernelGGL(k_bin_scatter<kAnaBS>, dim3(nblk), dim3(kAnaBS), 0, st, bin, r.nrows, blk_off, bin_start, list);
 }
 
-constexpr int kSymRowWords = 2048;
+// Rows of a hash bin (up to 2^(LGS-1) products) whose B has at most 65536
+// columns: a workgroup per row over an LDS bitmap of the columns (1024 words
+// when B has at most 32768 columns, else 2048).  False: B is wider.
+template <class Rows, int LGS>
+bool sym_bitmap_rows(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
+  constexpr int kBS = 256, U = row_unroll(1 << (LGS - 1), kBS);
+  const int64_t cols = (int64_t)rows.Tmax * kTile;
+  const int n = plan.count[bin];
+  if (cols <= (int64_t)32 * 1024) {
+    auto kb = k_sym_bitmap_row<Rows, 1024, kBS, U>;
+    static int occb = occupancy(kb, kBS);
+    hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
+    return true;
+  }
+  if (cols <= (int64_t)32 * 2048) {
+    auto kb = k_sym_bitmap_row<Rows, 2048, kBS, U>;
+    static int occb = occupancy(kb, kBS);
+    hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
+    return true;
+  }
+  return false;
+}
 
 template <class Rows, int LGS, int BS>
 void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
   const int n = plan.count[bin];
   if (n == 0) return;
-  if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
-    // columns below 65536: a workgroup per row over a bitmap of the columns
-    constexpr int kBS = 256;
-    auto kb = k_sym_bitmap_row<Rows, kSymRowWords, kBS, row_unroll(1 << (LGS - 1), kBS)>;
-    static int occb = occupancy(kb, kBS);
-    hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
-    return;
-  }
+  if (sym_bitmap_rows<Rows, LGS>(rows, plan, bin, cnt_out, cus, st)) return;
   auto k = k_sym_hash<Rows, LGS, BS>;
   static int occ = occupancy(k, BS);
   hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, rows, plan.bins, bin, cnt_out);
@@ -152,14 +166,7 @@ void sym_hash_wave_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* 
   const int n = plan.count[bin];
   if (n == 0) return;
   if constexpr (LGS >= 10) {
-    if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
-      // columns below 65536: a workgroup per row over a bitmap of the columns
-      constexpr int kBS = 256;
-      auto kb = k_sym_bitmap_row<Rows, kSymRowWords, kBS, row_unroll(1 << (LGS - 1), kBS)>;
-      static int occb = occupancy(kb, kBS);
-      hipLaunchKernelGGL(kb, dim3(grid_for(n, 1, cus * occb * 4)), dim3(kBS), 0, st, rows, plan.bins, bin, cnt_out);
-      return;
-    }
+    if (sym_bitmap_rows<Rows, LGS>(rows, plan, bin, cnt_out, cus, st)) return;
   }
   constexpr int BS = 256;
   auto k = k_sym_hash_wave<Rows, LGS, BS>;
@@ -172,8 +179,14 @@ void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int
                     hipStream_t st) {
   const int nd = plan.ndense();
   if (nd == 0) return;
-  if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kSymRowWords) {
-    // narrow B: a bitmap of four tiles, 256-thread workgroups
+  if (rows.Tmax <= 2) {
+    // narrow B: a bitmap of two or four tiles, 256-thread workgroups
+    auto k = k_sym_dense<Rows, 2, 256>;
+    static int occ = occupancy(k, 256);
+    hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(256), 0, st, rows, plan.bins, cnt_out, off2);
+    return;
+  }
+  if (rows.Tmax <= 4) {
     auto k = k_sym_dense<Rows, 4, 256>;
     static int occ = occupancy(k, 256);
     hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(256), 0, st, rows, plan.bins, cnt_out, off2);

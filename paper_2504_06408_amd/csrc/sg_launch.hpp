@@ -278,6 +278,7 @@ struct KLib {
 // run one wavefront per row, larger ones one workgroup per row over a shared
 // bitmap (the hash bins of 2^kRowBitmapLgMin slots and up).
 constexpr int kWaveWords = 2048;
+constexpr int kWaveWordsHalf = 1024;
 constexpr int kWaveBS = 128;
 constexpr int kWaveLgMax = 9;
 constexpr int kRowBitmapBS = 256;
@@ -287,20 +288,29 @@ constexpr int kRowBitmapLgMin = 10;
 // one 1024-thread workgroup per CU (bitmap, ranks, the accumulators with
 // their 16-bit columns and the iterator's arrays fill the 160 KB of LDS).
 constexpr int kDenseBitmapBS = 1024;
-template <class Sr, class Rows>
+template <class Sr, class Rows, int WORDS>
 constexpr int dense_bitmap_cap() {
-  constexpr int fixed = kWaveWords * 6 + kDenseBitmapBS * ((int)sizeof(typename Rows::Src::Item) + 16) + 1024;
+  constexpr int fixed = WORDS * 6 + kDenseBitmapBS * ((int)sizeof(typename Rows::Src::Item) + 16) + 1024;
   constexpr int cap = ((160 * 1024 - fixed) / ((int)sizeof(typename Sr::Acc) + 2)) & ~255;
   return cap < 65280 ? cap : 65280;  // ranks are 16-bit
+}
+
+// Bitmap words of the narrow-B kernels for a batch whose widest B has
+// `cols` columns: 1024 (32768 columns) or 2048 (65536); 0: too wide.
+inline int narrow_words(int64_t cols) {
+  return cols <= (int64_t)32 * kWaveWordsHalf ? kWaveWordsHalf : (cols <= (int64_t)32 * kWaveWords ? kWaveWords : 0);
 }
 
 template <class Sr, class Rows, int LGS, int BS, class Kp>
 inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipStream_t st, const Kp& kp) {
   const int n = c.plan.count[bin];
   if (n == 0) return;
+  const int words = narrow_words((int64_t)rows.Tmax * kTile);
   if constexpr (LGS >= kRowBitmapLgMin) {
-    if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kWaveWords) {
-      const KRef kb = kp.template bitmap_row<Sr, Rows, kWaveWords, (1 << (LGS - 1)), kRowBitmapBS>();
+    if (words) {
+      constexpr int CAP = 1 << (LGS - 1);
+      const KRef kb = words == kWaveWordsHalf ? kp.template bitmap_row<Sr, Rows, kWaveWordsHalf, CAP, kRowBitmapBS>()
+                                              : kp.template bitmap_row<Sr, Rows, kWaveWords, CAP, kRowBitmapBS>();
       if (kb.ok()) {
         klaunch(kb, dim3(grid_for(n, 1, c.cus * kb.occ * 4)), dim3(kRowBitmapBS), st, rows, c.plan.bins, (int)bin,
                 c.C, c.err);
@@ -308,8 +318,10 @@ inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipS
       }
     }
   } else if constexpr (LGS <= kWaveLgMax) {
-    if ((int64_t)rows.Tmax * kTile <= (int64_t)32 * kWaveWords) {
-      const KRef kw = kp.template wave_bitmap<Sr, Rows, kWaveWords, (1 << (LGS - 1)), kWaveBS>();
+    if (words) {
+      constexpr int CAP = 1 << (LGS - 1);
+      const KRef kw = words == kWaveWordsHalf ? kp.template wave_bitmap<Sr, Rows, kWaveWordsHalf, CAP, kWaveBS>()
+                                              : kp.template wave_bitmap<Sr, Rows, kWaveWords, CAP, kWaveBS>();
       if (kw.ok()) {
         klaunch(kw, dim3(grid_for(n, kWaveBS / kWave, c.cus * kw.occ * 4)), dim3(kWaveBS), st, rows, c.plan.bins,
                 (int)bin, c.C, c.err);
@@ -387,17 +399,20 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st, 
   const int32_t Tmax = rows.Tmax;
   // over narrow B, whole rows of at most DCAP entries take the bitmap fold:
   // the task builder puts them on its slab list (one slab spanning the row)
-  constexpr int DCAP = dense_bitmap_cap<Sr, Rows>();
+  constexpr int DCAP = dense_bitmap_cap<Sr, Rows, kWaveWords>();
+  constexpr int DCAPH = dense_bitmap_cap<Sr, Rows, kWaveWordsHalf>();
   KRef kb{};
-  if ((int64_t)Tmax * kTile <= (int64_t)32 * kWaveWords)
-    kb = kp.template bitmap_dense<Sr, Rows, kWaveWords, DCAP, kDenseBitmapBS>();
+  const int words = narrow_words((int64_t)Tmax * kTile);
+  if (words == kWaveWordsHalf) kb = kp.template bitmap_dense<Sr, Rows, kWaveWordsHalf, DCAPH, kDenseBitmapBS>();
+  else if (words == kWaveWords) kb = kp.template bitmap_dense<Sr, Rows, kWaveWords, DCAP, kDenseBitmapBS>();
   const bool bm = kb.ok();
+  const int32_t dcap = words == kWaveWordsHalf ? DCAPH : DCAP;
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(kCtrInts, 256, 64)), dim3(256), 0, st, c.task_ctr,
                      (int64_t)kCtrInts, (int32_t)0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)Tmax, 256, 1024)), dim3(256), 0, st, book,
                      3 * (int64_t)Tmax, (int32_t)0);
   hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
-                     c.plan.bins, c.off2, Tmax, bm ? Tmax : 0, bm ? DCAP : 0, c.tile_min, kRangeCap, c.tasks,
+                     c.plan.bins, c.off2, Tmax, bm ? Tmax : 0, bm ? dcap : 0, c.tile_min, kRangeCap, c.tasks,
                      c.tasks + c.task_cap, c.tasks + 2 * c.task_cap, book, c.task_ctr);
   hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, Tmax, c.task_ctr);
   if (bm) {
