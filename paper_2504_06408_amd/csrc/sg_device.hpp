@@ -323,6 +323,87 @@ SG_DEV void wave_bitonic_sort(int32_t& key, P& pay) {
 // folds it into LDS.  Each lane first fetches U products (U independent loads
 // in flight, so the gathers are not serialised behind the LDS updates) and
 // then applies them.
+// One chunk's sources [c0, c0 + BS) into compacted slots (see above);
+// returns the chunk's product count, *nc its slots.
+template <int BS, class Src>
+SG_DEV int64_t product_chunk(const Src& src, int64_t nsrc, int64_t c0, typename Src::Item* s_item, int64_t* s_start,
+                             int64_t* s_off, int64_t* s_wave, int* nc) {
+  constexpr int NW = BS / kWave;
+  const int64_t j = c0 + threadIdx.x;
+  int64_t start = 0, len = 0;
+  typename Src::Item it{};
+  if (j < nsrc) src.load(j, it, start, len);
+  // sources with an empty segment are dropped: one scan of (length, flag)
+  // pairs gives each non-empty source its slot and first product; a slot
+  // keeps its segment start minus that offset, so product q of slot k is
+  // element s_start[k] + q of its source
+  const int64_t pk = (len << 16) | (len > 0 ? 1 : 0);
+  int64_t tot;
+  const int64_t ex = block_excl_scan<NW, int64_t>(pk, s_wave, &tot);
+  if (len > 0) {
+    const int pos = (int)(ex & 0xffff);
+    s_item[pos] = it;
+    s_off[pos] = ex >> 16;
+    s_start[pos] = start - (ex >> 16);
+  }
+  *nc = (int)(tot & 0xffff);
+  block_sync();
+  return tot >> 16;
+}
+
+// The products of block [qb, qb + 64*U) of a chunk of nc slots and `total`
+// products: lane l fetches q = qb + u*64 + l into p[u] (ok[u]: q < total).
+// The owners of the block's first and last product come from a 64-ary
+// search (one LDS read per lane and level); each lane then searches only the
+// slots in between, starting from its previous hit.  All searches come
+// first, then all U fetches (their loads in flight together).
+template <int BS, int U, class Src, class Fetch, class P>
+SG_DEV void product_block(const typename Src::Item* s_item, const int64_t* s_start, const int64_t* s_off, int nc,
+                          int64_t total, int64_t qb, Fetch& fetch, P* p, bool* ok) {
+  constexpr int64_t kBlock = (int64_t)kWave * U;
+  const int lane = lane_id();
+  // odd, so that the lanes' 8-byte offset reads spread over all LDS banks
+  const int stride = ((nc + kWave - 1) / kWave) | 1;
+  const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
+  int a, e;
+  {
+    const int i1 = lane * stride;
+    const int64_t o1 = i1 < nc ? s_off[i1] : INT64_MAX;
+    const int ca = __popcll(__ballot(o1 <= qb)), ce = __popcll(__ballot(o1 <= qe));
+    const int ba = (ca - 1) * stride, be = (ce - 1) * stride;
+    const int l2 = lane & 31;
+    const int i2 = (lane < 32 ? ba : be) + l2;
+    const int64_t o2 = (l2 < stride && i2 < nc) ? s_off[i2] : INT64_MAX;
+    const unsigned long long m2 = __ballot(o2 <= (lane < 32 ? qb : qe));
+    a = ba + __popc((uint32_t)m2) - 1;
+    e = be + __popc((uint32_t)(m2 >> 32)) - 1;
+  }
+  int own[U];
+  int lo = a;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t q = qb + u * kWave + lane;
+    ok[u] = q < total;
+    if (ok[u]) {
+      int hi = e;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= q) lo = mid;
+        else hi = mid - 1;
+      }
+    }
+    own[u] = lo;
+  }
+  // lanes past the chunk's end fetch the block's first product, which
+  // always exists
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = ok[u] ? own[u] : a;
+    const int64_t q = ok[u] ? qb + u * kWave + lane : qb;
+    p[u] = fetch(s_item[k], s_start[k] + q);
+  }
+}
+
 template <int BS, int U, class Src, class Fetch, class Apply>
 SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s_item, int64_t* s_start,
                              int64_t* s_off, int64_t* s_wave, Fetch& fetch, Apply& apply) {
@@ -330,85 +411,69 @@ SG_DEV void for_each_product(const Src& src, int64_t nsrc, typename Src::Item* s
   static_assert(BS < (1 << 16) && (((BS + kWave - 1) / kWave) | 1) <= kWave / 2,
                 "slot counts in 16 bits; two search levels of half a wavefront");
   using P = decltype(fetch(s_item[0], (int64_t)0));
-  const int lane = lane_id();
+  constexpr int64_t kBlock = (int64_t)kWave * U;
   for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
-    const int64_t j = c0 + threadIdx.x;
-    int64_t start = 0, len = 0;
-    typename Src::Item it{};
-    if (j < nsrc) src.load(j, it, start, len);
-    // sources with an empty segment are dropped: one scan of (length, flag)
-    // pairs gives each non-empty source its slot and first product; a slot
-    // keeps its segment start minus that offset, so product q of slot k is
-    // element s_start[k] + q of its source
-    const int64_t pk = (len << 16) | (len > 0 ? 1 : 0);
-    int64_t tot;
-    const int64_t ex = block_excl_scan<NW, int64_t>(pk, s_wave, &tot);
-    if (len > 0) {
-      const int pos = (int)(ex & 0xffff);
-      s_item[pos] = it;
-      s_off[pos] = ex >> 16;
-      s_start[pos] = start - (ex >> 16);
-    }
-    const int nc = (int)(tot & 0xffff);
-    const int64_t total = tot >> 16;
-    block_sync();
+    int nc;
+    const int64_t total = product_chunk<BS>(src, nsrc, c0, s_item, s_start, s_off, s_wave, &nc);
     // Wave w takes blocks of 64*U consecutive products; its lanes take
     // q = qb + u*64 + lane (u < U), so every load instruction is coalesced.
-    // The owners of the block's first and last product come from a 64-ary
-    // search (one LDS read per lane and level); each lane then searches
-    // only the slots in between, starting from its previous hit.  All
-    // searches come first, then all U fetches (their loads in flight
-    // together), then the applies.
-    constexpr int64_t kBlock = (int64_t)kWave * U;
-    // odd, so that the lanes' 8-byte offset reads spread over all LDS banks
-    const int stride = ((nc + kWave - 1) / kWave) | 1;
     for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
-      const int64_t qe = (qb + kBlock - 1) < (total - 1) ? (qb + kBlock - 1) : (total - 1);
-      int a, e;
-      {
-        const int i1 = lane * stride;
-        const int64_t o1 = i1 < nc ? s_off[i1] : INT64_MAX;
-        const int ca = __popcll(__ballot(o1 <= qb)), ce = __popcll(__ballot(o1 <= qe));
-        const int ba = (ca - 1) * stride, be = (ce - 1) * stride;
-        const int l2 = lane & 31;
-        const int i2 = (lane < 32 ? ba : be) + l2;
-        const int64_t o2 = (l2 < stride && i2 < nc) ? s_off[i2] : INT64_MAX;
-        const unsigned long long m2 = __ballot(o2 <= (lane < 32 ? qb : qe));
-        a = ba + __popc((uint32_t)m2) - 1;
-        e = be + __popc((uint32_t)(m2 >> 32)) - 1;
-      }
-      int own[U];
-      bool ok[U];
-      int lo = a;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t q = qb + u * kWave + lane;
-        ok[u] = q < total;
-        if (ok[u]) {
-          int hi = e;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= q) lo = mid;
-            else hi = mid - 1;
-          }
-        }
-        own[u] = lo;
-      }
-      // lanes past the chunk's end fetch the block's first product, which
-      // always exists
       P p[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = ok[u] ? own[u] : a;
-        const int64_t q = ok[u] ? qb + u * kWave + lane : qb;
-        p[u] = fetch(s_item[k], s_start[k] + q);
-      }
+      bool ok[U];
+      product_block<BS, U, Src>(s_item, s_start, s_off, nc, total, qb, fetch, p, ok);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ok[u]) apply(p[u]);
     }
     block_sync();
   }
+}
+
+// A first pass over a row's products that keeps them in registers when the
+// row fits one round (at most BS sources and BS*U products: one block per
+// wavefront).  Then each lane's products of its wavefront's block are
+// fetched with fetch_full into p[u] (ok[u] marks the valid ones), passed to
+// apply1 through key(p[u]), and kept for the caller's later passes; returns
+// true.  A larger row goes through for_each_product(fetch1, apply1) and
+// false is returned.
+template <int BS, int U, class Src, class FetchFull, class Key, class Fetch1, class Apply1, class P>
+SG_DEV bool products_held(const Src& src, int64_t nsrc, typename Src::Item* s_item, int64_t* s_start, int64_t* s_off,
+                          int64_t* s_wave, FetchFull& fetch_full, Key& key, Fetch1& fetch1, Apply1& apply1, P* p,
+                          bool* ok) {
+  constexpr int NW = BS / kWave;
+  constexpr int64_t kBlock = (int64_t)kWave * U;
+#pragma unroll
+  for (int u = 0; u < U; ++u) ok[u] = false;
+  if (nsrc <= BS) {
+    int nc;
+    const int64_t total = product_chunk<BS>(src, nsrc, 0, s_item, s_start, s_off, s_wave, &nc);
+    if (total <= (int64_t)NW * kBlock) {
+      const int64_t qb = (int64_t)wave_id() * kBlock;
+      if (qb < total) {
+        product_block<BS, U, Src>(s_item, s_start, s_off, nc, total, qb, fetch_full, p, ok);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (ok[u]) apply1(key(p[u]));
+      }
+      block_sync();
+      return true;
+    }
+    // too many products to hold: the chunk is set up, so finish this pass
+    // over it (the only chunk) here
+    using P1 = decltype(fetch1(s_item[0], (int64_t)0));
+    for (int64_t qb = (int64_t)wave_id() * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
+      P1 q[U];
+      bool k[U];
+      product_block<BS, U, Src>(s_item, s_start, s_off, nc, total, qb, fetch1, q, k);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k[u]) apply1(q[u]);
+    }
+    block_sync();
+    return false;
+  }
+  for_each_product<BS, U>(src, nsrc, s_item, s_start, s_off, s_wave, fetch1, apply1);
+  return false;
 }
 
 }  // namespace sg

@@ -862,7 +862,7 @@ constexpr int row_unroll(int P, int BS) { return P / BS < 1 ? 1 : (P / BS > kUnr
 
 // One row (source s bound to local row li, m entries written from o); the
 // bitmap is clear on entry and on exit.
-template <class Sr, class Src, int WORDS, int CAP, int BS>
+template <class Sr, class Src, int WORDS, int CAP, int BS, bool kHold>
 SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, int64_t li, int64_t o, int32_t m,
                             OutC C, int32_t* err) {
   using Item = typename Src::Item;
@@ -876,10 +876,22 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
   const int w0 = (int)threadIdx.x * kThreadWords;
   for (int x = threadIdx.x; x < m && x < CAP; x += BS) sm.val[x] = Sr::ident();
   const int64_t nsrc = s.bind(li, 0, s.T);
-  // pass 1: the column set (columns masked to the bitmap)
   auto f1 = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
   auto a1 = [&](int32_t c) { atomicOr(&sm.bits[c >> 5], 1u << (c & 31)); };
-  for_each_product<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f1, a1);
+  auto f2 = [&](const Item& it, int64_t idx) {
+    return ColVal<Acc>{s.col(it, idx) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
+  };
+  // pass 1: the column set (columns masked to the bitmap); with kHold, a row
+  // of one round keeps its products in registers for pass 2
+  ColVal<Acc> pp[kHold ? U : 1];
+  bool ok[kHold ? U : 1];
+  bool held = false;
+  if constexpr (kHold) {
+    auto key = [](const ColVal<Acc>& p) { return p.c; };
+    held = products_held<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f2, key, f1, a1, pp, ok);
+  } else {
+    for_each_product<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f1, a1);
+  }
   int32_t lt = 0;
 #pragma unroll
   for (int k = 0; k < kThreadWords; ++k) lt += __popc(sm.bits[w0 + k]);
@@ -893,9 +905,6 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
   if (threadIdx.x == 0 && total != m) atomicOr(err, 1);
   block_sync();
   // pass 2: fold every product into its compacted slot
-  auto f2 = [&](const Item& it, int64_t idx) {
-    return ColVal<Acc>{s.col(it, idx) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
-  };
   auto a2 = [&](const ColVal<Acc>& p) {
     const int w = p.c >> 5;
     const int32_t rr = (int32_t)sm.rank[w] + __popc(sm.bits[w] & ((1u << (p.c & 31)) - 1u));
@@ -904,7 +913,14 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
       sm.col[rr] = (uint16_t)p.c;
     }
   };
-  for_each_product<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f2, a2);
+  if (held) {
+#pragma unroll
+    for (int u = 0; u < (kHold ? U : 1); ++u)
+      if (ok[u]) a2(pp[u]);
+    block_sync();
+  } else {
+    for_each_product<BS, U>(s, nsrc, sm.item, sm.start, sm.off, sm.wave, f2, a2);
+  }
   // write-out in rank order; the thread's words are cleared for the next row
   for (int x = threadIdx.x; x < m && x < CAP; x += BS) {
     C.col[o + x] = (int32_t)sm.col[x];
@@ -930,7 +946,9 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int
     Src s{};
     int64_t li;
     rows.get(i, s, li);
-    bitmap_row_fold<Sr, Src, WORDS, CAP, BS>(sm, s, li, o, m, C, err);
+    // rows of up to 1024 products keep them in registers between the passes
+    // (at 8 products per lane the registers would cost occupancy)
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 4)>(sm, s, li, o, m, C, err);
   }
 }
 
@@ -1325,7 +1343,7 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_dense(Rows rows, Bins bins, O
     Src s{};
     int64_t li;
     rows.get(i, s, li);
-    bitmap_row_fold<Sr, Src, WORDS, CAP, BS>(sm, s, li, o, m, C, err);
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, false>(sm, s, li, o, m, C, err);
   });
 }
 
