@@ -87,19 +87,52 @@ __global__ __launch_bounds__(BS) void k_slab_bounds(const int64_t* rowptr, const
   const int nx = S * per + S + 1;
   for (int64_t k = w0; k < nb; k += nw) {
     const int64_t b = rowptr[k], e = rowptr[k + 1];
+    const int64_t n = e - b;
+    // a row of at most 63 entries (almost every row) is held one column tile
+    // per lane; lane t finds pos(t), the entries below tile t, by a search
+    // over the lanes' tiles (non-decreasing along the lanes: the row is sorted)
+    int32_t mypos = 0;
+    // (a full wavefront of entries would need a 65th answer; lanes hold tiles
+    // below 64 only)
+    const bool inlanes = n < kWave && T <= kWave;
+    if (inlanes) {
+      const int l = lane_id();
+      const int32_t tl = l < n ? (col[b + l] >> kTileLog) : INT32_MAX;
+      int lo = 0;  // first lane whose tile is >= t (n if none)
+#pragma unroll
+      for (int step = kWave / 2; step > 0; step >>= 1) {
+        const int32_t v = __shfl(tl, lo + step - 1, kWave);
+        if (v < l) lo += step;
+      }
+      mypos = lo < (int)n ? lo : (int32_t)n;
+    }
     auto pos = [&](int t) -> int32_t {
+      int32_t sh = 0;
+      if (inlanes) sh = __shfl(mypos, t & (kWave - 1), kWave);  // the whole wavefront takes part
       if (t <= 0) return 0;
-      if (t >= T) return (int32_t)(e - b);
+      if (t >= T) return (int32_t)n;
+      if (inlanes) return t < kWave ? sh : (int32_t)n;
       return (int32_t)(lower_bound_col(col, b, e, (int64_t)t << kTileLog) - b);
     };
-    for (int x = lane_id(); x < nx; x += kWave) {
+    // every lane runs every round (the lane shuffles of pos read all lanes)
+    for (int x0 = 0; x0 < nx; x0 += kWave) {
+      const int x = x0 + lane_id();
+      int t1, t0;
       if (x < S * per) {
         const int s = x / per, t = x - s * per;
-        const int tg = s * G + t < T ? s * G + t : T;
-        rpt[((int64_t)s * nb + k) * per + t] = pos(tg) - pos(s * G);
+        t1 = s * G + t < T ? s * G + t : T;
+        t0 = s * G;
       } else {
-        const int s = x - S * per;
-        bnd[k * (S + 1) + s] = pos(s * G < T ? s * G : T);
+        const int s = x < nx ? x - S * per : S;
+        t1 = s * G < T ? s * G : T;
+        t0 = 0;
+      }
+      const int32_t p1 = pos(t1), p0 = pos(t0);
+      if (x < S * per) {
+        const int s = x / per, t = x - s * per;
+        rpt[((int64_t)s * nb + k) * per + t] = p1 - p0;
+      } else if (x < nx) {
+        bnd[k * (S + 1) + (x - S * per)] = p1;
       }
     }
   }
