@@ -994,6 +994,61 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
         int nl;
         const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
+        constexpr int kWinU = kSlabU / 2;  // products held per lane (registers: the kernel sits at 128)
+        if (mt < kSpanMin && total <= (int64_t)NW * kWave * kWinU) {
+          // a sparse tile (no span counts) whose products fit one round: the
+          // light tasks' scheme instead of two sweeps of all kTile slots --
+          // products held in registers, a bitmap of the tile's columns and
+          // word ranks, values and 16-bit columns at their ranks, copied out
+          // in order; its LDS is borrowed from the head of the accumulator
+          // and reset to the identity afterwards
+          uint32_t* w_bits = reinterpret_cast<uint32_t*>(s_acc);
+          uint16_t* w_rank = reinterpret_cast<uint16_t*>(w_bits + kTileWords);
+          Acc* w_val = reinterpret_cast<Acc*>(w_rank + kTileWords);
+          uint16_t* w_col = reinterpret_cast<uint16_t*>(w_val + kSpanMin);
+          constexpr int kWinSlots =
+              (int)((kTileWords * 6 + kSpanMin * (sizeof(Acc) + 2) + sizeof(Acc) - 1) / sizeof(Acc));
+          static_assert(kWinSlots <= kTile, "the window fits the accumulator");
+          w_bits[threadIdx.x] = 0u;
+          for (int x = threadIdx.x; x < mt; x += BS) w_val[x] = Sr::ident();
+          block_sync();
+          static_assert(BS == kTileWords, "one bitmap word per thread");
+          ColVal<Acc> pp[kWinU];
+          bool ok[kWinU];
+          slab_round<BS, kWinU, V, kNarrow>(L, nl, total, (int64_t)wv * kWave * kWinU, b.pcv, f, pp, ok);
+#pragma unroll
+          for (int u = 0; u < kWinU; ++u)
+            if (ok[u]) atomicOr(&w_bits[pp[u].c >> 5], 1u << (pp[u].c & 31));
+          block_sync();
+          const uint32_t wb = w_bits[threadIdx.x];
+          int32_t tot;
+          const int32_t ex = block_excl_scan<NW, int32_t>(__popc(wb), s_wave32, &tot);
+          w_rank[threadIdx.x] = (uint16_t)ex;
+          if (threadIdx.x == 0 && tot != mt) atomicOr(err, 1);
+          block_sync();
+#pragma unroll
+          for (int u = 0; u < kWinU; ++u)
+            if (ok[u]) {
+              const int w = pp[u].c >> 5;
+              const int32_t r = (int32_t)w_rank[w] + __popc(w_bits[w] & ((1u << (pp[u].c & 31)) - 1u));
+              if (r < mt) {
+                Sr::lds_acc(&w_val[r], pp[u].v);
+                w_col[r] = (uint16_t)pp[u].c;
+              }
+            }
+          block_sync();
+          const int64_t o0 = uniform64(tk.out + rel);
+          char* colb = reinterpret_cast<char*>(C.col + o0);
+          char* valb = reinterpret_cast<char*>((V*)C.val + o0);
+          for (uint32_t x = threadIdx.x; x < (uint32_t)mt; x += BS) {
+            *reinterpret_cast<int32_t*>(colb + x * (uint32_t)sizeof(int32_t)) = cw0 + (int32_t)w_col[x];
+            *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(w_val[x]);
+          }
+          block_sync();
+          for (int x = threadIdx.x; x < kWinSlots; x += BS) s_acc[x] = Sr::ident();
+          block_sync();
+          continue;
+        }
         slab_iterate<BS, kSlabU, V, false, kNarrow>(L, nl, total, b.pcv, f, ap);
       } else {
         slab_products<BS, kSlabU, V, true, false, kNarrow>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
