@@ -994,7 +994,7 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
         }
         int nl;
         const int64_t total = src_compact<V, true, BS>(L, st, len, av, &nl);
-        constexpr int kWinU = kSlabU / 2;  // products held per lane (registers: the kernel sits at 128)
+        constexpr int kWinU = 2;  // products held per lane (registers: the kernel sits at 128)
         if (mt < kSpanMin && total <= (int64_t)NW * kWave * kWinU) {
           // a sparse tile (no span counts) whose products fit one round: the
           // light tasks' scheme instead of two sweeps of all kTile slots --
