@@ -13,16 +13,18 @@
 //
 //   symbolic  per task an LDS bitmap of the slab (16 KB at 2^17 columns);
 //             per-tile popcounts become the row's per-tile output counts
-//   numeric   bitmap + rank accumulator over a window of the slab: pass 1
-//             sets the window's bitmap, a scan turns it into per-word ranks,
-//             pass 2 folds every product into the compacted slot
-//             rank(column) of an LDS value array, and the bitmap walk writes
-//             the window's entries in column order (no sort, no probing).
-//             A slab whose entries fit the value array is one window; a
-//             larger one is cut into runs of whole tiles that fit, and a
-//             single tile holding more than the array is done in rank chunks
-//             (pass 2 repeated, each pass keeping one range of ranks).  The
-//             task's sources are read once and kept in LDS for all passes.
+//   numeric   a slab holding at most a light task's capacity of entries is
+//             one light task: pass 1 sets the slab's bitmap, a scan turns it
+//             into per-word ranks, pass 2 folds every product into the
+//             compacted slot rank(column) of an LDS value array and stores
+//             its column there too, and both arrays are copied out in column
+//             order (no sort, no probing).  A fuller slab is one heavy task:
+//             the row's sources are read once, then each tile is folded into
+//             a dense LDS accumulator of kTile slots and compacted in column
+//             order by a sweep whose wavefronts take their output offsets
+//             from the symbolic pass's span counts; a sparse tile (no span
+//             counts) whose products fit a round uses the light scheme in
+//             LDS borrowed from the accumulator instead.
 #pragma once
 
 #include "sg_kernels.hpp"
