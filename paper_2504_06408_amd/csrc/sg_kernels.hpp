@@ -1222,30 +1222,38 @@ __host__ __device__ inline const int32_t* book_off(const int32_t* book, int32_t 
   return book + 3 * Tmax + list * (Tmax + 1);
 }
 
+// Bucket counters of up to kTaskAggBuckets tiles per list are aggregated in
+// LDS per block (one global atomic per block and bucket instead of one per
+// task: every dense row of the chip appends to the same few buckets).
+constexpr int kTaskAggBuckets = 1024;
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t G,
                                                     int32_t slab_cap, int32_t tile_min, int32_t range_cap,
                                                     Task* tiles, Task* ranges, Task* slabs, int32_t* book,
                                                     int32_t* ctr) {
   __shared__ unsigned long long s_ent[3];
+  __shared__ int32_t s_cnt[3 * kTaskAggBuckets], s_base[3 * kTaskAggBuckets];
   if (threadIdx.x < 3) s_ent[threadIdx.x] = 0ull;
+  const bool agg = Tmax <= kTaskAggBuckets;  // uniform
+  if (agg)
+    for (int x = threadIdx.x; x < 3 * Tmax; x += BS) s_cnt[x] = 0;
   block_sync();
   unsigned long long ent[3] = {0ull, 0ull, 0ull};
   const int32_t nd = dense_rows(bins);
-  int32_t* cnt_t = book;
-  int32_t* cnt_r = book + Tmax;
-  int32_t* cnt_s = book + 2 * Tmax;
+  int32_t* cnt_g[3] = {book, book + Tmax, book + 2 * Tmax};  // tile, range, slab buckets
+  Task* lists[3] = {tiles, ranges, slabs};
   const int32_t span = G > 0 ? G : Tmax;
-  for (int h = blockIdx.x * BS + threadIdx.x; h < nd; h += gridDim.x * BS) {
+  // the tasks of dense row h, in a fixed order: emit(list, bucket, task)
+  auto gen = [&](int32_t h, bool count, auto&& emit) {
     const int32_t* o2 = off2 + (int64_t)h * (Tmax + 1);
     for (int32_t ta = 0; ta < Tmax; ta += span) {
       const int32_t tb = (ta + span) < Tmax ? (ta + span) : Tmax;
       const int32_t ms = o2[tb] - o2[ta];
       if (ms == 0) continue;
       if (G > 0 && ms <= slab_cap) {
-        const int32_t s = ta / G;
-        slabs[(int64_t)s * nd + atomicAdd(&cnt_s[s], 1)] = Task{h, ta, tb};
-        ent[kListSlab] += (unsigned long long)ms;
+        emit(kListSlab, ta / G, Task{h, ta, tb});
+        if (count) ent[kListSlab] += (unsigned long long)ms;
         continue;
       }
       int32_t r0 = -1, rlast = -1, racc = 0;
@@ -1253,16 +1261,16 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
         const int32_t c = o2[t + 1] - o2[t];
         if (c == 0) continue;
         if (c >= tile_min) {
-          if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
+          if (r0 >= 0) emit(kListRange, r0, Task{h, r0, rlast + 1});
           r0 = -1;
           racc = 0;
-          tiles[(int64_t)t * nd + atomicAdd(&cnt_t[t], 1)] = Task{h, t, t + 1};
-          ent[kListTile] += (unsigned long long)c;
+          emit(kListTile, t, Task{h, t, t + 1});
+          if (count) ent[kListTile] += (unsigned long long)c;
           continue;
         }
-        ent[kListRange] += (unsigned long long)c;
+        if (count) ent[kListRange] += (unsigned long long)c;
         if (r0 >= 0 && racc + c > range_cap) {
-          ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
+          emit(kListRange, r0, Task{h, r0, rlast + 1});
           r0 = -1;
           racc = 0;
         }
@@ -1270,7 +1278,35 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
         rlast = t;
         racc += c;
       }
-      if (r0 >= 0) ranges[(int64_t)r0 * nd + atomicAdd(&cnt_r[r0], 1)] = Task{h, r0, rlast + 1};
+      if (r0 >= 0) emit(kListRange, r0, Task{h, r0, rlast + 1});
+    }
+  };
+  if (!agg) {
+    for (int h = blockIdx.x * BS + threadIdx.x; h < nd; h += gridDim.x * BS)
+      gen(h, true, [&](int l, int32_t bk, const Task& tk) {
+        lists[l][(int64_t)bk * nd + atomicAdd(&cnt_g[l][bk], 1)] = tk;
+      });
+  } else {
+    for (int h0 = blockIdx.x * BS; h0 < nd; h0 += gridDim.x * BS) {
+      const int h = h0 + (int)threadIdx.x;
+      // count the block's tasks per bucket, reserve each bucket's range with
+      // one global atomic, then generate the tasks again into their slots
+      if (h < nd) gen(h, true, [&](int l, int32_t bk, const Task&) { atomicAdd(&s_cnt[l * Tmax + bk], 1); });
+      block_sync();
+      for (int x = threadIdx.x; x < 3 * Tmax; x += BS) {
+        const int32_t c = s_cnt[x];
+        s_base[x] = c > 0 ? atomicAdd(&cnt_g[x / Tmax][x % Tmax], c) : 0;
+        s_cnt[x] = 0;
+      }
+      block_sync();
+      if (h < nd)
+        gen(h, false, [&](int l, int32_t bk, const Task& tk) {
+          const int32_t k = l * Tmax + bk;
+          lists[l][(int64_t)bk * nd + s_base[k] + atomicAdd(&s_cnt[k], 1)] = tk;
+        });
+      block_sync();
+      for (int x = threadIdx.x; x < 3 * Tmax; x += BS) s_cnt[x] = 0;
+      block_sync();
     }
   }
   // entries per task kind (statistics): block sums, one atomic each
