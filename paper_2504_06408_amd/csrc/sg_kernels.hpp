@@ -1397,9 +1397,10 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
   using Acc = typename Sr::Acc;
   using V = typename Sr::V;
   __shared__ Acc s_acc[kTile];
-  __shared__ uint32_t s_bm[kTileWords];
+  __shared__ __align__(8) uint32_t s_bm[kTileWords];
   __shared__ Item s_item[BS];
   __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
+  __shared__ int32_t s_wcnt[NW];
   __shared__ int64_t s_slot;
   for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
   for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
@@ -1425,24 +1426,56 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
       atomicOr(&s_bm[p.c >> 5], 1u << (p.c & 31));
     };
     for_each_product<BS, kUnroll>(s, nsrc, s_item, s_start, s_off, s_wave, fetch, apply);
-    uint32_t bits = threadIdx.x < kTileWords ? s_bm[threadIdx.x] : 0u;
-    int32_t tot;
-    int32_t pos = block_excl_scan<NW, int32_t>(__popc(bits), (int32_t*)s_wave, &tot);
-    if (threadIdx.x == 0 && tot != hi - lo) atomicOr(err, 1);
-    if (threadIdx.x < kTileWords) {
-      while (bits) {
-        const int b = __ffs((int)bits) - 1;
-        bits &= bits - 1u;
-        const int c = threadIdx.x * 32 + b;
-        if (pos < hi - lo) {
-          C.col[base + pos] = (int32_t)(c0 + c);
-          ((V*)C.val)[base + pos] = Sr::out(s_acc[c]);
-        }
-        s_acc[c] = Sr::ident();
-        ++pos;
-      }
-      s_bm[threadIdx.x] = 0u;
+    // compaction: wavefront wv sweeps slots [wv*kSpanW, (wv+1)*kSpanW), 64
+    // per step; a step's occupancy is two bitmap words (one broadcast read),
+    // so its stores go to consecutive outputs; the wavefront's output base
+    // is the popcount of the bitmap words before its span
+    constexpr int kSpanW = kTile / NW, kSpanWords = kSpanW / 32;
+    static_assert(kSpanWords <= kWave && kSpanW % (64 * 8) == 0, "a lane counts one word; whole groups of steps");
+    const int wv = wave_id();
+    const int sb = wv * kSpanW;
+    const uint32_t wbits = lane_id() < kSpanWords ? s_bm[wv * kSpanWords + lane_id()] : 0u;
+    const int32_t cnt = wave_sum((int32_t)__popc(wbits));
+    if (lane_id() == 0) s_wcnt[wv] = cnt;
+    block_sync();
+    int32_t wbase = 0, tot = 0;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      const int32_t v = s_wcnt[u];
+      wbase += u < wv ? v : 0;
+      tot += v;
     }
+    if (threadIdx.x == 0 && tot != hi - lo) atomicOr(err, 1);
+    const uint32_t lim = (uint32_t)(hi - lo - wbase);
+    char* colb = reinterpret_cast<char*>(C.col + uniform64(base + wbase));
+    char* valb = reinterpret_cast<char*>((V*)C.val + uniform64(base + wbase));
+    const unsigned long long* bm64 = reinterpret_cast<const unsigned long long*>(s_bm);
+    uint32_t run = 0;
+    for (int j0 = 0; j0 < kSpanW; j0 += 64 * 8) {
+      Acc v[8];
+      unsigned long long mk[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        v[k] = s_acc[sb + j0 + 64 * k + lane_id()];
+        mk[k] = bm64[(sb + j0 + 64 * k) >> 6];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int x = sb + j0 + 64 * k + lane_id();
+        const bool occ = (mk[k] >> lane_id()) & 1ull;
+        const uint32_t r =
+            run + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[k], 0u));
+        if (occ) {
+          if (r < lim) {
+            *reinterpret_cast<int32_t*>(colb + r * (uint32_t)sizeof(int32_t)) = (int32_t)(c0 + x);
+            *reinterpret_cast<V*>(valb + r * (uint32_t)sizeof(V)) = Sr::out(v[k]);
+          }
+          s_acc[x] = Sr::ident();
+        }
+        run += (uint32_t)__popcll(mk[k]);
+      }
+    }
+    if (lane_id() < kSpanWords) s_bm[wv * kSpanWords + lane_id()] = 0u;
     block_sync();
   });
 }
