@@ -121,6 +121,7 @@ struct SpgemmSrc {
   int64_t ncols;       // columns of B
   int64_t a0;
   int32_t t0, t1;
+  static constexpr bool kParts = false;
 
   struct Item {
     V a;
@@ -175,7 +176,37 @@ SG_DEV int64_t lower_bound_col(const int32_t* col, int64_t lo, int64_t hi, int64
   return lo;
 }
 
-// Row i of a merge: one source per part, segment = the part's row i.
+// First position p in [a, b) with col[p] >= x (b if none), found by the 32
+// lanes of a half-wavefront together: a 32-ary search, one load per lane and
+// level (four dependent loads for rows of ~32k entries instead of ~15).
+// Every lane of the half-wavefront gets the result.
+SG_DEV int64_t halfwave_lower_bound(const int32_t* col, int64_t a, int64_t b, int64_t x) {
+  const int hl = lane_id() & 31;
+  const bool upper = lane_id() >= 32;
+  while (b - a > 32) {
+    const int64_t step = (b - a + 31) / 32;
+    const int64_t p = a + hl * step;
+    const unsigned long long m = __ballot(p < b && (int64_t)col[p] < x);
+    const int c = __popc(upper ? (uint32_t)(m >> 32) : (uint32_t)m);
+    if (c == 0) {
+      b = a;
+    } else {
+      const int64_t nb = a + (int64_t)c * step;
+      a = a + (int64_t)(c - 1) * step + 1;
+      b = nb < b ? nb : b;
+    }
+  }
+  const int64_t p = a + hl;
+  const unsigned long long m = __ballot(p < b && (int64_t)col[p] < x);
+  return a + __popc(upper ? (uint32_t)(m >> 32) : (uint32_t)m);
+}
+
+constexpr int kLdsParts = 64;  // merges of up to this many parts find their tile bounds together
+
+// Row i of a merge: one source per part, segment = the part's row i.  For
+// a task over column tiles [t0, t1) the segments are cut to the tiles' column
+// range, by a binary search per part in load(), or from pre[2j], pre[2j+1]
+// when the workgroup found them together beforehand (merge_bounds).
 template <class V>
 struct MergeSrc {
   const PartDesc* parts;
@@ -184,6 +215,8 @@ struct MergeSrc {
   int64_t ncols;
   int64_t row;
   int32_t t0, t1;
+  const int64_t* pre = nullptr;
+  static constexpr bool kParts = true;
 
   struct Item {
     const int32_t* col;
@@ -194,10 +227,18 @@ struct MergeSrc {
     row = i;
     t0 = ta;
     t1 = tb;
+    pre = nullptr;
     return nparts;
   }
   SG_DEV void load(int64_t j, Item& it, int64_t& start, int64_t& len) const {
     const PartDesc P = parts[j];
+    if (pre != nullptr) {
+      it.col = P.col;
+      it.val = (const V*)P.val;
+      start = pre[2 * j];
+      len = pre[2 * j + 1] - start;
+      return;
+    }
     int64_t s = P.rowptr[row], e = P.rowptr[row + 1];
     if (!(t0 == 0 && t1 == T)) {
       const int64_t lo = (int64_t)t0 << kTileLog;
@@ -215,6 +256,26 @@ struct MergeSrc {
   template <class Sr>
   SG_DEV typename Sr::Acc value(const Item& it, int64_t idx) const {
     return Sr::lift(it.val[idx]);
+  }
+  // Segment bounds of every part for the bound tile range, one wavefront
+  // per part (the lower bound in one half, the upper in the other), into
+  // s_se[2j], s_se[2j+1]; then load() reads them.  All threads of the block
+  // call it; it ends with a barrier.
+  template <int BS>
+  SG_DEV void merge_bounds(int64_t* s_se) {
+    constexpr int NW = BS / kWave;
+    const int64_t lo = (int64_t)t0 << kTileLog;
+    int64_t hi = (int64_t)t1 << kTileLog;
+    hi = hi < ncols ? hi : ncols;
+    for (int j = wave_id(); j < nparts; j += NW) {
+      const PartDesc P = parts[j];
+      const int64_t s = P.rowptr[row], e = P.rowptr[row + 1];
+      const int64_t r = halfwave_lower_bound(P.col, s, e, lane_id() < 32 ? lo : hi);
+      if (lane_id() == 0) s_se[2 * j] = r;
+      if (lane_id() == 32) s_se[2 * j + 1] = r;
+    }
+    block_sync();
+    pre = s_se;
   }
   SG_DEV static Item shfl_item(const Item& it, int src) {
     Item o;
@@ -1002,6 +1063,7 @@ struct HashSmem {
   int32_t hist[(S >= 1024) ? NW * 256 : 1];
   int32_t wt[4];
   int32_t n;
+  int64_t se[Src::kParts ? 2 * kLdsParts : 1];  // merge part bounds (merge_bounds)
 };
 
 // One hash task: the products of local row li restricted to column tiles
@@ -1022,6 +1084,9 @@ SG_DEV void hash_task(HashSmem<Sr, Src, LGS, BS>& sm, Src& s, int64_t li, int32_
   if (threadIdx.x == 0) sm.n = 0;
   block_sync();
   const int64_t nsrc = s.bind(li, t0, t1);
+  if constexpr (Src::kParts) {
+    if (s.nparts <= kLdsParts && !(t0 == 0 && t1 == s.T)) s.template merge_bounds<BS>(sm.se);
+  }
   auto fetch = [&](const Item& it, int64_t idx) {
     return ColVal<typename Sr::Acc>{s.col(it, idx), s.template value<Sr>(it, idx)};
   };
@@ -1402,6 +1467,7 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
   __shared__ int64_t s_start[BS], s_off[BS], s_wave[NW];
   __shared__ int32_t s_wcnt[NW];
   __shared__ int64_t s_slot;
+  __shared__ int64_t s_se[Src::kParts ? 2 * kLdsParts : 1];
   for (int x = threadIdx.x; x < kTile; x += BS) s_acc[x] = Sr::ident();
   for (int x = threadIdx.x; x < kTileWords; x += BS) s_bm[x] = 0u;
   const int32_t* L = bins.list + bins.start[kBinDense0];
@@ -1418,6 +1484,9 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
     int64_t li;
     rows.get(i, s, li);
     const int64_t nsrc = s.bind(li, tk.t0, tk.t1);
+    if constexpr (Src::kParts) {
+      if (s.nparts <= kLdsParts && !(tk.t0 == 0 && tk.t1 == s.T)) s.template merge_bounds<BS>(s_se);
+    }
     auto fetch = [&](const Item& it, int64_t idx) {
       return ColVal<Acc>{(int32_t)(s.col(it, idx) - c0), s.template value<Sr>(it, idx)};
     };
