@@ -192,6 +192,20 @@ void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int
     hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(256), 0, st, rows, plan.bins, cnt_out, off2);
     return;
   }
+  // bitmaps of 16 or 32 tiles (32 or 64 KB) leave room for several
+  // 512-thread workgroups per CU where the 64-tile one fits one
+  if (rows.Tmax <= 16) {
+    auto k = k_sym_dense<Rows, 16, 512>;
+    static int occ = occupancy(k, 512);
+    hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(512), 0, st, rows, plan.bins, cnt_out, off2);
+    return;
+  }
+  if (rows.Tmax <= 32) {
+    auto k = k_sym_dense<Rows, 32, 512>;
+    static int occ = occupancy(k, 512);
+    hipLaunchKernelGGL(k, dim3(grid_for(nd, 1, cus * occ * 2)), dim3(512), 0, st, rows, plan.bins, cnt_out, off2);
+    return;
+  }
   constexpr int BS = sizeof(typename Rows::Src::Item) <= 8 ? 1024 : 512;
   auto k = k_sym_dense<Rows, kSymTiles, BS>;
   static int occ = occupancy(k, BS);
