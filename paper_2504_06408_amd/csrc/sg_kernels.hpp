@@ -914,6 +914,7 @@ struct BitmapRowSmem {
   uint16_t col[CAP];
   typename Src::Item item[BS];
   int64_t start[BS], off[BS], wave[BS / kWave];
+  int64_t se[Src::kParts ? 2 * kLdsParts : 1];  // merge part bounds (merge_bounds)
 };
 
 // Products per lane per round of a workgroup-per-row fold over rows of about
@@ -921,11 +922,13 @@ struct BitmapRowSmem {
 // block of the row, at most kUnroll.
 constexpr int row_unroll(int P, int BS) { return P / BS < 1 ? 1 : (P / BS > kUnroll ? kUnroll : P / BS); }
 
-// One row (source s bound to local row li, m entries written from o); the
-// bitmap is clear on entry and on exit.
+// The part of local row li inside column tiles [t0, t1) (the whole row:
+// 0, T), whose columns must lie below 32*WORDS past the range's first
+// column; m entries written from o.  The bitmap is clear on entry and on
+// exit.
 template <class Sr, class Src, int WORDS, int CAP, int BS, bool kHold>
-SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, int64_t li, int64_t o, int32_t m,
-                            OutC C, int32_t* err) {
+SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, int64_t li, int32_t t0, int32_t t1,
+                            int64_t o, int32_t m, OutC C, int32_t* err) {
   using Item = typename Src::Item;
   using Acc = typename Sr::Acc;
   using V = typename Sr::V;
@@ -936,11 +939,15 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
   constexpr int U = row_unroll(CAP, BS);
   const int w0 = (int)threadIdx.x * kThreadWords;
   for (int x = threadIdx.x; x < m && x < CAP; x += BS) sm.val[x] = Sr::ident();
-  const int64_t nsrc = s.bind(li, 0, s.T);
-  auto f1 = [&](const Item& it, int64_t idx) { return s.col(it, idx) & (32 * WORDS - 1); };
+  const int64_t nsrc = s.bind(li, t0, t1);
+  if constexpr (Src::kParts) {
+    if (s.nparts <= kLdsParts && !(t0 == 0 && t1 == s.T)) s.template merge_bounds<BS>(sm.se);
+  }
+  const int32_t c0 = t0 << kTileLog;  // columns relative to the range's first
+  auto f1 = [&](const Item& it, int64_t idx) { return (s.col(it, idx) - c0) & (32 * WORDS - 1); };
   auto a1 = [&](int32_t c) { atomicOr(&sm.bits[c >> 5], 1u << (c & 31)); };
   auto f2 = [&](const Item& it, int64_t idx) {
-    return ColVal<Acc>{s.col(it, idx) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
+    return ColVal<Acc>{(s.col(it, idx) - c0) & (32 * WORDS - 1), s.template value<Sr>(it, idx)};
   };
   // pass 1: the column set (columns masked to the bitmap); with kHold, a row
   // of one round keeps its products in registers for pass 2
@@ -984,7 +991,7 @@ SG_DEV void bitmap_row_fold(BitmapRowSmem<Sr, Src, WORDS, CAP, BS>& sm, Src& s, 
   }
   // write-out in rank order; the thread's words are cleared for the next row
   for (int x = threadIdx.x; x < m && x < CAP; x += BS) {
-    C.col[o + x] = (int32_t)sm.col[x];
+    C.col[o + x] = c0 + (int32_t)sm.col[x];
     ((V*)C.val)[o + x] = Sr::out(sm.val[x]);
   }
 #pragma unroll
@@ -1009,7 +1016,7 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int
     rows.get(i, s, li);
     // rows of up to 1024 products keep them in registers between the passes
     // (at 8 products per lane the registers would cost occupancy)
-    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 4)>(sm, s, li, o, m, C, err);
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 4)>(sm, s, li, 0, s.T, o, m, C, err);
   }
 }
 
@@ -1291,6 +1298,7 @@ __host__ __device__ inline const int32_t* book_off(const int32_t* book, int32_t 
 // LDS per block (one global atomic per block and bucket instead of one per
 // task: every dense row of the chip appends to the same few buckets).
 constexpr int kTaskAggBuckets = 1024;
+constexpr int kRangeSpanMax = 4;  // column tiles of a range task
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t G,
@@ -1334,7 +1342,7 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
           continue;
         }
         if (count) ent[kListRange] += (unsigned long long)c;
-        if (r0 >= 0 && racc + c > range_cap) {
+        if (r0 >= 0 && (racc + c > range_cap || t + 1 - r0 > kRangeSpanMax)) {
           emit(kListRange, r0, Task{h, r0, rlast + 1});
           r0 = -1;
           racc = 0;
@@ -1444,7 +1452,37 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_dense(Rows rows, Bins bins, O
     Src s{};
     int64_t li;
     rows.get(i, s, li);
-    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, false>(sm, s, li, o, m, C, err);
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, false>(sm, s, li, 0, s.T, o, m, C, err);
+  });
+}
+
+// Range tasks (runs of sparse tiles, at most kRangeSpanMax tiles and CAP
+// entries) by the same bitmap-and-rank fold over the range's columns,
+// instead of a hash table and a sort.
+template <class Sr, class Rows, int WORDS, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_ranges_bitmap(Rows rows, Bins bins, OutC C, const int32_t* off2,
+                                                          const Task* tasks, const int32_t* book, int32_t* ctr,
+                                                          int32_t* err) {
+  using Src = typename Rows::Src;
+  static_assert(32 * WORDS >= kRangeSpanMax * kTile, "a range fits the bitmap");
+  __shared__ BitmapRowSmem<Sr, Src, WORDS, CAP, BS> sm;
+  __shared__ int64_t s_slot;
+  for (int x = threadIdx.x; x < WORDS; x += BS) sm.bits[x] = 0u;
+  block_sync();
+  const int32_t* L = bins.list + bins.start[kBinDense0];
+  const int32_t Tmax = rows.Tmax;
+  const int32_t nd = dense_rows(bins);
+  for_each_queued(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, [&](int64_t g) {
+    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g);
+    const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
+    const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
+    const int64_t i = L[tk.h];
+    if (threadIdx.x == 0 && (hi - lo > CAP || tk.t1 - tk.t0 > kRangeSpanMax)) atomicOr(err, 1);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 8)>(sm, s, li, tk.t0, tk.t1, C.rowptr[i] + lo,
+                                                                         hi - lo, C, err);
   });
 }
 

@@ -270,6 +270,11 @@ struct KLib {
     static const KRef k = kref_static((const void*)k_num_bitmap_dense<Sr, Rows, WORDS, CAP, BS>, BS);
     return k;
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef ranges_bitmap() const {
+    static const KRef k = kref_static((const void*)k_num_ranges_bitmap<Sr, Rows, WORDS, CAP, BS>, BS);
+    return k;
+  }
 };
 
 // Hash rows whose columns all lie below 32 * kWaveWords (products whose B has
@@ -288,9 +293,11 @@ constexpr int kRowBitmapLgMin = 10;
 // one 1024-thread workgroup per CU (bitmap, ranks, the accumulators with
 // their 16-bit columns and the iterator's arrays fill the 160 KB of LDS).
 constexpr int kDenseBitmapBS = 1024;
+constexpr int kRangeBitmapBS = 256;
 template <class Sr, class Rows, int WORDS>
 constexpr int dense_bitmap_cap() {
-  constexpr int fixed = WORDS * 6 + kDenseBitmapBS * ((int)sizeof(typename Rows::Src::Item) + 16) + 1024;
+  constexpr int fixed = WORDS * 6 + kDenseBitmapBS * ((int)sizeof(typename Rows::Src::Item) + 16) + 1024 +
+                        (Rows::Src::kParts ? 16 * kLdsParts : 0);
   constexpr int cap = ((160 * 1024 - fixed) / ((int)sizeof(typename Sr::Acc) + 2)) & ~255;
   return cap < 65280 ? cap : 65280;  // ranks are 16-bit
 }
@@ -429,12 +436,21 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st, 
   klaunch(k, dim3(grid), dim3(BS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2, (const Task*)c.tasks,
           (const int32_t*)book, c.task_ctr, c.err);
   c.marks.mark(kPhNumDenseTiles, 0);
-  constexpr int RBS = ranges_bs((int)sizeof(typename Sr::Acc));
-  const KRef k2 = kp.template ranges<Sr, Rows, kRangeLg, RBS>();
-  const int grid2 = c.cus * k2.occ > kQueues ? c.cus * k2.occ : kQueues;
+  // range tasks (at most kRangeSpanMax tiles): the bitmap fold, else (run-
+  // time semirings) a hash table and a sort
+  const KRef kr = kp.template ranges_bitmap<Sr, Rows, kWaveWords, kRangeCap, kRangeBitmapBS>();
   c.marks.mark(kPhNumDenseRanges, 1);
-  klaunch(k2, dim3(grid2), dim3(RBS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2,
-          (const Task*)(c.tasks + c.task_cap), (const int32_t*)book, c.task_ctr, c.err);
+  if (kr.ok()) {
+    const int grid2 = c.cus * kr.occ > kQueues ? c.cus * kr.occ : kQueues;
+    klaunch(kr, dim3(grid2), dim3(kRangeBitmapBS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2,
+            (const Task*)(c.tasks + c.task_cap), (const int32_t*)book, c.task_ctr, c.err);
+  } else {
+    constexpr int RBS = ranges_bs((int)sizeof(typename Sr::Acc));
+    const KRef k2 = kp.template ranges<Sr, Rows, kRangeLg, RBS>();
+    const int grid2 = c.cus * k2.occ > kQueues ? c.cus * k2.occ : kQueues;
+    klaunch(k2, dim3(grid2), dim3(RBS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2,
+            (const Task*)(c.tasks + c.task_cap), (const int32_t*)book, c.task_ctr, c.err);
+  }
   c.marks.mark(kPhNumDenseRanges, 0);
 }
 

@@ -325,6 +325,10 @@ struct KUser {
   KRef bitmap_dense() const {
     return KRef{};
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef ranges_bitmap() const {
+    return KRef{};
+  }
 };
 
 }  // namespace
