@@ -164,10 +164,12 @@ sg_status sg_handle_destroy(sg_handle* h);
  * 2^slab_log columns), "light_cap" (0 = the light kernel's LDS capacity, or
  * 1..32768: a dense row's slab with at most this many output entries is a
  * light task, a fuller one a heavy task; set here it applies to every
- * semiring), "dense_tile_min" (1..2048, whole-row tile path of batches and
- * dense_slab=0 only: a dense row's column tile with at least this many
- * output entries is accumulated in a dense LDS array, smaller ones in an LDS
- * hash table).  Returns SG_ERR_INVALID for an unknown
+ * semiring), "dense_tile_min" (1..2048, default 2048; whole-row tile path of
+ * batches and dense_slab=0 only: a dense row's column tile with at least
+ * this many output entries is accumulated in a dense LDS array, runs of
+ * smaller ones (at most four tiles and 2048 entries) on an LDS column bitmap,
+ * or for run-time semirings in an LDS hash table).  Returns SG_ERR_INVALID
+ * for an unknown
  * name or a bad value. */
 sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value);
 

@@ -208,7 +208,7 @@ inline void klaunch(const KRef& k, dim3 grid, dim3 block, hipStream_t st, A... a
 // then run the two persistent task kernels.
 constexpr int kRangeLg = 12;          // range tasks: hash table of 4096 slots
 constexpr int kRangeCap = 2048;       // entries per range task
-constexpr int kTileMinDefault = 1024; // entries that make a tile a dense-tile task
+constexpr int kTileMinDefault = 2048; // entries that make a tile a dense-tile task (= kRangeCap)
 
 // Block sizes of the numeric kernels (shared by the launchers and by the
 // run-time compilation of semirings, which instantiates the same kernels).
