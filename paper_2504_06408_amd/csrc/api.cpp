@@ -86,8 +86,13 @@ int32_t tiles_of(int64_t ncols) {
   return t < 1 ? 1 : (int32_t)t;
 }
 
-Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr) {
+Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr, int32_t T) {
   Policy p{};
+  // the library's semirings merge hash rows over B wider than the bitmap
+  // kernels' 65,536 columns; such a row holds all its products in LDS, so its
+  // bin is chosen by its products
+  p.by_products = numeric && h->merge_rows && sr && sr->id >= 1 && sr->id <= 5 && T > 0 &&
+                  narrow_words((int64_t)T * kTile) == 0;
   p.numeric = numeric;
   p.force = h->force;
   p.hash_max = h->hash_max;
@@ -415,7 +420,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   SgArena ar;
   ar.base = (char*)bufs.ws.p;
   BinPlan plan;
-  const Policy pol = make_policy(h, 1, sr);
+  const Policy pol = make_policy(h, 1, sr, r.T);
   clear_phases(h, kPhNumAnalyze, kPhSymDenseBitmap);
   clear_phases(h, kPhNumDenseSlab, kNPhases);
   const Marks mk = handle_marks(h, st);
@@ -478,6 +483,7 @@ sg_status run_numeric(sg_handle* h, const sg_semiring* sr, RowSource& r, const s
   }
   c.tile_min = h->tile_min;
   c.cus = h->cus;
+  c.merge_rows = h->merge_rows;
   c.comp_dense = pol.comp_mode != kCompNone;
   c.light_cap = light_cap_for(h, sr);
   h->last_nd = nd;
@@ -558,6 +564,9 @@ sg_status sg_handle_set_option(sg_handle* h, const char* name, const char* value
   } else if (n == "gather32") {
     if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "gather32 must be 0 or 1");
     h->gather32 = v == "1";
+  } else if (n == "merge_rows") {
+    if (v != "0" && v != "1") return sg_fail(h, SG_ERR_INVALID, "merge_rows must be 0 or 1");
+    h->merge_rows = v == "1";
   } else if (n == "force_path") {
     if (v == "auto") h->force = kForceAuto;
     else if (v == "small") h->force = kForceSmall;

@@ -206,7 +206,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   sg_handle* h = P->h;
   hipStream_t st = P->stream;
   const Policy ps = make_policy(h, 0, nullptr);
-  const Policy pn = make_policy(h, 1, &P->sr);
+  const Policy pn = make_policy(h, 1, &P->sr, S.src.T);
   launch_analyze(S.src, ps, nullptr, S.p, S.nt, S.bin, S.hist, S.blk_off, S.bin_start, S.bin_count, S.list, S.off + 1, st);
   BinPlan bp = S.graph_plan();
   if (S.nd == 0) {
@@ -241,6 +241,7 @@ void record_stage(sg_plan* P, Stage& S, bool has_dense_inputs) {
   }
   c.tile_min = h->tile_min;
   c.cus = h->cus;
+  c.merge_rows = h->merge_rows;
   c.light_cap = light_cap_for(h, &P->sr);
   c.comp_dense = pn.comp_mode != kCompNone;
   switch (P->sr.id) {

@@ -112,6 +112,7 @@ struct sg_handle {
   SlabBufs sb;               // column-slab partition of B and the dense-row table
   int slab = 1;              // dense rows of single products use the column-slab path
   int gather32 = 1;          // slab symbolic gathers at 32-bit offsets where B allows
+  int merge_rows = 1;        // hash rows of 512+ products over wide B merged from their sorted segments
   int32_t tile_min = sg::kTileMinDefault;
   int32_t slab_ls = 0;     // slab width 2^slab_ls of the column-slab path (0: chosen from ncols)
   int32_t light_cap = 0;   // most entries of a light slab task (0: the LDS capacity)
@@ -133,7 +134,7 @@ sg_status sg_check_hip(sg_handle* h, hipError_t e, const char* what);
 
 namespace sg {
 int32_t tiles_of(int64_t ncols);
-Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr);
+Policy make_policy(const sg_handle* h, int numeric, const sg_semiring* sr, int32_t T = 0);
 // Analysis + binning of the rows of r; waits for the stream to read the bin
 // counts.  Scratch comes from `ar`.  p_keep / nt_keep (optional) receive the
 // per-row product and term counts; with rebin set they are read instead and

@@ -51,6 +51,7 @@ struct Policy {
   int32_t comp_mode;
   int32_t comp_min_terms;
   int64_t comp_min_products;
+  int32_t by_products;  // numeric hash bins sized from products (rows the merge kernel takes), not entries
 };
 
 SG_DEV int hash_bin(int64_t need, int lg_floor) {
@@ -80,7 +81,8 @@ SG_DEV int bin_of(const Policy& pol, int64_t p, int64_t m, int64_t nterms) {
   if (!pol.numeric) return hash_bin(p, 8);
   const bool comp = pol.comp_mode == kCompAll ||
                     (pol.comp_mode == kCompRule && nterms > pol.comp_min_terms && p > pol.comp_min_products);
-  const int64_t mm = m < 1 ? 1 : (m > kHashCap ? kHashCap : m);
+  const int64_t need = pol.by_products ? p : m;
+  const int64_t mm = need < 1 ? 1 : (need > kHashCap ? kHashCap : need);
   return hash_bin(mm, kHashLgMin) + (comp ? (kBinHashC0 - kBinHash0) : 0);
 }
 
@@ -1017,6 +1019,192 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int
     // rows of up to 1024 products keep them in registers between the passes
     // (at 8 products per lane the registers would cost occupancy)
     bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 4)>(sm, s, li, 0, s.T, o, m, C, err);
+  }
+}
+
+// Numeric rows of at most CAP products over any B, one workgroup per row,
+// with neither a hash table nor a sort: each source's segment of the row (a
+// B row times its A value, or one part's row in a merge) is already sorted
+// by column, so the row is the merge of its non-empty segments.  The
+// products are staged in LDS in segment order (the runs); each round merges
+// neighbouring runs pairwise, every element finding its place in the merged
+// run by a binary search of its partner run (ties: the left run first, so
+// equal columns stay in source order); after ceil(log2(runs)) rounds equal
+// columns are adjacent and the first element of each group folds the group
+// with (+).  The groups' results are staged at their ranks in the free
+// buffer and copied out coalesced.
+template <class Sr, class Src, int CAP, int BS>
+struct MergeRowSmem {
+  static constexpr int kChunkBytes = BS * (16 + (int)sizeof(typename Src::Item));
+  static constexpr int kBufBytes = CAP * (4 + (int)sizeof(typename Sr::Acc));
+  int32_t key[CAP];
+  typename Sr::Acc val[CAP];
+  // the second (key, value) buffer of the rounds; while the products are
+  // staged, the iterator's chunk arrays (start, off, item)
+  alignas(16) char other[kBufBytes > kChunkBytes ? kBufBytes : kChunkBytes];
+  uint16_t roff[CAP + 1];  // first element of each run (round 0)
+  int64_t wave[BS / kWave];
+};
+
+template <class Sr, class Rows, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_merge_row(Rows rows, Bins bins, int bin, OutC C, int32_t* err) {
+  using Src = typename Rows::Src;
+  using Item = typename Src::Item;
+  using Acc = typename Sr::Acc;
+  using V = typename Sr::V;
+  constexpr int NW = BS / kWave;
+  constexpr int EPT = (CAP + BS - 1) / BS;  // elements per thread
+  constexpr int U = row_unroll(CAP, BS);
+  static_assert(CAP <= 65535, "16-bit run offsets");
+  __shared__ MergeRowSmem<Sr, Src, CAP, BS> sm;
+  int64_t* const c_start = reinterpret_cast<int64_t*>(sm.other);
+  int64_t* const c_off = c_start + BS;
+  Item* const c_item = reinterpret_cast<Item*>(c_off + BS);
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = L[r];
+    const int64_t o = C.rowptr[i];
+    const int32_t m = (int32_t)(C.rowptr[i + 1] - o);
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    auto fetch = [&](const Item& it, int64_t idx) {
+      return ColVal<Acc>{s.col(it, idx), s.template value<Sr>(it, idx)};
+    };
+    // staging, one chunk of BS sources at a time: the products in segment
+    // order and the first element of every non-empty segment
+    int32_t total = 0, runs = 0;  // block-uniform
+    bool over = false;
+    for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
+      int nc;
+      const int64_t ct = product_chunk<BS>(s, nsrc, c0, c_item, c_start, c_off, sm.wave, &nc);
+      if (ct > (int64_t)(CAP - total)) {
+        over = true;
+        break;
+      }
+      for (int k = threadIdx.x; k < nc; k += BS) sm.roff[runs + k] = (uint16_t)(total + c_off[k]);
+      for (int64_t qb = (int64_t)wave_id() * kWave * U; qb < ct; qb += (int64_t)NW * kWave * U) {
+        ColVal<Acc> p[U];
+        bool ok[U];
+        product_block<BS, U, Src>(c_item, c_start, c_off, nc, ct, qb, fetch, p, ok);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (ok[u]) {
+            const int x = total + (int)(qb + u * kWave + lane_id());
+            sm.key[x] = p[u].c;
+            sm.val[x] = p[u].v;
+          }
+      }
+      total += (int32_t)ct;
+      runs += nc;
+      block_sync();
+    }
+    if (over) {  // more products than the bin allows: the analysis disagrees
+      if (threadIdx.x == 0) atomicOr(err, 1);
+      continue;
+    }
+    if (threadIdx.x == 0) sm.roff[runs] = (uint16_t)total;
+    block_sync();
+    int32_t* kin = sm.key;
+    Acc* vin = sm.val;
+    int32_t* kout = reinterpret_cast<int32_t*>(sm.other);
+    Acc* vout = reinterpret_cast<Acc*>(sm.other + CAP * 4);
+    // searches step down from the largest power of two below the bound, for
+    // all EPT elements of a thread together (their LDS reads overlap)
+    const int top_len = total > 0 ? 1 << (31 - __clz(total)) : 0;
+    for (int sh = 0; (1 << sh) < runs; ++sh) {
+      const int rr = (runs + (1 << sh) - 1) >> sh;  // runs of this round
+      const int top_run = 1 << (31 - __clz(rr));
+      int q[EPT];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) q[k] = 0;
+      // the run of each element: the last q with roff[q << sh] <= x
+      for (int step = top_run; step > 0; step >>= 1) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int x = (int)threadIdx.x + k * BS;
+          const int t = q[k] + step;
+          if (x < total && t < rr && (int)sm.roff[t << sh] <= x) q[k] = t;
+        }
+      }
+      int32_t c[EPT];
+      int ps[EPT], len[EPT], cnt[EPT];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const int x = (int)threadIdx.x + k * BS;
+        const int p = q[k] ^ 1;
+        c[k] = x < total ? kin[x] : 0;
+        ps[k] = 0;
+        len[k] = 0;
+        cnt[k] = 0;
+        if (x < total && p < rr) {
+          const int pe = (p + 1) << sh;
+          ps[k] = sm.roff[p << sh];
+          len[k] = (int)sm.roff[pe < runs ? pe : runs] - ps[k];
+        }
+      }
+      // the partner run's elements before the element: below its column
+      // for a left run, up to and including it for a right run
+      for (int step = top_len; step > 0; step >>= 1) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int t = cnt[k] + step;
+          if (t <= len[k]) {
+            const int32_t y = kin[ps[k] + t - 1];
+            if ((q[k] & 1) ? y <= c[k] : y < c[k]) cnt[k] = t;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const int x = (int)threadIdx.x + k * BS;
+        if (x < total) {
+          // a right run's merged run starts at its partner's first element
+          const int dest = (q[k] & 1) ? ps[k] + (x - (int)sm.roff[q[k] << sh]) + cnt[k] : x + cnt[k];
+          kout[dest] = c[k];
+          vout[dest] = vin[x];
+        }
+      }
+      block_sync();
+      int32_t* kt = kin;
+      kin = kout;
+      kout = kt;
+      Acc* vt = vin;
+      vin = vout;
+      vout = vt;
+    }
+    // groups of equal columns: thread t holds elements [t*EPT, (t+1)*EPT)
+    const int x0 = (int)threadIdx.x * EPT;
+    int32_t heads = 0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int x = x0 + k;
+      if (x < total && (x == 0 || kin[x] != kin[x - 1])) ++heads;
+    }
+    int32_t nh;
+    int32_t rk = block_excl_scan<NW, int32_t>(heads, (int32_t*)sm.wave, &nh);
+    if (threadIdx.x == 0 && nh != m) atomicOr(err, 1);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int x = x0 + k;
+      if (x < total && (x == 0 || kin[x] != kin[x - 1])) {
+        const int32_t cx = kin[x];
+        Acc a = vin[x];
+        for (int y = x + 1; y < total && kin[y] == cx; ++y) a = Sr::add(a, vin[y]);
+        kout[rk] = cx;
+        vout[rk] = a;
+        ++rk;
+      }
+    }
+    block_sync();
+    const int wr = nh < m ? nh : m;
+    for (int x = threadIdx.x; x < wr; x += BS) {
+      C.col[o + x] = kout[x];
+      ((V*)C.val)[o + x] = Sr::out(vout[x]);
+    }
+    block_sync();
   }
 }
 

@@ -95,6 +95,7 @@ struct NumCtx {
   int cus;
   int comp_dense;     // float sums: dense rows use compensated accumulation
   int32_t light_cap;  // slab path: most entries of a light task (0: the LDS capacity)
+  int merge_rows;     // hash bins of 2^kMergeRowLgMin slots and up over wide B: merge kernel
 };
 
 // Bytes of the dense-row task buffer: three task lists of task_cap entries
@@ -255,6 +256,11 @@ struct KLib {
     static const KRef k = kref_static((const void*)k_num_ranges<Sr, Rows, LGS, BS>, BS);
     return k;
   }
+  template <class Sr, class Rows, int CAP, int BS>
+  KRef merge_row() const {
+    static const KRef k = kref_static((const void*)k_num_merge_row<Sr, Rows, CAP, BS>, BS);
+    return k;
+  }
   template <class Sr, class Rows, int WORDS, int CAP, int BS>
   KRef wave_bitmap() const {
     static const KRef k = kref_static((const void*)k_num_wave_bitmap<Sr, Rows, WORDS, CAP, BS>, BS);
@@ -288,6 +294,14 @@ constexpr int kWaveBS = 128;
 constexpr int kWaveLgMax = 9;
 constexpr int kRowBitmapBS = 256;
 constexpr int kRowBitmapLgMin = 10;
+
+// Hash rows over wider B, of up to 2^(kMergeRowLgMin-1) products and more,
+// are merged from their sorted segments (k_num_merge_row): the (key, value)
+// buffers take 2*CAP*(4+acc) bytes of LDS, so rows of 4096 products with
+// 4-byte accumulators run two 512-thread workgroups per CU, and with 8-byte
+// ones one of 1024 threads.
+constexpr int kMergeRowLgMin = 10;
+constexpr int merge_row_bs(int cap, int acc_bytes) { return cap <= 1024 ? 256 : (acc_bytes >= 8 && cap > 2048 ? 1024 : 512); }
 
 // Dense rows over narrow B: whole rows of up to dense_bitmap_cap entries in
 // one 1024-thread workgroup per CU (bitmap, ranks, the accumulators with
@@ -332,6 +346,18 @@ inline void launch_num_hash_one(const Rows& rows, const NumCtx& c, int bin, hipS
       if (kw.ok()) {
         klaunch(kw, dim3(grid_for(n, kWaveBS / kWave, c.cus * kw.occ * 4)), dim3(kWaveBS), st, rows, c.plan.bins,
                 (int)bin, c.C, c.err);
+        return;
+      }
+    }
+  }
+  if constexpr (LGS >= kMergeRowLgMin) {
+    if (!words && c.merge_rows) {
+      constexpr int CAP = 1 << (LGS - 1);
+      constexpr int MBS = merge_row_bs(CAP, (int)sizeof(typename Sr::Acc));
+      const KRef km = kp.template merge_row<Sr, Rows, CAP, MBS>();
+      if (km.ok()) {
+        klaunch(km, dim3(grid_for(n, 1, c.cus * km.occ * 4)), dim3(MBS), st, rows, c.plan.bins, (int)bin, c.C,
+                c.err);
         return;
       }
     }

@@ -313,6 +313,10 @@ struct KUser {
     return get(n_ranges(rows<Rows>(), LGS, BS));
   }
   // (run-time semirings take the workgroup hash kernels for every hash row)
+  template <class Sr, class Rows, int CAP, int BS>
+  KRef merge_row() const {
+    return KRef{};
+  }
   template <class Sr, class Rows, int WORDS, int CAP, int BS>
   KRef wave_bitmap() const {
     return KRef{};

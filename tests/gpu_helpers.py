@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
+import synth
 from helpers import (BOOL, F32, F64, I64, MINPLUS, assert_close_gated, assert_exact, assert_same_pattern,
                      rel_error_stats)
 
@@ -63,3 +64,34 @@ def check_product(h, sr: int, A, B, acc: int = 0, rows=None, what: str = ""):
         rp, cl, vl = rows_of(C, rows)
         ref = oracle.get().spgemm(sr, A, B, rows=np.asarray(rows, np.int64))
     return compare(sr, rp, cl, vl, ref, what), C
+
+
+def hcat(mats):
+    """Column concatenation [M_1 .. M_n] of equal-height CSRs."""
+    n = mats[0].nrows
+    rows = []
+    off = 0
+    for M in mats:
+        rows.append((M, off))
+        off += M.ncols
+    rowptr = np.zeros(n + 1, np.int64)
+    cols, vals = [], []
+    for r in range(n):
+        for M, o in rows:
+            s, e = M.rowptr[r], M.rowptr[r + 1]
+            cols.append(np.asarray(M.col[s:e], np.int64) + o)
+            vals.append(np.asarray(M.val[s:e]))
+        rowptr[r + 1] = rowptr[r] + sum(M.rowptr[r + 1] - M.rowptr[r] for M, _ in rows)
+    return synth.CSR(n, off, rowptr, np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+
+
+def vcat(mats):
+    """Row concatenation of equal-width CSRs."""
+    rowptr = [np.zeros(1, np.int64)]
+    base = 0
+    for M in mats:
+        rowptr.append(np.asarray(M.rowptr[1:], np.int64) + base)
+        base += int(M.rowptr[-1])
+    return synth.CSR(sum(M.nrows for M in mats), mats[0].ncols, np.concatenate(rowptr),
+                     np.concatenate([np.asarray(M.col) for M in mats]),
+                     np.concatenate([np.asarray(M.val) for M in mats]))

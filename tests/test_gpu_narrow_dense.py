@@ -16,7 +16,7 @@ import pytest
 import oracle
 import synth
 from helpers import ALL, with_vals
-from gpu_helpers import check_product, compare, to_dev
+from gpu_helpers import check_product, compare, hcat, to_dev, vcat
 
 pytestmark = pytest.mark.gpu
 
@@ -82,8 +82,8 @@ def test_batch_products_and_merge(h, sr):
     plan = h.batch_plan(sg.semiring(sr), [to_dev(a) for a in As], [to_dev(b) for b in Bs], [0, 4])
     try:
         # the block identity: sum_q A_q B_q = [A_1 .. A_4] [B_1; ..; B_4]
-        Acat = synth.CSR(64, 4 * 4096, *_hcat(As), )
-        Bcat = _vcat(Bs)
+        Acat = hcat(As)
+        Bcat = vcat(Bs)
         ref_m = oracle.get().spgemm(sr, Acat, Bcat)
         for rep in range(2):
             plan.execute()
@@ -95,37 +95,6 @@ def test_batch_products_and_merge(h, sr):
         assert m.min() < 12544 and m.max() > 44288, (m.min(), m.max())
     finally:
         plan.destroy()
-
-
-def _hcat(mats):
-    """rowptr, col, val of the column concatenation of equal-height CSRs."""
-    n = mats[0].nrows
-    rows = []
-    off = 0
-    for M in mats:
-        rows.append((M, off))
-        off += M.ncols
-    rowptr = np.zeros(n + 1, np.int64)
-    cols, vals = [], []
-    for r in range(n):
-        for M, o in rows:
-            s, e = M.rowptr[r], M.rowptr[r + 1]
-            cols.append(np.asarray(M.col[s:e], np.int64) + o)
-            vals.append(np.asarray(M.val[s:e]))
-        rowptr[r + 1] = rowptr[r] + sum(M.rowptr[r + 1] - M.rowptr[r] for M, _ in rows)
-    return rowptr, np.concatenate(cols).astype(np.int32), np.concatenate(vals)
-
-
-def _vcat(mats):
-    """Row concatenation of equal-width CSRs."""
-    rowptr = [np.zeros(1, np.int64)]
-    base = 0
-    for M in mats:
-        rowptr.append(np.asarray(M.rowptr[1:], np.int64) + base)
-        base += int(M.rowptr[-1])
-    return synth.CSR(sum(M.nrows for M in mats), mats[0].ncols, np.concatenate(rowptr),
-                     np.concatenate([np.asarray(M.col) for M in mats]),
-                     np.concatenate([np.asarray(M.val) for M in mats]))
 
 
 @pytest.mark.parametrize("sr", ALL)
