@@ -905,6 +905,16 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
   });
 }
 
+// Products plus entries of a heavy task's tile that take the staged path:
+// at most 8192, and no more than the accumulator's LDS holds next to the
+// tile's bitmap and word ranks (a product or an entry takes its
+// accumulator and a 16-bit column).
+template <class Acc>
+constexpr int stage_max() {
+  constexpr int fit = (kTile * (int)sizeof(Acc) - kTileWords * 6 - 8) / ((int)sizeof(Acc) + 2);
+  return fit < 8192 ? fit : 8192;
+}
+
 // Heavy tasks (a slab holding more entries than a light task's value
 // array): the row's sources are loaded once (A value, column, slab segment
 // start), then each non-empty tile of the slab is folded in one pass into a
@@ -939,6 +949,9 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
   if (bcache)
     for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
   block_sync();
+  // accumulator slots [0, dirty) were used by a staged tile and hold no
+  // identity; the next tile that folds into the dense accumulator resets them
+  int32_t dirty = 0;
   for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, [&](int64_t g) {
     const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
     const int ts0 = tk.t0, ts1 = tk.t1;
@@ -1047,12 +1060,82 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
             *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(w_val[x]);
           }
           block_sync();
-          for (int x = threadIdx.x; x < kWinSlots; x += BS) s_acc[x] = Sr::ident();
-          block_sync();
+          dirty = dirty > kWinSlots ? dirty : kWinSlots;
           continue;
+        }
+        if (total + mt <= stage_max<Acc>()) {
+          // a sparse tile whose products fit LDS next to its entries: the
+          // products are staged in LDS (16-bit column, value) while the
+          // tile's column bitmap is set, the bitmap's word ranks give each
+          // product its entry, and the entries are copied out in order --
+          // no sweep of all kTile slots.  The LDS is the accumulator's.
+          char* base = reinterpret_cast<char*>(s_acc);
+          uint32_t* g_bits = reinterpret_cast<uint32_t*>(base);
+          uint16_t* g_rank = reinterpret_cast<uint16_t*>(base + kTileWords * 4);
+          Acc* g_val = reinterpret_cast<Acc*>(base + kTileWords * 6);
+          uint16_t* g_col = reinterpret_cast<uint16_t*>(g_val + mt);
+          const int pv0 = (kTileWords * 6 + mt * (int)(sizeof(Acc) + 2) + 7) & ~7;
+          Acc* g_pv = reinterpret_cast<Acc*>(base + pv0);
+          uint16_t* g_pc = reinterpret_cast<uint16_t*>(g_pv + total);
+          static_assert(BS == kTileWords, "one bitmap word per thread");
+          g_bits[threadIdx.x] = 0u;
+          for (int x = threadIdx.x; x < mt; x += BS) g_val[x] = Sr::ident();
+          block_sync();
+          constexpr int64_t kBlock = (int64_t)kWave * kSlabU;
+          for (int64_t qb = (int64_t)wv * kBlock; qb < total; qb += (int64_t)NW * kBlock) {
+            ColVal<Acc> pp[kSlabU];
+            bool ok[kSlabU];
+            slab_round<BS, kSlabU, V, kNarrow>(L, nl, total, qb, b.pcv, f, pp, ok);
+#pragma unroll
+            for (int u = 0; u < kSlabU; ++u)
+              if (ok[u]) {
+                const int q = (int)qb + u * kWave + lane_id();
+                g_pc[q] = (uint16_t)pp[u].c;
+                g_pv[q] = pp[u].v;
+                atomicOr(&g_bits[pp[u].c >> 5], 1u << (pp[u].c & 31));
+              }
+          }
+          block_sync();
+          const uint32_t wb = g_bits[threadIdx.x];
+          int32_t tot;
+          const int32_t ex = block_excl_scan<NW, int32_t>(__popc(wb), s_wave32, &tot);
+          g_rank[threadIdx.x] = (uint16_t)ex;
+          if (threadIdx.x == 0 && tot != mt) atomicOr(err, 1);
+          block_sync();
+          for (int q = threadIdx.x; q < (int)total; q += BS) {
+            const int c = g_pc[q];
+            const int w = c >> 5;
+            const int32_t r = (int32_t)g_rank[w] + __popc(g_bits[w] & ((1u << (c & 31)) - 1u));
+            if (r < mt) {
+              Sr::lds_acc(&g_val[r], g_pv[q]);
+              g_col[r] = (uint16_t)c;
+            }
+          }
+          block_sync();
+          const int64_t o0 = uniform64(tk.out + rel);
+          char* colb = reinterpret_cast<char*>(C.col + o0);
+          char* valb = reinterpret_cast<char*>((V*)C.val + o0);
+          for (uint32_t x = threadIdx.x; x < (uint32_t)mt; x += BS) {
+            *reinterpret_cast<int32_t*>(colb + x * (uint32_t)sizeof(int32_t)) = cw0 + (int32_t)g_col[x];
+            *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(g_val[x]);
+          }
+          block_sync();
+          const int32_t used = (pv0 + (int)total * (int)(sizeof(Acc) + 2) + (int)sizeof(Acc) - 1) / (int)sizeof(Acc);
+          dirty = dirty > used ? dirty : used;
+          continue;
+        }
+        if (dirty) {
+          for (int x = threadIdx.x; x < dirty; x += BS) s_acc[x] = Sr::ident();
+          dirty = 0;
+          block_sync();
         }
         slab_iterate<BS, kSlabU, V, false, kNarrow>(L, nl, total, b.pcv, f, ap);
       } else {
+        if (dirty) {
+          for (int x = threadIdx.x; x < dirty; x += BS) s_acc[x] = Sr::ident();
+          dirty = 0;
+          block_sync();
+        }
         slab_products<BS, kSlabU, V, true, false, kNarrow>(b, a_col, a_val, tk.a0, tk.nsrc, tk.s, t - ts0, t + 1 - ts0,
                                                            false, false, 0, 0, L, b.pcv, f, ap);
       }

@@ -142,6 +142,40 @@ def test_heavy_tile_span_counts(h, sr):
     assert st["tile_tasks"] == 1 and st["tile_entries"] == c0.size, st
 
 
+@pytest.mark.parametrize("sr", ALL)
+def test_heavy_tiles_staged_and_dense(h, sr):
+    """Heavy tasks whose tiles alternate between the dense accumulator and
+    the LDS-staged path (products and entries of a sparse tile staged in the
+    accumulator's LDS), so a dense tile follows a staged one inside a task
+    and across tasks.  One slab of 2^17 columns, light cap 64: per row, tile
+    0 folds 4 x 3000 products (dense), tile 1 2 x 1500 (staged), tile 2 300
+    (one round in registers), tile 3 4 x 5000 (dense), tile 4 2000
+    (staged), tile 5 nothing, tile 6 1100 (staged, with span counts), tile 7
+    4 x 8000 (dense)."""
+    _reset_knobs(h)
+    rng = np.random.default_rng(260)
+
+    def cols(t, k):
+        return (t << 14) + np.sort(rng.choice(1 << 14, size=k, replace=False))
+
+    t0, t1, t2, t3, t4, t6, t7 = cols(0, 3000), cols(1, 1500), cols(2, 300), cols(3, 5000), cols(4, 2000), \
+        cols(6, 1100), cols(7, 8000)
+    rows = [np.concatenate([t0, t1, t2, t3, t7]), np.concatenate([t0, t1, t3, t7]),
+            np.concatenate([t0, t3, t4, t7]), np.concatenate([t0, t3, t6, t7])]
+    B = synth.CSR(4, 1 << 17, np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64),
+                  np.concatenate(rows).astype(np.int32), np.zeros(sum(r.size for r in rows)))
+    A = synth.CSR(3, 4, np.array([0, 4, 8, 10], np.int64), np.array([0, 1, 2, 3, 0, 1, 2, 3, 1, 3], np.int32),
+                  np.zeros(10))
+    h.set_option("slab_log", 17)
+    h.set_option("light_cap", 64)
+    try:
+        check_product(h, sr, with_vals(A, sr, 261), with_vals(B, sr, 262), what="staged and dense tiles")
+        st = h.stats()
+        assert st["tile_tasks"] == 3 and st["slab_tasks"] == 0, st
+    finally:
+        _reset_knobs(h)
+
+
 @pytest.mark.parametrize("sr", [MINPLUS, I64])
 @pytest.mark.parametrize("g32", [0, 1])
 def test_symbolic_gather_widths(h, sr, g32):
