@@ -1027,12 +1027,72 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int
 // B row times its A value, or one part's row in a merge) is already sorted
 // by column, so the row is the merge of its non-empty segments.  The
 // products are staged in LDS in segment order (the runs); each round merges
-// neighbouring runs pairwise, every element finding its place in the merged
-// run by a binary search of its partner run (ties: the left run first, so
-// equal columns stay in source order); after ceil(log2(runs)) rounds equal
-// columns are adjacent and the first element of each group folds the group
-// with (+).  The groups' results are staged at their ranks in the free
+// neighbouring runs pairwise along their merge paths (ties: the left run
+// first, so equal columns stay in source order); after ceil(log2(runs))
+// rounds equal columns are adjacent and the first element of each group
+// folds the group with (+).  The groups' results are staged at their ranks in the free
 // buffer and copied out coalesced.
+// One round of the pairwise merge: the runs of this round are the round-0
+// runs taken 2^sh at a time, run q covering [roff[q<<sh], roff[(q+1)<<sh])
+// (clipped to the last), and runs 2p and 2p+1 are merged into the output
+// range they cover together.  Thread t produces outputs [t*EPT, (t+1)*EPT):
+// its pair by a binary search over the pairs, how many of the pair's first
+// outputs come from the left run by a binary search along the pair's merge
+// path (the left run's element goes first on equal columns, so the merge is
+// stable), then EPT steps of a sequential merge, moving to the next pair
+// where one ends.  Columns are below 2^31 - 1, which stands for "run empty".
+template <class Acc, int EPT>
+SG_DEV void merge_path_round(const int32_t* kin, const Acc* vin, int32_t* kout, Acc* vout, const uint16_t* roff,
+                             int runs, int total, int sh) {
+  const int x0 = (int)threadIdx.x * EPT;
+  if (x0 >= total) return;
+  const int sh1 = sh + 1;
+  const int np = (runs + (1 << sh1) - 1) >> sh1;
+  auto bound = [&](int r) { return (int)roff[r < runs ? r : runs]; };
+  int p = 0;
+  for (int step = 1 << (31 - __clz(np)); step > 0; step >>= 1) {
+    const int t = p + step;
+    if (t < np && (int)roff[t << sh1] <= x0) p = t;
+  }
+  int s = roff[p << sh1], mid = bound((2 * p + 1) << sh), e = bound((2 * p + 2) << sh);
+  const int d = x0 - s;
+  int lo = d > e - mid ? d - (e - mid) : 0, hi = d < mid - s ? d : mid - s;
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (kin[s + m] <= kin[mid + d - 1 - m]) lo = m + 1;
+    else hi = m;
+  }
+  int a = s + lo, b = mid + (d - lo);
+  constexpr int32_t kNone = 0x7FFFFFFF;
+  int32_t ka = a < mid ? kin[a] : kNone, kb = b < e ? kin[b] : kNone;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int x = x0 + k;
+    if (x >= total) break;
+    if (x == e) {  // the next pair starts here
+      ++p;
+      s = e;
+      mid = bound((2 * p + 1) << sh);
+      e = bound((2 * p + 2) << sh);
+      a = s;
+      b = mid;
+      ka = a < mid ? kin[a] : kNone;
+      kb = b < e ? kin[b] : kNone;
+    }
+    if (a < mid && (b >= e || ka <= kb)) {
+      kout[x] = ka;
+      vout[x] = vin[a];
+      ++a;
+      ka = a < mid ? kin[a] : kNone;
+    } else {
+      kout[x] = kb;
+      vout[x] = vin[b];
+      ++b;
+      kb = b < e ? kin[b] : kNone;
+    }
+  }
+}
+
 template <class Sr, class Src, int CAP, int BS>
 struct MergeRowSmem {
   static constexpr int kChunkBytes = BS * (16 + (int)sizeof(typename Src::Item));
@@ -1111,62 +1171,8 @@ __global__ __launch_bounds__(BS) void k_num_merge_row(Rows rows, Bins bins, int 
     Acc* vin = sm.val;
     int32_t* kout = reinterpret_cast<int32_t*>(sm.other);
     Acc* vout = reinterpret_cast<Acc*>(sm.other + CAP * 4);
-    // searches step down from the largest power of two below the bound, for
-    // all EPT elements of a thread together (their LDS reads overlap)
-    const int top_len = total > 0 ? 1 << (31 - __clz(total)) : 0;
     for (int sh = 0; (1 << sh) < runs; ++sh) {
-      const int rr = (runs + (1 << sh) - 1) >> sh;  // runs of this round
-      const int top_run = 1 << (31 - __clz(rr));
-      int q[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) q[k] = 0;
-      // the run of each element: the last q with roff[q << sh] <= x
-      for (int step = top_run; step > 0; step >>= 1) {
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-          const int x = (int)threadIdx.x + k * BS;
-          const int t = q[k] + step;
-          if (x < total && t < rr && (int)sm.roff[t << sh] <= x) q[k] = t;
-        }
-      }
-      int32_t c[EPT];
-      int ps[EPT], len[EPT], cnt[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        const int x = (int)threadIdx.x + k * BS;
-        const int p = q[k] ^ 1;
-        c[k] = x < total ? kin[x] : 0;
-        ps[k] = 0;
-        len[k] = 0;
-        cnt[k] = 0;
-        if (x < total && p < rr) {
-          const int pe = (p + 1) << sh;
-          ps[k] = sm.roff[p << sh];
-          len[k] = (int)sm.roff[pe < runs ? pe : runs] - ps[k];
-        }
-      }
-      // the partner run's elements before the element: below its column
-      // for a left run, up to and including it for a right run
-      for (int step = top_len; step > 0; step >>= 1) {
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-          const int t = cnt[k] + step;
-          if (t <= len[k]) {
-            const int32_t y = kin[ps[k] + t - 1];
-            if ((q[k] & 1) ? y <= c[k] : y < c[k]) cnt[k] = t;
-          }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        const int x = (int)threadIdx.x + k * BS;
-        if (x < total) {
-          // a right run's merged run starts at its partner's first element
-          const int dest = (q[k] & 1) ? ps[k] + (x - (int)sm.roff[q[k] << sh]) + cnt[k] : x + cnt[k];
-          kout[dest] = c[k];
-          vout[dest] = vin[x];
-        }
-      }
+      merge_path_round<Acc, EPT>(kin, vin, kout, vout, sm.roff, runs, total, sh);
       block_sync();
       int32_t* kt = kin;
       kin = kout;
