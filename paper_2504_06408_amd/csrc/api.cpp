@@ -368,6 +368,7 @@ sg_status run_symbolic(sg_handle* h, RowSource& r, const sg_csr* B, int64_t* C_r
     }
     mk.mark(kPhSymBounds, 0);
   }
+  r.merge_rows = h->merge_rows;
   launch_symbolic(r, plan, C_rowptr + 1, off2, h->cus, mk, st);
   mk.mark(kPhSymScan, 1);
   launch_fill_i64(C_rowptr, 1, 0, st);

@@ -384,6 +384,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
     const sg_csr& A = P->A[0];
     const sg_csr& B = P->B[0];
     S.src.mode = kModeProduct;
+    S.src.merge_rows = h->merge_rows;
     S.src.a_rowptr = A.rowptr;
     S.src.a_col = A.col;
     S.src.a_val = A.val;
@@ -398,6 +399,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
     S.b = B;
   } else {
     S.src.mode = kModeBatchProducts;
+    S.src.merge_rows = h->merge_rows;
     S.src.probs = P->d_probs;
     S.src.rbase = P->d_rbase_p;
     S.src.coarse = P->d_coarse_p;
@@ -427,6 +429,7 @@ sg_status plan_build(sg_plan* P, size_t pool_bytes) {
     SG_HIP(h, hipMemcpyAsync(P->d_parts, parts.data(), sizeof(PartDesc) * parts.size(), hipMemcpyHostToDevice, st));
     SG_HIP(h, hipMemcpyAsync(P->d_groups, groups.data(), sizeof(GroupDesc) * (size_t)ng, hipMemcpyHostToDevice, st));
     M.src.mode = kModeBatchMerges;
+    M.src.merge_rows = h->merge_rows;
     M.src.groups = P->d_groups;
     M.src.rbase = P->d_rbase_m;
     M.src.coarse = P->d_coarse_m;

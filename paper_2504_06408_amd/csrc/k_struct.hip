@@ -152,10 +152,18 @@ bool sym_bitmap_rows(const Rows& rows, const BinPlan& plan, int bin, int64_t* cn
 }
 
 template <class Rows, int LGS, int BS>
-void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st) {
+void sym_hash_one(const Rows& rows, const BinPlan& plan, int bin, int64_t* cnt_out, int cus, hipStream_t st,
+                  bool merge) {
   const int n = plan.count[bin];
   if (n == 0) return;
   if (sym_bitmap_rows<Rows, LGS>(rows, plan, bin, cnt_out, cus, st)) return;
+  if (merge) {
+    // wider B: the rows' sorted segments merged in LDS, columns only
+    auto km = k_sym_merge_row<Rows, 1 << (LGS - 1), 512>;
+    static int occm = occupancy(km, 512);
+    hipLaunchKernelGGL(km, dim3(grid_for(n, 1, cus * occm * 4)), dim3(512), 0, st, rows, plan.bins, bin, cnt_out);
+    return;
+  }
   auto k = k_sym_hash<Rows, LGS, BS>;
   static int occ = occupancy(k, BS);
   hipLaunchKernelGGL(k, dim3(grid_for(n, 1, cus * occ * 4)), dim3(BS), 0, st, rows, plan.bins, bin, cnt_out);
@@ -214,7 +222,7 @@ void sym_dense_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int
 
 template <class Rows>
 void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int32_t* off2, int cus,
-                   const Marks& marks, hipStream_t st, bool dense) {
+                   const Marks& marks, hipStream_t st, bool dense, bool merge) {
   marks.mark(kPhSymSmall, 1);
   if (plan.count[kBinSmall]) {
     auto k = k_sym_small<Rows>;
@@ -230,8 +238,8 @@ void symbolic_rows(const Rows& rows, const BinPlan& plan, int64_t* cnt_out, int3
   sym_hash_wave_one<Rows, 9>(rows, plan, kBinHash0 + 2, cnt_out, cus, st);
   sym_hash_wave_one<Rows, 10>(rows, plan, kBinHash0 + 3, cnt_out, cus, st);
   sym_hash_wave_one<Rows, 11>(rows, plan, kBinHash0 + 4, cnt_out, cus, st);
-  sym_hash_one<Rows, 12, 512>(rows, plan, kBinHash0 + 5, cnt_out, cus, st);
-  sym_hash_one<Rows, 13, 512>(rows, plan, kBinHash0 + 6, cnt_out, cus, st);
+  sym_hash_one<Rows, 12, 512>(rows, plan, kBinHash0 + 5, cnt_out, cus, st, merge);
+  sym_hash_one<Rows, 13, 512>(rows, plan, kBinHash0 + 6, cnt_out, cus, st, merge);
   marks.mark(kPhSymHash, 0);
   if (!dense) return;
   marks.mark(kPhSymDense, 1);
@@ -367,7 +375,9 @@ void launch_symbolic(const RowSource& r, const BinPlan& plan, int64_t* cnt_out, 
                      const Marks& marks, hipStream_t st) {
   const bool slab = use_slab(r);
   with_rows<uint8_t, false>(r,
-                            [&](const auto& rows) { symbolic_rows(rows, plan, cnt_out, off2, cus, marks, st, !slab); });
+                            [&](const auto& rows) {
+                              symbolic_rows(rows, plan, cnt_out, off2, cus, marks, st, !slab, r.merge_rows != 0);
+                            });
   if (slab) {
     marks.mark(kPhSymDense, 1);
     sym_slab(r, plan, cnt_out, off2, cus, marks, st);

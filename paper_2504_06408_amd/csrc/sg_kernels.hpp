@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_row(Rows rows, Bins bins, int
 // path (the left run's element goes first on equal columns, so the merge is
 // stable), then EPT steps of a sequential merge, moving to the next pair
 // where one ends.  Columns are below 2^31 - 1, which stands for "run empty".
-template <class Acc, int EPT>
+template <class Acc, int EPT, bool kVals = true>
 SG_DEV void merge_path_round(const int32_t* kin, const Acc* vin, int32_t* kout, Acc* vout, const uint16_t* roff,
                              int runs, int total, int sh) {
   const int x0 = (int)threadIdx.x * EPT;
@@ -1081,12 +1081,12 @@ SG_DEV void merge_path_round(const int32_t* kin, const Acc* vin, int32_t* kout, 
     }
     if (a < mid && (b >= e || ka <= kb)) {
       kout[x] = ka;
-      vout[x] = vin[a];
+      if constexpr (kVals) vout[x] = vin[a];
       ++a;
       ka = a < mid ? kin[a] : kNone;
     } else {
       kout[x] = kb;
-      vout[x] = vin[b];
+      if constexpr (kVals) vout[x] = vin[b];
       ++b;
       kb = b < e ? kin[b] : kNone;
     }
@@ -1211,6 +1211,83 @@ __global__ __launch_bounds__(BS) void k_num_merge_row(Rows rows, Bins bins, int 
       ((V*)C.val)[o + x] = Sr::out(vout[x]);
     }
     block_sync();
+  }
+}
+
+// Symbolic count of rows of at most CAP products by the same merge of the
+// row's sorted segments, columns only: the count is the number of groups of
+// equal columns after the last round.
+template <class Rows, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_sym_merge_row(Rows rows, Bins bins, int bin, int64_t* cnt_out) {
+  using Src = typename Rows::Src;
+  using Item = typename Src::Item;
+  constexpr int NW = BS / kWave;
+  constexpr int EPT = (CAP + BS - 1) / BS;
+  constexpr int U = row_unroll(CAP, BS);
+  constexpr int kChunkBytes = BS * (16 + (int)sizeof(Item));
+  static_assert(CAP <= 65535, "16-bit run offsets");
+  __shared__ int32_t s_key[CAP];
+  __shared__ __align__(16) char s_other[CAP * 4 > kChunkBytes ? CAP * 4 : kChunkBytes];
+  __shared__ uint16_t s_roff[CAP + 1];
+  __shared__ int64_t s_wave[NW];
+  int64_t* const c_start = reinterpret_cast<int64_t*>(s_other);
+  int64_t* const c_off = c_start + BS;
+  Item* const c_item = reinterpret_cast<Item*>(c_off + BS);
+  const int n = bins.count[bin];
+  const int32_t* L = bins.list + bins.start[bin];
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    const int64_t i = L[r];
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    auto fetch = [&](const Item& it, int64_t idx) { return s.col(it, idx); };
+    int32_t total = 0, runs = 0;
+    bool over = false;
+    for (int64_t c0 = 0; c0 < nsrc; c0 += BS) {
+      int nc;
+      const int64_t ct = product_chunk<BS>(s, nsrc, c0, c_item, c_start, c_off, s_wave, &nc);
+      if (ct > (int64_t)(CAP - total)) {
+        over = true;
+        break;
+      }
+      for (int k = threadIdx.x; k < nc; k += BS) s_roff[runs + k] = (uint16_t)(total + c_off[k]);
+      for (int64_t qb = (int64_t)wave_id() * kWave * U; qb < ct; qb += (int64_t)NW * kWave * U) {
+        int32_t p[U];
+        bool ok[U];
+        product_block<BS, U, Src>(c_item, c_start, c_off, nc, ct, qb, fetch, p, ok);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (ok[u]) s_key[total + (int)(qb + u * kWave + lane_id())] = p[u];
+      }
+      total += (int32_t)ct;
+      runs += nc;
+      block_sync();
+    }
+    if (over) {  // more products than the bin allows: count nothing, so the
+                 // numeric pass flags the row
+      if (threadIdx.x == 0) cnt_out[i] = 0;
+      continue;
+    }
+    if (threadIdx.x == 0) s_roff[runs] = (uint16_t)total;
+    block_sync();
+    int32_t* kin = s_key;
+    int32_t* kout = reinterpret_cast<int32_t*>(s_other);
+    for (int sh = 0; (1 << sh) < runs; ++sh) {
+      merge_path_round<int32_t, EPT, false>(kin, nullptr, kout, nullptr, s_roff, runs, total, sh);
+      block_sync();
+      int32_t* kt = kin;
+      kin = kout;
+      kout = kt;
+    }
+    int32_t heads = 0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int x = (int)threadIdx.x * EPT + k;
+      if (x < total && (x == 0 || kin[x] != kin[x - 1])) ++heads;
+    }
+    const int64_t tot = block_sum<NW, int64_t>((int64_t)heads, s_wave);
+    if (threadIdx.x == 0) cnt_out[i] = tot;
   }
 }
 

@@ -18,6 +18,7 @@ enum RowMode { kModeProduct = 0, kModeMerge = 1, kModeBatchProducts = 2, kModeBa
 // Everything a symbolic or numeric launch needs to describe its rows.
 struct RowSource {
   int mode;
+  int merge_rows = 1;  // symbolic hash bins of 2^12 slots and up over wide B: the merge kernel
   // single product
   const int64_t* a_rowptr;
   const int32_t* a_col;
