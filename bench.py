@@ -640,7 +640,7 @@ def main():
                     help="also run a plain 512 MiB copy kernel (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the product is the per-GPU local multiply and this build has no "
+        print("bench.py measures one GPU: the product is the per-GPU local multiply and this library has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
