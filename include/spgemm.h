@@ -160,7 +160,7 @@ sg_status sg_handle_destroy(sg_handle* h);
  * column tile through a per-B-row tile offset table), "gather32" (0/1,
  * default 1: the slab path's gathers use 32-bit offsets when its partition of
  * B spans less than 4 GiB; 0: always 64-bit), "merge_rows" (0/1, default 1:
- * a row of 257 to 4096 products over B of more than 65,536 columns is
+ * a row of 65 to 4096 products over B of more than 65,536 columns is
  * merged in LDS from its sources' sorted segments; 0: LDS hash table and
  * sort), "slab_log" (0 = chosen from
  * B's width, or 14..17: the slab path cuts B's columns into slabs of

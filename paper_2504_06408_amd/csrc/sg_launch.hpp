@@ -296,13 +296,15 @@ constexpr int kWaveLgMax = 9;
 constexpr int kRowBitmapBS = 256;
 constexpr int kRowBitmapLgMin = 10;
 
-// Hash rows over wider B, of up to 2^(kMergeRowLgMin-1) products and more,
-// are merged from their sorted segments (k_num_merge_row): the (key, value)
+// Hash rows over wider B of more than 2^(kMergeRowLgMin-2) products are
+// merged from their sorted segments (k_num_merge_row): the (key, value)
 // buffers take 2*CAP*(4+acc) bytes of LDS, so rows of 4096 products with
 // 4-byte accumulators run two 512-thread workgroups per CU, and with 8-byte
-// ones one of 1024 threads.
-constexpr int kMergeRowLgMin = 10;
-constexpr int merge_row_bs(int cap, int acc_bytes) { return cap <= 1024 ? 256 : (acc_bytes >= 8 && cap > 2048 ? 1024 : 512); }
+// ones one of 1024 threads; rows of up to 256 products take one wavefront.
+constexpr int kMergeRowLgMin = 8;
+constexpr int merge_row_bs(int cap, int acc_bytes) {
+  return cap <= 256 ? 64 : (cap <= 1024 ? 256 : (acc_bytes >= 8 && cap > 2048 ? 1024 : 512));
+}
 
 // Dense rows over narrow B: whole rows of up to dense_bitmap_cap entries in
 // one 1024-thread workgroup per CU (bitmap, ranks, the accumulators with

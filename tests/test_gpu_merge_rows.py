@@ -1,5 +1,5 @@
 """GPU parity of hash-bin rows over wide B (more than 65,536 columns): a row
-of 257 to 4096 products is merged in LDS from its sources' sorted segments
+of 65 to 4096 products is merged in LDS from its sources' sorted segments
 (option merge_rows, default on) instead of going through an LDS hash table
 and a sort.  Each case runs with the option on and off against the CPU
 oracle, on rows of one to several hundred sources whose columns repeat
@@ -56,8 +56,9 @@ def _wide_rows(lengths, rng):
 def _operands(seed):
     """B: 6000 rows of 1 .. 4000 entries (log-uniform) plus 400 rows {7} and
     400 rows {7, 8, 9}.  A: rows of 1 .. 300 sources, each row aiming at 300
-    .. 4000 products from B rows of about equal length, and rows of 300 or
-    400 sources on the one- and three-column B rows."""
+    .. 4000 products (70 .. 256 for 60 rows of at most 12 sources) from B
+    rows of about equal length, and rows of 300 or 400 sources on the one-
+    and three-column B rows."""
     rng = np.random.default_rng(seed)
     lens = np.exp(rng.uniform(0, np.log(4000), 6000)).astype(np.int64) + 1
     brows = _wide_rows(lens, rng)
@@ -69,9 +70,11 @@ def _operands(seed):
     blen = np.array([len(r) for r in brows])
     order = np.argsort(blen[:one0])
     arows = []
-    for r in range(360):
+    for r in range(420):
         s = [1, 1, 2, 2, 3, 4, 6, 8, 12, 20, 40, 100, 300][r % 13]
-        target = int(rng.integers(300, 4000))
+        # rows of 65 .. 256 products (one wavefront per row) after 360 larger ones
+        target = int(rng.integers(300, 4000)) if r < 360 else int(rng.integers(70, 256))
+        s = s if r < 360 else min(s, 12)
         per = max(1, target // s)
         # B rows of length in (per/2, per]
         lo = np.searchsorted(blen[order], per // 2 + 1)
@@ -104,8 +107,8 @@ def test_operands_reach_the_merge_bins():
     A, B = _ops(900)
     p = _products(A, B)
     assert B.ncols > 65536
-    assert ((p > 256) & (p <= 4096)).mean() > 0.8, np.percentile(p, [5, 50, 95])
-    assert (p > 2048).sum() > 50 and ((p > 256) & (p <= 512)).sum() > 10
+    assert ((p > 64) & (p <= 4096)).mean() > 0.8, np.percentile(p, [5, 50, 95])
+    assert (p > 2048).sum() > 50 and ((p > 256) & (p <= 512)).sum() > 10 and ((p > 64) & (p <= 256)).sum() > 30
 
 
 @pytest.mark.parametrize("sr", ALL)
