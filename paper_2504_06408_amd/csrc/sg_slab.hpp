@@ -22,9 +22,11 @@
 //             the row's sources are read once, then each tile is folded into
 //             a dense LDS accumulator of kTile slots and compacted in column
 //             order by a sweep whose wavefronts take their output offsets
-//             from the symbolic pass's span counts; a sparse tile (no span
-//             counts) whose products fit a round uses the light scheme in
-//             LDS borrowed from the accumulator instead.
+//             from the symbolic pass's span counts; a sparse tile uses the
+//             light scheme in LDS borrowed from the accumulator instead
+//             (products in registers when they fit a round and the tile has
+//             no span counts, else staged in that LDS when products plus
+//             entries fit it).
 #pragma once
 
 #include "sg_kernels.hpp"
@@ -918,8 +920,10 @@ constexpr int stage_max() {
 // Heavy tasks (a slab holding more entries than a light task's value
 // array): the row's sources are loaded once (A value, column, slab segment
 // start), then each non-empty tile of the slab is folded in one pass into a
-// dense 16384-slot LDS accumulator and compacted in column order; per tile a
-// source only re-reads its two tile offsets.  Slots are reset to the
+// dense 16384-slot LDS accumulator and compacted in column order, or, when
+// sparse, ranked on a bitmap of its columns (see the staged path below);
+// when the row's sources fit one chunk (one per thread), their tile offsets
+// stay in registers for every tile.  Slots are reset to the
 // identity as they are compacted; for semirings whose identity no product
 // reaches (kValueMarks) occupancy is read off the accumulator, otherwise an
 // occupancy bitmap is kept.  8-byte accumulators fill 128 KB of LDS: one
