@@ -160,9 +160,10 @@ sg_status sg_handle_destroy(sg_handle* h);
  * column tile through a per-B-row tile offset table), "gather32" (0/1,
  * default 1: the slab path's gathers use 32-bit offsets when its partition of
  * B spans less than 4 GiB; 0: always 64-bit), "merge_rows" (0/1, default 1:
- * a row of 65 to 4096 products over B of more than 65,536 columns is
- * merged in LDS from its sources' sorted segments; 0: LDS hash table and
- * sort), "slab_log" (0 = chosen from
+ * in the numeric pass a row of 65 to 4096 products over B of more than
+ * 65,536 columns, in the symbolic pass such a row of 1025 to 4096, is
+ * merged in LDS from its sources' sorted segments; 0: LDS hash tables, and
+ * a sort in the numeric pass), "slab_log" (0 = chosen from
  * B's width, or 14..17: the slab path cuts B's columns into slabs of
  * 2^slab_log columns), "light_cap" (0 = the light kernel's LDS capacity, or
  * 1..32768: a dense row's slab with at most this many output entries is a
