@@ -1539,6 +1539,28 @@ SG_DEV void for_each_queued(int32_t* ctr, int list, int64_t ntask, int64_t* s_sl
   }
 }
 
+// for_each_queued for tasks that start from a record: the records of a
+// grab's tasks are read together right after the grab (thread j reads the
+// j-th with fetch(g)) and wait in s_rec (kGrab entries of LDS), so only a
+// grab's first task waits for its record.  task(rec) as above.
+template <class Rec, class Fetch, class F>
+SG_DEV void for_each_queued_rec(int32_t* ctr, int list, int64_t ntask, int64_t* s_slot, Rec* s_rec, Fetch&& fetch,
+                                F&& task) {
+  const int q = (int)(blockIdx.x % kQueues);
+  int32_t* qc = queue_ctr(ctr, list, q);
+  const int64_t nq = ntask > q ? (ntask - q + kQueues - 1) / kQueues : 0;
+  while (true) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(qc, kGrab);
+    block_sync();
+    const int64_t j0 = *s_slot;
+    if (j0 >= nq) break;  // uniform; s_slot is not written again
+    const int64_t j1 = (j0 + kGrab) < nq ? (j0 + kGrab) : nq;
+    if ((int64_t)threadIdx.x < j1 - j0) s_rec[threadIdx.x] = fetch(q + (j0 + (int64_t)threadIdx.x) * kQueues);
+    block_sync();
+    for (int64_t j = j0; j < j1; ++j) task(s_rec[j - j0]);
+  }
+}
+
 // Numeric dense-row work is cut into tasks from the symbolic pass's per-tile
 // counts.  With column slabs of G tiles (G > 0: single products), a slab
 // holding at most slab_cap entries becomes one slab task (bitmap + rank

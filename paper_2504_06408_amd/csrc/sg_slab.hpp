@@ -684,10 +684,21 @@ __global__ __launch_bounds__(BS, 7) void k_sym_slab(SlabB<uint8_t> b, const Dens
   const int nwords = G * kTileWords;
   for (int x = threadIdx.x; x < nwords; x += BS) s_bm[x] = 0u;
   const int64_t nd = dense_rows(bins);
-  for_each_queued(ctr, kListSymSlab, nd * S, &L.slot, [&](int64_t g) {
-    const int32_t s = (int32_t)(g / nd);
-    const int64_t h = g - (int64_t)s * nd;
-    const DenseRow d = dr[h];
+  struct SymTask {
+    DenseRow d;
+    int64_t h;
+    int32_t s;
+  };
+  __shared__ SymTask s_rec[kGrab];
+  auto fetch = [&](int64_t g) {
+    const int32_t sl = (int32_t)(g / nd);
+    const int64_t hh = g - (int64_t)sl * nd;
+    return SymTask{dr[hh], hh, sl};
+  };
+  for_each_queued_rec(ctr, kListSymSlab, nd * S, &L.slot, s_rec, fetch, [&](const SymTask& task) {
+    const int32_t s = task.s;
+    const int64_t h = task.h;
+    const DenseRow d = task.d;
     const int ts0 = s * G;
     // the partition holds each entry's bitmap code (slab_bit_code): only
     // each tile's count of distinct columns is needed, and with a tile's
@@ -780,8 +791,10 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
     for (int x = threadIdx.x; x <= T; x += BS) L.boff[x] = boff[x];
   block_sync();
   const int wv = wave_id();
-  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &L.slot, [&](int64_t g) {
-    const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
+  __shared__ SlabTask s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g); };
+  for_each_queued_rec(ctr, kListSlab, (int64_t)ctr[kListSlab], &L.slot, s_rec, fetch, [&](const SlabTask& task) {
+    const SlabTask tk = task;
     const int ts0 = tk.s * G, ts1 = ts0 + G < T ? ts0 + G : T;
     const bool whole = tk.t0 == ts0 && tk.t1 == ts1;
     const int32_t tr0 = tk.t0 - ts0, tr1 = tk.t1 - ts0;
@@ -956,8 +969,10 @@ __global__ __launch_bounds__(BS, sizeof(typename Sr::Acc) > 4 ? 2 : 4) void k_nu
   // accumulator slots [0, dirty) were used by a staged tile and hold no
   // identity; the next tile that folds into the dense accumulator resets them
   int32_t dirty = 0;
-  for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, [&](int64_t g) {
-    const SlabTask tk = bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g);
+  __shared__ SlabTask s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_slab_task<V, BS>(tasks, boff, L, bcache, T, nd, g); };
+  for_each_queued_rec(ctr, kListTile, (int64_t)ctr[kListTile], &L.slot, s_rec, fetch, [&](const SlabTask& task) {
+    const SlabTask tk = task;
     const int ts0 = tk.t0, ts1 = tk.t1;
     block_sync();
     if ((int)threadIdx.x <= ts1 - ts0) {

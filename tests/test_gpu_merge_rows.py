@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import ALL, with_vals
+from helpers import ALL, F32, with_vals
 from gpu_helpers import check_product, compare, hcat, to_dev, vcat
 
 pytestmark = pytest.mark.gpu
@@ -57,7 +57,7 @@ def _operands(seed):
     """B: 6000 rows of 1 .. 4000 entries (log-uniform) plus 400 rows {7} and
     400 rows {7, 8, 9}.  A: rows of 1 .. 300 sources, each row aiming at 300
     .. 4000 products (70 .. 256 for 60 rows of at most 12 sources) from B
-    rows of about equal length, and rows of 300 or 400 sources on the one-
+    rows of about equal length, and rows of 100 to 400 sources on the one-
     and three-column B rows."""
     rng = np.random.default_rng(seed)
     lens = np.exp(rng.uniform(0, np.log(4000), 6000)).astype(np.int64) + 1
@@ -85,6 +85,10 @@ def _operands(seed):
     arows.append(np.arange(one0, one0 + 400))
     arows.append(np.arange(three0, three0 + 300))
     arows.append(np.concatenate([np.arange(one0, one0 + 200), np.arange(three0, three0 + 200)]))
+    # rows of one-wavefront bins whose sources fill several chunks of 64
+    arows.append(np.arange(one0, one0 + 200))
+    arows.append(np.arange(one0, one0 + 100))
+    arows.append(np.concatenate([np.arange(one0, one0 + 70), np.arange(three0, three0 + 40)]))
     A = _csr(arows, B.nrows)
     return A, B
 
@@ -123,6 +127,24 @@ def test_single_product(h, sr, merge):
         check_product(h, sr, A, B, what=f"merge_rows={merge}")
     finally:
         _reset(h)
+
+
+@pytest.mark.parametrize("acc", ["compensated", "plain"])
+def test_fp32_accumulation_modes(h, acc):
+    """fp32 sums with every row compensated (8-byte (hi, lo) accumulators,
+    which the merge kernel folds group by group in registers) or none,
+    merge rows on and off."""
+    import paper_2504_06408_amd as sg
+    mode = sg.ACC_COMPENSATED if acc == "compensated" else sg.ACC_PLAIN
+    A, B = _ops(900)
+    A, B = with_vals(A, F32, 961), with_vals(B, F32, 962)
+    for merge in (1, 0):
+        _reset(h)
+        h.set_option("merge_rows", merge)
+        try:
+            check_product(h, F32, A, B, acc=mode, what=f"fp32 {acc}, merge_rows={merge}")
+        finally:
+            _reset(h)
 
 
 @pytest.mark.parametrize("sr", ALL)
