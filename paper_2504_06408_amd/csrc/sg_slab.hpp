@@ -304,20 +304,15 @@ struct SlabTask {
   int32_t m;       // C entries in the slab
 };
 
-// Entries of a light task's LDS value array (32 KB of accumulators).
-// Light tasks with accumulators of 4 bytes or more also keep each entry's
-// column (its low 16 bits) at its rank, so the write-out is two coalesced
-// copies instead of a walk over the bitmap; the value and column arrays
-// share 42 KB of LDS.
-template <class Sr>
-constexpr bool light_cols_lds() {
-  return sizeof(typename Sr::Acc) >= 4;
-}
+// Entries of a light task's LDS arrays: besides its accumulator a light
+// task keeps each entry's column (its low 16 bits) at its rank, so the
+// write-out is two coalesced copies instead of a walk over the bitmap; the
+// value and column arrays share 42 KB of LDS.
 constexpr int light_cap_of(int acc_bytes) { return (43008 / (acc_bytes + 2)) & ~63; }
 
 template <class Sr>
 constexpr int slab_cap() {
-  return light_cols_lds<Sr>() ? light_cap_of((int)sizeof(typename Sr::Acc)) : 32768 / (int)sizeof(typename Sr::Acc);
+  return light_cap_of((int)sizeof(typename Sr::Acc));
 }
 
 constexpr int kTaskSlabsLds = 512;  // slabs whose bucket counters a block keeps in LDS
@@ -780,8 +775,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
   __shared__ uint32_t s_bits[kSlabWordsMax];
   __shared__ uint16_t s_rank[kSlabWordsMax];
   __shared__ Acc s_val[CAP];
-  constexpr bool kCols = light_cols_lds<Sr>();
-  __shared__ uint16_t s_col[kCols ? CAP : 1];
+  __shared__ uint16_t s_col[CAP];
   __shared__ SrcLds<V, BS> L;
   __shared__ int32_t s_wt[NW];
   const int T = b.T, G = b.G;
@@ -822,7 +816,7 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
       const int32_t r = (int32_t)s_rank[w] + __popc(s_bits[w] & ((1u << (p.c & 31)) - 1u));
       if (r < m) {
         Sr::lds_acc(&s_val[r], p.v);
-        if constexpr (kCols) s_col[r] = (uint16_t)p.c;
+        s_col[r] = (uint16_t)p.c;
       }
     };
     ColVal<Acc> pp[kSlabU];
@@ -883,40 +877,20 @@ __global__ __launch_bounds__(BS, 4) void k_num_slab(SlabB<V> b, const int32_t* a
                                                                    whole, one, nl, total, L, b.pcv, f2, a2);
     }
     block_sync();
-    // write-out: column ids from the bitmap walk (no LDS reads inside the
-    // loop), values in rank order (coalesced); the bitmap is cleared for the
-    // next task
-    // (lanes store at 32-bit offsets from the task's uniform output base)
+    // write-out: columns and values in rank order, both coalesced (lanes
+    // store at 32-bit offsets from the task's uniform output base); window
+    // columns are below 2^17, and bit 16 is set exactly for the ranks from
+    // that of word 2048 on; the bitmap is cleared for the next task
     const int64_t o0 = uniform64(tk.out);
     char* colb = reinterpret_cast<char*>(C.col + o0);
     char* valb = reinterpret_cast<char*>((V*)C.val + o0);
-    if constexpr (kCols) {
-      // window columns are below 2^17; bit 16 is set exactly for the ranks
-      // from that of word 2048 on
-      const uint32_t split = nwords > 2048 ? (uint32_t)s_rank[2048] : (uint32_t)m;
-      for (uint32_t x = threadIdx.x; x < (uint32_t)m; x += BS) {
-        const int32_t c = (int32_t)s_col[x] | (x >= split ? 65536 : 0);
-        *reinterpret_cast<int32_t*>(colb + x * (uint32_t)sizeof(int32_t)) = (int32_t)cw0 + c;
-        *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(s_val[x]);
-      }
-      for (int it = 0; it < wpw; it += kWave) s_bits[wv * wpw + it + lane_id()] = 0u;
-      return;
-    }
-    for (int it = 0; it < wpw; it += kWave) {
-      const int w = wv * wpw + it + lane_id();
-      uint32_t bits = s_bits[w];
-      uint32_t r = s_rank[w];
-      const int32_t cbase = (int32_t)(cw0 + w * 32);
-      while (bits) {
-        const int bt = __ffs((int)bits) - 1;
-        bits &= bits - 1u;
-        if (r < (uint32_t)m) *reinterpret_cast<int32_t*>(colb + r * (uint32_t)sizeof(int32_t)) = cbase + bt;
-        ++r;
-      }
-      s_bits[w] = 0u;
-    }
-    for (uint32_t x = threadIdx.x; x < (uint32_t)m; x += BS)
+    const uint32_t split = nwords > 2048 ? (uint32_t)s_rank[2048] : (uint32_t)m;
+    for (uint32_t x = threadIdx.x; x < (uint32_t)m; x += BS) {
+      const int32_t c = (int32_t)s_col[x] | (x >= split ? 65536 : 0);
+      *reinterpret_cast<int32_t*>(colb + x * (uint32_t)sizeof(int32_t)) = (int32_t)cw0 + c;
       *reinterpret_cast<V*>(valb + x * (uint32_t)sizeof(V)) = Sr::out(s_val[x]);
+    }
+    for (int it = 0; it < wpw; it += kWave) s_bits[wv * wpw + it + lane_id()] = 0u;
   });
 }
 

@@ -55,11 +55,12 @@ bool find_int(const std::string& s, const char* key, long long* out) {
 }
 
 // LDS capacity of a light task for the accumulator the semiring's dense rows
-// use (32 KB of accumulators; compensated fp32 sums keep a float pair).
+// use (accumulators and 16-bit columns in 42 KB; compensated fp32 sums keep a
+// float pair).
 int32_t full_light_cap(const sg_semiring* sr) {
   int acc = sr->value_bytes;
   if (sr->id == SG_PLUS_TIMES_F32 && sr->acc_flags != SG_ACC_PLAIN) acc = 8;
-  return acc >= 4 ? sg::light_cap_of(acc) : 32768 / acc;
+  return sg::light_cap_of(acc);
 }
 
 struct Knobs {
