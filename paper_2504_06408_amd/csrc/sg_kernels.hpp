@@ -1596,8 +1596,8 @@ constexpr int kRangeSpanMax = 4;  // column tiles of a range task
 template <int BS>
 __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* off2, int32_t Tmax, int32_t G,
                                                     int32_t slab_cap, int32_t tile_min, int32_t range_cap,
-                                                    Task* tiles, Task* ranges, Task* slabs, int32_t* book,
-                                                    int32_t* ctr) {
+                                                    int32_t run_tiles, Task* tiles, Task* ranges, Task* slabs,
+                                                    int32_t* book, int32_t* ctr) {
   __shared__ unsigned long long s_ent[3];
   __shared__ int32_t s_cnt[3 * kTaskAggBuckets], s_base[3 * kTaskAggBuckets];
   if (threadIdx.x < 3) s_ent[threadIdx.x] = 0ull;
@@ -1622,7 +1622,7 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
         if (count) ent[kListSlab] += (unsigned long long)ms;
         continue;
       }
-      int32_t r0 = -1, rlast = -1, racc = 0;
+      int32_t r0 = -1, rlast = -1, racc = 0, run0 = -1;
       for (int t = ta; t < tb; ++t) {
         const int32_t c = o2[t + 1] - o2[t];
         if (c == 0) continue;
@@ -1635,6 +1635,16 @@ __global__ __launch_bounds__(BS) void k_dense_tasks(Bins bins, const int32_t* of
           continue;
         }
         if (count) ent[kListRange] += (unsigned long long)c;
+        if (run_tiles > 0) {
+          // one run task per group of run_tiles tiles holding range tiles;
+          // its kernel forms the ranges by the rules below
+          const int32_t g0 = ta + (t - ta) / run_tiles * run_tiles;
+          if (g0 != run0) {
+            run0 = g0;
+            emit(kListRange, g0, Task{h, g0, (g0 + run_tiles) < tb ? (g0 + run_tiles) : tb});
+          }
+          continue;
+        }
         if (r0 >= 0 && (racc + c > range_cap || t + 1 - r0 > kRangeSpanMax)) {
           emit(kListRange, r0, Task{h, r0, rlast + 1});
           r0 = -1;
@@ -1776,6 +1786,95 @@ __global__ __launch_bounds__(BS) void k_num_ranges_bitmap(Rows rows, Bins bins, 
     rows.get(i, s, li);
     bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 8)>(sm, s, li, tk.t0, tk.t1, C.rowptr[i] + lo,
                                                                          hi - lo, C, err);
+  });
+}
+
+// Range runs of products: one task per (dense row, group of up to
+// kRunTiles tiles) holding range tiles.  The row's sources (one per thread
+// when they fit a chunk) load their B row, A value and B row start once;
+// the task then forms the group's ranges by the task builder's rules and
+// folds each on the column bitmap, where a source only reads its two tile
+// offsets.  A per-range task reloaded every source.
+constexpr int kRunTiles = 8;
+
+template <class V>
+struct RunSrc : SpgemmSrc<V, true> {
+  using Base = SpgemmSrc<V, true>;
+  bool cached = false;  // the calling thread holds its source below
+  int32_t kk = 0;
+  V av{};
+  int64_t b0 = 0;
+  SG_DEV void load(int64_t j, typename Base::Item& it, int64_t& start, int64_t& len) const {
+    if (!cached) {
+      Base::load(j, it, start, len);
+      return;
+    }
+    it.a = av;
+    const int32_t* r = this->rp2 + (int64_t)kk * (this->T + 1);
+    const int32_t s0 = r[this->t0];
+    start = b0 + s0;
+    len = r[this->t1] - s0;
+  }
+};
+
+template <class Sr, class Rows, int WORDS, int CAP, int BS>
+__global__ __launch_bounds__(BS) void k_num_range_runs(Rows rows, Bins bins, OutC C, const int32_t* off2,
+                                                       const Task* tasks, const int32_t* book, int32_t* ctr,
+                                                       int32_t tile_min, int32_t* err) {
+  using V = typename Sr::V;
+  using Src = RunSrc<V>;
+  static_assert(32 * WORDS >= kRangeSpanMax * kTile, "a range fits the bitmap");
+  __shared__ BitmapRowSmem<Sr, Src, WORDS, CAP, BS> sm;
+  __shared__ int64_t s_slot;
+  for (int x = threadIdx.x; x < WORDS; x += BS) sm.bits[x] = 0u;
+  block_sync();
+  const int32_t* L = bins.list + bins.start[kBinDense0];
+  const int32_t Tmax = rows.Tmax;
+  const int32_t nd = dense_rows(bins);
+  for_each_queued(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, [&](int64_t g) {
+    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g);
+    const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
+    const int64_t i = L[tk.h];
+    const int64_t obase = C.rowptr[i];
+    Src s{};
+    int64_t li;
+    rows.get(i, s, li);
+    const int64_t nsrc = s.bind(li, 0, s.T);
+    if (nsrc <= BS) {
+      s.cached = true;
+      if ((int64_t)threadIdx.x < nsrc) {
+        const int64_t e = s.a0 + threadIdx.x;
+        s.kk = s.a_col[e];
+        s.av = s.a_val[e];
+        s.b0 = s.b_rowptr[s.kk];
+      }
+    }
+    auto fold = [&](int32_t r0, int32_t r1) {
+      const int32_t lo = o2[r0], hi = o2[r1];
+      if (threadIdx.x == 0 && (hi - lo > CAP || r1 - r0 > kRangeSpanMax)) atomicOr(err, 1);
+      bitmap_row_fold<Sr, Src, WORDS, CAP, BS, (row_unroll(CAP, BS) <= 8)>(sm, s, li, r0, r1, obase + lo, hi - lo,
+                                                                           C, err);
+    };
+    int32_t r0 = -1, rlast = -1, racc = 0;
+    for (int t = tk.t0; t < tk.t1; ++t) {
+      const int32_t c = o2[t + 1] - o2[t];
+      if (c == 0) continue;
+      if (c >= tile_min) {  // a dense-tile task
+        if (r0 >= 0) fold(r0, rlast + 1);
+        r0 = -1;
+        racc = 0;
+        continue;
+      }
+      if (r0 >= 0 && (racc + c > CAP || t + 1 - r0 > kRangeSpanMax)) {
+        fold(r0, rlast + 1);
+        r0 = -1;
+        racc = 0;
+      }
+      if (r0 < 0) r0 = t;
+      rlast = t;
+      racc += c;
+    }
+    if (r0 >= 0) fold(r0, rlast + 1);
   });
 }
 

@@ -282,6 +282,11 @@ struct KLib {
     static const KRef k = kref_static((const void*)k_num_ranges_bitmap<Sr, Rows, WORDS, CAP, BS>, BS);
     return k;
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef range_runs() const {
+    static const KRef k = kref_static((const void*)k_num_range_runs<Sr, Rows, WORDS, CAP, BS>, BS);
+    return k;
+  }
 };
 
 // Hash rows whose columns all lie below 32 * kWaveWords (products whose B has
@@ -447,9 +452,13 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st, 
                      (int64_t)kCtrInts, (int32_t)0);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(3 * (int64_t)Tmax, 256, 1024)), dim3(256), 0, st, book,
                      3 * (int64_t)Tmax, (int32_t)0);
+  // products: range tasks as runs over groups of kRunTiles tiles
+  KRef krr{};
+  if constexpr (!Rows::Src::kParts) krr = kp.template range_runs<Sr, Rows, kWaveWords, kRangeCap, kRangeBitmapBS>();
+  const int32_t run_tiles = krr.ok() ? kRunTiles : 0;
   hipLaunchKernelGGL(k_dense_tasks<256>, dim3(grid_for(c.plan.ndense(), 256, c.cus * 8)), dim3(256), 0, st,
-                     c.plan.bins, c.off2, Tmax, bm ? Tmax : 0, bm ? dcap : 0, c.tile_min, kRangeCap, c.tasks,
-                     c.tasks + c.task_cap, c.tasks + 2 * c.task_cap, book, c.task_ctr);
+                     c.plan.bins, c.off2, Tmax, bm ? Tmax : 0, bm ? dcap : 0, c.tile_min, kRangeCap, run_tiles,
+                     c.tasks, c.tasks + c.task_cap, c.tasks + 2 * c.task_cap, book, c.task_ctr);
   hipLaunchKernelGGL(k_task_offsets<1024>, dim3(1), dim3(1024), 0, st, book, Tmax, c.task_ctr);
   if (bm) {
     const int grid = c.cus * kb.occ > kQueues ? c.cus * kb.occ : kQueues;
@@ -469,7 +478,11 @@ inline void launch_num_dense(const Rows& rows, const NumCtx& c, hipStream_t st, 
   // time semirings) a hash table and a sort
   const KRef kr = kp.template ranges_bitmap<Sr, Rows, kWaveWords, kRangeCap, kRangeBitmapBS>();
   c.marks.mark(kPhNumDenseRanges, 1);
-  if (kr.ok()) {
+  if (run_tiles) {
+    const int grid2 = c.cus * krr.occ > kQueues ? c.cus * krr.occ : kQueues;
+    klaunch(krr, dim3(grid2), dim3(kRangeBitmapBS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2,
+            (const Task*)(c.tasks + c.task_cap), (const int32_t*)book, c.task_ctr, c.tile_min, c.err);
+  } else if (kr.ok()) {
     const int grid2 = c.cus * kr.occ > kQueues ? c.cus * kr.occ : kQueues;
     klaunch(kr, dim3(grid2), dim3(kRangeBitmapBS), st, rows, c.plan.bins, c.C, (const int32_t*)c.off2,
             (const Task*)(c.tasks + c.task_cap), (const int32_t*)book, c.task_ctr, c.err);

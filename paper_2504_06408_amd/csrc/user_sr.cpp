@@ -333,6 +333,10 @@ struct KUser {
   KRef ranges_bitmap() const {
     return KRef{};
   }
+  template <class Sr, class Rows, int WORDS, int CAP, int BS>
+  KRef range_runs() const {
+    return KRef{};
+  }
 };
 
 }  // namespace
