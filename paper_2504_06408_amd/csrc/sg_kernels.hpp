@@ -1746,8 +1746,10 @@ __global__ __launch_bounds__(BS) void k_num_bitmap_dense(Rows rows, Bins bins, O
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t nd = dense_rows(bins);
-  for_each_queued(ctr, kListSlab, (int64_t)ctr[kListSlab], &s_slot, [&](int64_t g) {
-    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListSlab), Tmax, nd, (int32_t)g);
+  __shared__ Task s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_task(tasks, book_off(book, Tmax, kListSlab), Tmax, nd, (int32_t)g); };
+  for_each_queued_rec(ctr, kListSlab, (int64_t)ctr[kListSlab], &s_slot, s_rec, fetch, [&](const Task& task) {
+    const Task tk = task;
     const int64_t i = L[tk.h];
     const int64_t o = C.rowptr[i];
     const int32_t m = (int32_t)(C.rowptr[i + 1] - o);
@@ -1775,8 +1777,10 @@ __global__ __launch_bounds__(BS) void k_num_ranges_bitmap(Rows rows, Bins bins, 
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t nd = dense_rows(bins);
-  for_each_queued(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, [&](int64_t g) {
-    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g);
+  __shared__ Task s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g); };
+  for_each_queued_rec(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, s_rec, fetch, [&](const Task& task) {
+    const Task tk = task;
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];
@@ -1831,8 +1835,10 @@ __global__ __launch_bounds__(BS) void k_num_range_runs(Rows rows, Bins bins, Out
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t nd = dense_rows(bins);
-  for_each_queued(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, [&](int64_t g) {
-    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g);
+  __shared__ Task s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g); };
+  for_each_queued_rec(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, s_rec, fetch, [&](const Task& task) {
+    const Task tk = task;
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int64_t i = L[tk.h];
     const int64_t obase = C.rowptr[i];
@@ -1903,8 +1909,10 @@ __global__ __launch_bounds__(BS) void k_num_tiles(Rows rows, Bins bins, OutC C, 
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t nd = dense_rows(bins);
-  for_each_queued(ctr, kListTile, (int64_t)ctr[kListTile], &s_slot, [&](int64_t g) {
-    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListTile), Tmax, nd, (int32_t)g);
+  __shared__ Task s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_task(tasks, book_off(book, Tmax, kListTile), Tmax, nd, (int32_t)g); };
+  for_each_queued_rec(ctr, kListTile, (int64_t)ctr[kListTile], &s_slot, s_rec, fetch, [&](const Task& task) {
+    const Task tk = task;
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];
@@ -1990,8 +1998,10 @@ __global__ __launch_bounds__(BS) void k_num_ranges(Rows rows, Bins bins, OutC C,
   const int32_t* L = bins.list + bins.start[kBinDense0];
   const int32_t Tmax = rows.Tmax;
   const int32_t nd = dense_rows(bins);
-  for_each_queued(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, [&](int64_t g) {
-    const Task tk = bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g);
+  __shared__ Task s_rec[kGrab];
+  auto fetch = [&](int64_t g) { return bucket_task(tasks, book_off(book, Tmax, kListRange), Tmax, nd, (int32_t)g); };
+  for_each_queued_rec(ctr, kListRange, (int64_t)ctr[kListRange], &s_slot, s_rec, fetch, [&](const Task& task) {
+    const Task tk = task;
     const int32_t* o2 = off2 + (int64_t)tk.h * (Tmax + 1);
     const int32_t lo = o2[tk.t0], hi = o2[tk.t1];
     const int64_t i = L[tk.h];
